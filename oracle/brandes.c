@@ -1,0 +1,560 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, sequential Brandes betweenness for undirected, unweighted graphs in
+ * CSR form, written to be checked by eye against the method the paper uses
+ * (Brandes 2001, cited in the section "Heuristics and Approximation
+ * Algorithms" and in Table 1, "betweenness", O(nm) time).  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it; the GPU library neither links nor calls it.
+ *
+ * Forms:
+ *   - exact: sum of dependencies over all sources (Table 1, "betweenness");
+ *   - source set: sum over a given source list times a scale factor
+ *     (Table 1, "ap. betweenness", sampling shortest-path trees);
+ *   - pair sampling (Riondato and Kornaropoulos, cited for the epsilon
+ *     guarantee in "Heuristics and Approximation Algorithms").
+ *
+ * Conventions (the paper is silent on these; each is a stated reading):
+ *   - scores sum over ordered (s, t) pairs, endpoints excluded;
+ *   - sigma is uint64 and any addition that wraps is reported as
+ *     OR_E_SIGMA_OVERFLOW (no saturation);
+ *   - unreachable vertices have d = -1, sigma = 0 and add nothing;
+ *   - scores are FP64.
+ *
+ * The multi-threaded timing mode splits the source list into contiguous
+ * blocks, one per thread, each with private arrays, and adds the per-thread
+ * score arrays in thread order at the end: the parallel pattern the paper
+ * describes for its own implementation (per-thread dependency arrays summed
+ * at the end).  Each source is still plain sequential Brandes.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_INVALID_ARG (-1)
+#define OR_E_INVALID_GRAPH (-2)
+#define OR_E_SIGMA_OVERFLOW (-3)
+#define OR_E_NO_MEMORY (-4)
+
+typedef struct {
+    int32_t n;
+    const int32_t *rowptr;
+    const int32_t *colidx;
+} graph_t;
+
+/* Structural checks: rowptr[0] = 0, rowptr non-decreasing, rowptr[n] = m,
+ * every column index in [0, n). */
+int or_validate(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx) {
+    if (n < 0 || m < 0) return OR_E_INVALID_ARG;
+    if (n == 0) return OR_OK;
+    if (!rowptr || (m > 0 && !colidx)) return OR_E_INVALID_ARG;
+    if (rowptr[0] != 0) return OR_E_INVALID_GRAPH;
+    for (int32_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return OR_E_INVALID_GRAPH;
+    if ((int64_t)rowptr[n] != m) return OR_E_INVALID_GRAPH;
+    for (int64_t e = 0; e < m; ++e)
+        if (colidx[e] < 0 || colidx[e] >= n) return OR_E_INVALID_GRAPH;
+    return OR_OK;
+}
+
+/* Simple-graph checks on top of or_validate: adjacency strictly ascending
+ * (no duplicates), no self-loops, and every arc u->v has its reverse v->u. */
+int or_validate_strict(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    for (int32_t u = 0; u < n; ++u) {
+        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+            int32_t v = colidx[e];
+            if (v == u) return OR_E_INVALID_GRAPH;
+            if (e > rowptr[u] && colidx[e - 1] >= v) return OR_E_INVALID_GRAPH;
+            int found = 0;
+            for (int32_t f = rowptr[v]; f < rowptr[v + 1]; ++f)
+                if (colidx[f] == u) { found = 1; break; }
+            if (!found) return OR_E_INVALID_GRAPH;
+        }
+    }
+    return OR_OK;
+}
+
+/*
+ * Forward phase of Brandes' algorithm from source s: breadth-first search
+ * that records the distance d and the number of shortest paths sigma of
+ * every vertex, and the visit order S (non-decreasing distance).
+ * Returns OR_OK or OR_E_SIGMA_OVERFLOW.  d must be -1 and sigma 0 on entry.
+ */
+static int forward(const graph_t *g, int32_t s, int32_t *d, uint64_t *sigma,
+                   int32_t *S, int32_t *nS, int32_t *queue) {
+    int32_t head = 0, tail = 0, ns = 0;
+    int status = OR_OK;
+    d[s] = 0;
+    sigma[s] = 1;
+    queue[tail++] = s;
+    while (head < tail) {
+        int32_t v = queue[head++];
+        S[ns++] = v;
+        for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+            int32_t w = g->colidx[e];
+            if (d[w] < 0) {
+                d[w] = d[v] + 1;
+                queue[tail++] = w;
+            }
+            if (d[w] == d[v] + 1) {
+                uint64_t sum;
+                if (__builtin_add_overflow(sigma[w], sigma[v], &sum)) status = OR_E_SIGMA_OVERFLOW;
+                sigma[w] = sum;
+            }
+        }
+    }
+    *nS = ns;
+    return status;
+}
+
+typedef struct {
+    int32_t *d, *S, *queue;
+    uint64_t *sigma;
+    double *delta;
+} work_t;
+
+static int work_alloc(work_t *w, int32_t n) {
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    w->d = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->S = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->queue = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->sigma = (uint64_t *)malloc(nn * sizeof(uint64_t));
+    w->delta = (double *)malloc(nn * sizeof(double));
+    if (!w->d || !w->S || !w->queue || !w->sigma || !w->delta) return OR_E_NO_MEMORY;
+    for (int32_t i = 0; i < n; ++i) { w->d[i] = -1; w->sigma[i] = 0; w->delta[i] = 0.0; }
+    return OR_OK;
+}
+
+static void work_free(work_t *w) {
+    free(w->d); free(w->S); free(w->queue); free(w->sigma); free(w->delta);
+}
+
+/* Restore d, sigma, delta of the vertices reached from the last source. */
+static void work_reset(work_t *w, int32_t nS) {
+    for (int32_t i = 0; i < nS; ++i) {
+        int32_t v = w->S[i];
+        w->d[v] = -1; w->sigma[v] = 0; w->delta[v] = 0.0;
+    }
+}
+
+/*
+ * One source of Brandes' algorithm: forward phase, then the dependency
+ * accumulation in reverse visit order,
+ *     delta[v] += sigma[v] / sigma[w] * (1 + delta[w])
+ * for every predecessor v of w (d[v] = d[w] - 1), and bc[w] += delta[w]
+ * for w != s.
+ */
+static int one_source(const graph_t *g, int32_t s, work_t *w, double *bc) {
+    int32_t nS = 0;
+    int status = forward(g, s, w->d, w->sigma, w->S, &nS, w->queue);
+    if (status == OR_OK) {
+        for (int32_t i = nS - 1; i >= 0; --i) {
+            int32_t x = w->S[i];
+            for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+                int32_t v = g->colidx[e];
+                if (w->d[v] == w->d[x] - 1)
+                    w->delta[v] += (double)w->sigma[v] / (double)w->sigma[x] * (1.0 + w->delta[x]);
+            }
+            if (x != s) bc[x] += w->delta[x];
+        }
+    }
+    work_reset(w, nS);
+    return status;
+}
+
+/* d (-1 = unreachable) and sigma of every vertex for one source. */
+int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   int32_t s, int32_t *d, uint64_t *sigma) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (s < 0 || s >= n || !d || !sigma) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    int32_t *S = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!S || !q) { free(S); free(q); return OR_E_NO_MEMORY; }
+    for (int32_t i = 0; i < n; ++i) { d[i] = -1; sigma[i] = 0; }
+    int32_t nS;
+    st = forward(&g, s, d, sigma, S, &nS, q);
+    free(S); free(q);
+    return st;
+}
+
+typedef struct {
+    const graph_t *g;
+    const int32_t *src;
+    int32_t lo, hi;
+    double *bc;
+    int status;
+} job_t;
+
+static void *run_job(void *arg) {
+    job_t *j = (job_t *)arg;
+    work_t w;
+    j->status = work_alloc(&w, j->g->n);
+    if (j->status == OR_OK) {
+        for (int32_t i = j->lo; i < j->hi; ++i) {
+            int st = one_source(j->g, j->src[i], &w, j->bc);
+            if (st != OR_OK) { j->status = st; break; }
+        }
+    }
+    work_free(&w);
+    return NULL;
+}
+
+/*
+ * Betweenness summed over the sources src[0..k) in the given order
+ * (duplicates count twice), then multiplied by `scale`.  nthreads <= 1 runs
+ * sequentially; otherwise sources are split into contiguous blocks with a
+ * private score array per thread, summed in thread order.
+ */
+int or_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                  const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (k < 0 || (k > 0 && !src) || (n > 0 && !bc)) return OR_E_INVALID_ARG;
+    for (int32_t i = 0; i < k; ++i)
+        if (src[i] < 0 || src[i] >= n) return OR_E_INVALID_ARG;
+    for (int32_t i = 0; i < n; ++i) bc[i] = 0.0;
+    if (n == 0 || k == 0) return OR_OK;
+    graph_t g = {n, rowptr, colidx};
+    if (nthreads <= 1) {
+        job_t j = {&g, src, 0, k, bc, OR_OK};
+        run_job(&j);
+        st = j.status;
+    } else {
+        if (nthreads > k) nthreads = k;
+        job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
+        pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+        if (!jobs || !th) { free(jobs); free(th); return OR_E_NO_MEMORY; }
+        for (int32_t t = 0; t < nthreads; ++t) {
+            jobs[t].g = &g;
+            jobs[t].src = src;
+            jobs[t].lo = (int32_t)((int64_t)k * t / nthreads);
+            jobs[t].hi = (int32_t)((int64_t)k * (t + 1) / nthreads);
+            jobs[t].bc = (double *)calloc((size_t)n, sizeof(double));
+            jobs[t].status = jobs[t].bc ? OR_OK : OR_E_NO_MEMORY;
+        }
+        for (int32_t t = 0; t < nthreads; ++t)
+            if (jobs[t].status == OR_OK) pthread_create(&th[t], NULL, run_job, &jobs[t]);
+        for (int32_t t = 0; t < nthreads; ++t)
+            if (jobs[t].bc) pthread_join(th[t], NULL);
+        st = OR_OK;
+        for (int32_t t = 0; t < nthreads; ++t) {
+            if (jobs[t].status != OR_OK && st == OR_OK) st = jobs[t].status;
+            if (jobs[t].bc) {
+                for (int32_t i = 0; i < n; ++i) bc[i] += jobs[t].bc[i];
+                free(jobs[t].bc);
+            }
+        }
+        free(jobs);
+        free(th);
+    }
+    if (st == OR_OK && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return st;
+}
+
+/* Exact betweenness: every vertex is a source, in order 0..n-1. */
+int or_bc_exact(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                double *bc, int32_t nthreads) {
+    if (n < 0) return OR_E_INVALID_ARG;
+    int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!src) return OR_E_NO_MEMORY;
+    for (int32_t i = 0; i < n; ++i) src[i] = i;
+    int st = or_bc_sources(n, m, rowptr, colidx, src, n, 1.0, bc, nthreads);
+    free(src);
+    return st;
+}
+
+/*
+ * Work done by Brandes for a source list, summed over the sources:
+ *   out[0] = reached vertices (source included),
+ *   out[1] = arcs leaving reached vertices (sum of their degrees),
+ *   out[2] = shortest-path DAG arcs (v -> w with d[w] = d[v] + 1),
+ *   out[3] = sum over sources of the deepest level.
+ */
+int or_work_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   const int32_t *src, int32_t k, int64_t *out) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    graph_t g = {n, rowptr, colidx};
+    work_t w;
+    if (work_alloc(&w, n) != OR_OK) { work_free(&w); return OR_E_NO_MEMORY; }
+    out[0] = out[1] = out[2] = out[3] = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        int32_t nS;
+        int s2 = forward(&g, src[i], w.d, w.sigma, w.S, &nS, w.queue);
+        (void)s2;
+        out[0] += nS;
+        int32_t deepest = 0;
+        for (int32_t q = 0; q < nS; ++q) {
+            int32_t v = w.S[q];
+            out[1] += rowptr[v + 1] - rowptr[v];
+            if (w.d[v] > deepest) deepest = w.d[v];
+            for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e)
+                if (w.d[colidx[e]] == w.d[v] + 1) out[2]++;
+        }
+        out[3] += deepest;
+        work_reset(&w, nS);
+    }
+    work_free(&w);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Pair sampling (Riondato and Kornaropoulos).
+ *
+ * Random numbers: the counter-based SplitMix64 construction
+ * (Steele, Lea, Flood 2014).  mix64 is the SplitMix64 output function; the
+ * k-th output of a stream seeded with x is mix64(x + k*GAMMA); a draw
+ * indexed by (seed, stream, j, t) is output t+1 of the stream seeded with
+ * output j+1 of the stream seeded with output stream+1 of the stream seeded
+ * with `seed`.  bounded(x, N) = floor(x * N / 2^64).
+ * ---------------------------------------------------------------------- */
+#define GOLDEN 0x9E3779B97F4A7C15ULL
+
+uint64_t or_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t or_draw(uint64_t seed, uint64_t stream, uint64_t j, uint64_t t) {
+    uint64_t a = or_mix64(seed + (stream + 1) * GOLDEN);
+    uint64_t b = or_mix64(a + (j + 1) * GOLDEN);
+    return or_mix64(b + (t + 1) * GOLDEN);
+}
+
+uint64_t or_bounded(uint64_t x, uint64_t N) {
+    return (uint64_t)(((unsigned __int128)x * N) >> 64);
+}
+
+/* Plain BFS distances from s (d = -1 unreachable); returns eccentricity of
+ * s within its component and the lowest-id vertex at that distance. */
+static int32_t bfs_ecc(const graph_t *g, int32_t s, int32_t *d, int32_t *queue,
+                       int32_t *far_vertex, int32_t *reached) {
+    for (int32_t i = 0; i < g->n; ++i) d[i] = -1;
+    int32_t head = 0, tail = 0;
+    d[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+        int32_t v = queue[head++];
+        for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+            int32_t w = g->colidx[e];
+            if (d[w] < 0) { d[w] = d[v] + 1; queue[tail++] = w; }
+        }
+    }
+    int32_t ecc = 0, far = s;
+    for (int32_t i = 0; i < tail; ++i) {
+        int32_t v = queue[i];
+        if (d[v] > ecc || (d[v] == ecc && v < far)) { ecc = d[v]; far = v; }
+    }
+    *far_vertex = far;
+    *reached = tail;
+    return ecc;
+}
+
+/*
+ * Upper bound on the vertex diameter (number of vertices on a longest
+ * shortest path), for the sample size of pair sampling.
+ *   x0 = vertex of maximum degree, lowest id on ties;
+ *   e1 = eccentricity of x0, a = lowest-id vertex at distance e1;
+ *   e2 = eccentricity of a (double sweep; e2 + 1 is a lower bound);
+ *   c0 = size of the component of x0; c2 = largest other component.
+ * Within x0's component every shortest path has at most 2*e1 + 1 vertices
+ * and at most c0; in any other component at most its size.  Hence
+ *   VD_ub = max(min(2*e1 + 1, c0), c2).
+ * info = {x0, e1, a, e2, vd_ub, vd_lb = e2 + 1, c0, c2}.
+ */
+int or_vd_bound(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, int32_t *info) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (n == 0) { for (int i = 0; i < 8; ++i) info[i] = 0; return OR_OK; }
+    graph_t g = {n, rowptr, colidx};
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!d || !q) { free(d); free(q); return OR_E_NO_MEMORY; }
+    int32_t x0 = 0;
+    for (int32_t v = 1; v < n; ++v)
+        if (rowptr[v + 1] - rowptr[v] > rowptr[x0 + 1] - rowptr[x0]) x0 = v;
+    int32_t a, c0, c_a;
+    int32_t e1 = bfs_ecc(&g, x0, d, q, &a, &c0);
+    int32_t far2;
+    int32_t e2 = bfs_ecc(&g, a, d, q, &far2, &c_a);
+    /* component sizes: label every component by BFS from its lowest vertex */
+    int32_t c2 = 0;
+    for (int32_t i = 0; i < n; ++i) d[i] = -1;
+    int32_t comp = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        if (d[s] >= 0) continue;
+        int32_t head = 0, tail = 0;
+        d[s] = comp;
+        q[tail++] = s;
+        int contains_x0 = (s == x0);
+        while (head < tail) {
+            int32_t v = q[head++];
+            for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+                int32_t w = colidx[e];
+                if (d[w] < 0) { d[w] = comp; q[tail++] = w; if (w == x0) contains_x0 = 1; }
+            }
+        }
+        if (!contains_x0 && tail > c2) c2 = tail;
+        ++comp;
+    }
+    int32_t ub = 2 * e1 + 1;
+    if (ub > c0) ub = c0;
+    if (c2 > ub) ub = c2;
+    info[0] = x0; info[1] = e1; info[2] = a; info[3] = e2;
+    info[4] = ub; info[5] = e2 + 1; info[6] = c0; info[7] = c2;
+    free(d); free(q);
+    return OR_OK;
+}
+
+/*
+ * Riondato-Kornaropoulos sample size with constant c = 0.5:
+ *   r = ceil( c / eps^2 * ( floor(log2(VD - 2)) + 1 + ln(1/delta) ) ),
+ * with VD - 2 taken as at least 1.  floor(log2) is computed on integers.
+ */
+int64_t or_rk_sample_size(double eps, double delta, int32_t vd) {
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0)) return -1;
+    int64_t x = (int64_t)vd - 2;
+    if (x < 1) x = 1;
+    int32_t fl = 0;
+    while ((x >> (fl + 1)) > 0) ++fl;
+    double k = (double)(fl + 1) + (-log(delta));
+    double rr = 0.5 / (eps * eps) * k;
+    return (int64_t)ceil(rr);
+}
+
+/* Pair j: u uniform in [0, n), v uniform in [0, n) minus {u}. */
+static void pair_of(uint64_t seed, int64_t j, int32_t n, int32_t *u, int32_t *v) {
+    int32_t a = (int32_t)or_bounded(or_draw(seed, 1, (uint64_t)j, 0), (uint64_t)n);
+    int32_t b = (int32_t)or_bounded(or_draw(seed, 2, (uint64_t)j, 0), (uint64_t)(n - 1));
+    if (b >= a) b += 1;
+    *u = a;
+    *v = b;
+}
+
+/*
+ * One sample: shortest-path counting BFS from u (forward phase above), then
+ * a walk from v back to u.  At vertex w (step t) draw x = bounded(draw(seed,
+ * 3, j, t), sigma[w]) and take the first predecessor p, in adjacency order,
+ * whose running sum of sigma over predecessors exceeds x: p is chosen with
+ * probability sigma[p] / sigma[w], so the path is uniform among the
+ * shortest u-v paths.  Interior vertices are written to `interior`
+ * (from v's side towards u).  Returns the number of interior vertices, -1
+ * if v is unreachable from u, or OR_E_SIGMA_OVERFLOW - 100 on overflow.
+ */
+static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u, int32_t v,
+                          work_t *w, int32_t *interior) {
+    int32_t nS;
+    int st = forward(g, u, w->d, w->sigma, w->S, &nS, w->queue);
+    int32_t len = 0;
+    if (st != OR_OK) { work_reset(w, nS); return OR_E_SIGMA_OVERFLOW - 100; }
+    if (w->d[v] < 0) { work_reset(w, nS); return -1; }
+    int32_t x = v;
+    uint64_t t = 0;
+    while (x != u) {
+        uint64_t r = or_bounded(or_draw(seed, 3, (uint64_t)j, t), w->sigma[x]);
+        uint64_t acc = 0;
+        int32_t pick = -1;
+        for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+            int32_t p = g->colidx[e];
+            if (w->d[p] == w->d[x] - 1) {
+                acc += w->sigma[p];
+                if (acc > r) { pick = p; break; }
+            }
+        }
+        if (pick != u) interior[len++] = pick;
+        x = pick;
+        ++t;
+    }
+    work_reset(w, nS);
+    return len;
+}
+
+/* The path sample j draws for an explicit pair (u, v) (for inspection). */
+int or_sample_path_uv(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                      uint64_t seed, int64_t j, int32_t u, int32_t v, int32_t *interior, int32_t *len) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (u < 0 || u >= n || v < 0 || v >= n || u == v) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    work_t w;
+    if (work_alloc(&w, n) != OR_OK) { work_free(&w); return OR_E_NO_MEMORY; }
+    int32_t l = sample_one(&g, seed, j, u, v, &w, interior);
+    work_free(&w);
+    if (l < -1) return OR_E_SIGMA_OVERFLOW;
+    *len = l;
+    return OR_OK;
+}
+
+/* The sampled pair and path of sample j (for inspection). */
+int or_sample_path(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   uint64_t seed, int64_t j, int32_t *uv, int32_t *interior, int32_t *len) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (n < 2) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    work_t w;
+    if (work_alloc(&w, n) != OR_OK) { work_free(&w); return OR_E_NO_MEMORY; }
+    pair_of(seed, j, n, &uv[0], &uv[1]);
+    int32_t l = sample_one(&g, seed, j, uv[0], uv[1], &w, interior);
+    work_free(&w);
+    if (l < -1) return OR_E_SIGMA_OVERFLOW;
+    *len = l;
+    return OR_OK;
+}
+
+/* Counts cnt[p] = number of samples j in [0, r) whose path has p inside. */
+int or_pair_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   int64_t r, uint64_t seed, uint32_t *counts) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    for (int32_t i = 0; i < n; ++i) counts[i] = 0;
+    if (n < 2 || r <= 0) return OR_OK;
+    graph_t g = {n, rowptr, colidx};
+    work_t w;
+    int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (work_alloc(&w, n) != OR_OK || !interior) { work_free(&w); free(interior); return OR_E_NO_MEMORY; }
+    st = OR_OK;
+    for (int64_t j = 0; j < r; ++j) {
+        int32_t u, v;
+        pair_of(seed, j, n, &u, &v);
+        int32_t l = sample_one(&g, seed, j, u, v, &w, interior);
+        if (l < -1) { st = OR_E_SIGMA_OVERFLOW; break; }
+        for (int32_t i = 0; i < l; ++i) counts[interior[i]]++;
+    }
+    work_free(&w);
+    free(interior);
+    return st;
+}
+
+/*
+ * Full pair-sampling estimate: VD bound, sample size r, counts, and
+ * bc[v] = counts[v] / r * n (n - 1) (ordered-pair scale).
+ */
+int or_pair_sample(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   double eps, double delta, uint64_t seed, uint32_t *counts, double *bc,
+                   int64_t *r_out, int32_t *vd_out) {
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0)) return OR_E_INVALID_ARG;
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    int32_t info[8];
+    st = or_vd_bound(n, m, rowptr, colidx, info);
+    if (st != OR_OK) return st;
+    int64_t r = n >= 2 ? or_rk_sample_size(eps, delta, info[4]) : 0;
+    *r_out = r;
+    *vd_out = info[4];
+    st = or_pair_counts(n, m, rowptr, colidx, r, seed, counts);
+    if (st != OR_OK) return st;
+    double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
+    for (int32_t i = 0; i < n; ++i) bc[i] = (double)counts[i] * scale;
+    return OR_OK;
+}

@@ -1,0 +1,65 @@
+"""Exact betweenness by enumerating every simple path -- TEST INFRASTRUCTURE ONLY.
+
+For graphs of at most a dozen vertices.  For each ordered pair (s, t),
+s != t, a depth-first search lists all simple s-t paths; the shortest ones
+give d(s, t) and sigma(s, t), and each interior vertex v of a shortest path
+gets 1 / sigma(s, t).  This is the definition of betweenness the paper
+relies on (shortest paths through a node, section "Heuristics and
+Approximation Algorithms"), evaluated in exact rationals with no shortcut
+that Brandes' algorithm takes.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+
+def _adjacency(rowptr, colidx):
+    n = len(rowptr) - 1
+    return [[int(colidx[e]) for e in range(int(rowptr[v]), int(rowptr[v + 1]))] for v in range(n)]
+
+
+def all_pairs_paths(rowptr, colidx):
+    """dict (s, t) -> list of shortest simple s-t paths (vertex tuples)."""
+    adj = _adjacency(rowptr, colidx)
+    n = len(adj)
+    out = {}
+    for s in range(n):
+        paths_to = {t: [] for t in range(n)}
+        stack = [(s, (s,), {s})]
+        while stack:
+            v, p, seen = stack.pop()
+            if v != s:
+                paths_to[v].append(p)
+            for w in adj[v]:
+                if w not in seen:
+                    stack.append((w, p + (w,), seen | {w}))
+        for t in range(n):
+            if t == s or not paths_to[t]:
+                continue
+            best = min(len(p) for p in paths_to[t])
+            out[(s, t)] = [p for p in paths_to[t] if len(p) == best]
+    return out
+
+
+def brute_force(rowptr, colidx):
+    """(d, sigma, bc): d[s][t] (-1 unreachable, 0 on the diagonal),
+    sigma[s][t] (1 on the diagonal), bc[v] as exact Fractions over ordered pairs."""
+    n = len(rowptr) - 1
+    paths = all_pairs_paths(rowptr, colidx)
+    d = [[-1] * n for _ in range(n)]
+    sigma = [[0] * n for _ in range(n)]
+    bc = [Fraction(0)] * n
+    for s in range(n):
+        d[s][s] = 0
+        sigma[s][s] = 1
+    for (s, t), ps in paths.items():
+        d[s][t] = len(ps[0]) - 1
+        sigma[s][t] = len(ps)
+        through = [0] * n
+        for p in ps:
+            for v in p[1:-1]:
+                through[v] += 1
+        for v in range(n):
+            if through[v]:
+                bc[v] += Fraction(through[v], len(ps))
+    return d, sigma, bc
