@@ -1,0 +1,182 @@
+"""Benchmark: source-sampled Brandes betweenness on one MI355X.
+
+Workload (one step = one pass of the whole hot path over one batch):
+R-MAT scale 20, edge factor 16, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05),
+seed 2, symmetrised / deduplicated / self-loops removed (2^20 vertices,
+about 31.4M arcs); 4096 distinct uniform sources (seed 2); scores scaled by
+n / 4096.  A step is one nk_bc_sources call: CSR validation, the persistent
+Brandes kernel (forward path counting + FP64 dependency sweep) and scaling.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  GTEPS = sources x undirected edges / time / 1e9.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL = "k_brandes"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ["nk_device.h", "nk_kernels.h", "nk_kernels.hip"]:
+        with open(os.path.join(ROOT, "paper_1403_3005_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per launch of the main kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", text)
+    m_bytes = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0):
+    """The oracle (plain Brandes, the paper's per-thread-array parallel
+    pattern) on a bounded prefix of the same source list."""
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    probe = 16
+    t0 = time.perf_counter()
+    oracle.bc_sources(g.rowptr, g.colidx, src[:probe], 1.0, nthreads=1)
+    per_source = max((time.perf_counter() - t0) / probe, 1e-4)
+    k = int(max(threads, min(len(src), int(target_s * threads / per_source) // threads * threads)))
+    t0 = time.perf_counter()
+    oracle.bc_sources(g.rowptr, g.colidx, src[:k], 1.0, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": k * n_undirected / dt / 1e9,
+        "unit": "GTEPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {k} of the {len(src)} sources, same graph, {dt:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
+              "source across GPUs with one score all-reduce, which this build does not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1403_3005_amd as nk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
+    g, src = gg.workload_rmat20(2)
+    n, m = g.n, g.m
+    m_u = m // 2
+    k = len(src)
+    scale = n / k
+    rp = torch.from_numpy(g.rowptr).to(dev)
+    ci = torch.from_numpy(g.colidx).to(dev)
+    sv = torch.from_numpy(src).to(dev)
+    bc = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        nk.nk_bc_sources(rp, ci, sv, scale, bc=bc, stream=stream)
+        print(f"bench: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    kernel_us = []
+    stats = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        nk.nk_bc_sources(rp, ci, sv, scale, bc=bc, stream=stream)
+        stats = nk.nk_last_stats()
+        kernel_us.append(stats["kernel_us"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"bench: {args.steps} timed steps done", file=sys.stderr, flush=True)
+
+    sec = (t1 - t0) / args.steps
+    value = k * m_u / sec / 1e9
+    kern_s = float(np.mean(kernel_us)) * 1e-6
+    # algorithmic bytes per launch: per source 68 per reached vertex, 16 per
+    # arc of a reached vertex, 24 per shortest-path DAG arc
+    alg_bytes = 68 * stats["reached"] + 16 * stats["arcs_reached"] + 24 * stats["dag_arcs"]
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = counter_traffic("rmat20_sources4096")
+    out = {
+        "metric": "GTEPS for batched Brandes betweenness on 1 MI355X",
+        "value": round(value, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "rmat20_sources4096",
+            "graph": "R-MAT scale 20, edge factor 16, (0.57,0.19,0.19,0.05), seed 2",
+            "n": n,
+            "arcs": m,
+            "sources": k,
+            "scale": scale,
+            "arc_gteps": round(2 * value, 3),
+            "kernel_ms": round(kern_s * 1e3, 3),
+            "tuning": nk.nk_get_tuning(),
+            "workgroups": stats["workgroups"],
+            "block": stats["block"],
+            "levels_td": stats["levels_td"],
+            "levels_bu": stats["levels_bu"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": KERNEL,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, src, m_u)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * nk_bc.h -- Brandes betweenness centrality on one AMD Instinct MI355X
+ * (gfx950): the C ABI of libnkbc.so.
+ *
+ * The method is the one the NetworKit paper (Staudt, Sazonovs, Meyerhenke,
+ * arXiv 1403.3005) uses for betweenness (section "Heuristics and
+ * Approximation Algorithms"; Table 1): Brandes' algorithm for unweighted
+ * graphs, O(nm) for all sources -- per source a breadth-first search that
+ * counts shortest paths (distance d, path count sigma), then a reverse-level
+ * dependency accumulation (delta) -- summed over all sources, over a sampled
+ * source set (O(sm), scaled), or replaced by Riondato-Kornaropoulos pair
+ * sampling with an additive error guarantee epsilon at probability 1-delta.
+ *
+ * Graphs.  Undirected, unweighted, simple.  CSR with int32 indices:
+ *   rowptr  int32[n+1], rowptr[0] = 0, non-decreasing, rowptr[n] = m;
+ *   colidx  int32[m], entries in [0, n); every edge {u,v} appears as the two
+ *           arcs u->v and v->u; adjacency lists sorted ascending, no
+ *           self-loops, no duplicates (preconditions; the structural checks
+ *           run on every call, the simple-graph checks in
+ *           nk_validate_graph(strict=1)).
+ *   n       vertex count, 0 <= n < 2^31;  m  arc count, 0 <= m <= 2^31 - 2^16.
+ *
+ * Conventions (the paper does not fix them):
+ *   - scores sum over ORDERED pairs (s, t), s != v != t (twice the
+ *     unordered-pair value some libraries report);
+ *   - sigma is uint64; a path count that needs 2^64 or more is an error
+ *     (NK_E_SIGMA_OVERFLOW), never saturated;
+ *   - scores are FP64; unreachable vertices contribute nothing.
+ *
+ * Memory.  Unless stated otherwise every array argument is a DEVICE pointer
+ * (memory from hipMalloc or a PyTorch CUDA/HIP tensor) on the current HIP
+ * device.  The caller owns all inputs and outputs.  The library owns its
+ * scratch (pooled per device, released by nk_shutdown).
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Every call except the nk_server_* family enqueues its work on
+ * `stream` and synchronises that stream before it returns, so the returned
+ * status -- including a sigma overflow found on the GPU -- is final.
+ * Different host threads may call concurrently on different streams.
+ *
+ * Errors.  Functions return nk_status: 0 on success, a negative code on
+ * failure.  No C++ exception crosses this interface.  On failure the
+ * contents of output arrays are unspecified; nk_last_error() gives a message
+ * for the calling thread's last failure.  Argument checks come first, then
+ * graph checks, then the run.
+ */
+#ifndef NK_BC_H
+#define NK_BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nk_status;
+
+enum {
+    NK_OK = 0,
+    NK_E_INVALID_ARG = -1,     /* null pointer, negative size, bad epsilon ... */
+    NK_E_INVALID_GRAPH = -2,   /* CSR structure check failed                  */
+    NK_E_SIGMA_OVERFLOW = -3,  /* a shortest-path count needs >= 2^64         */
+    NK_E_NO_MEMORY = -4,       /* device allocation failed                    */
+    NK_E_HIP = -5,             /* a HIP runtime call failed                   */
+    NK_E_BUDGET = -6,          /* request can never fit the HBM budget        */
+    NK_E_TIMEOUT = -7,         /* nk_server_wait ran out of time              */
+    NK_E_INTERNAL = -8         /* internal capacity check tripped             */
+};
+
+/* Message for the calling thread's last failure ("" if none).  The pointer
+ * stays valid until the thread's next nk_* call. */
+const char *nk_last_error(void);
+
+/* Library version string. */
+const char *nk_version(void);
+
+/* Frees pooled device scratch on every device.  Optional; calls after it
+ * allocate again. */
+void nk_shutdown(void);
+
+/*
+ * CSR checks.  strict = 0: rowptr[0] = 0, rowptr non-decreasing,
+ * rowptr[n] = m, 0 <= colidx < n (the checks every call runs).
+ * strict = 1 adds: no self-loop, adjacency strictly ascending, every arc
+ * has its reverse.  Returns NK_OK or NK_E_INVALID_GRAPH.
+ */
+nk_status nk_validate_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                            int32_t strict, void *stream);
+
+/*
+ * Exact betweenness (Brandes' algorithm over every source, the paper's
+ * exact "Betweenness"; Table 1, O(nm)).
+ *   bc  FP64[n], overwritten: bc[v] = sum over ordered pairs (s,t),
+ *       s != v != t, of sigma_st(v) / sigma_st.
+ * n = 0 returns NK_OK and writes nothing.
+ */
+nk_status nk_bc_exact(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                      double *bc, void *stream);
+
+/*
+ * Betweenness summed over an explicit source list, times `scale` (the
+ * paper's sampled-source approximation: k shortest-path trees instead of n,
+ * O(km); scale = n/k gives the plain unbiased estimate).
+ *   sources  int32[k] DEVICE array of vertex ids in [0, n); a repeated id
+ *            counts once per occurrence; an id out of range is
+ *            NK_E_INVALID_ARG (detected on the device).
+ *   bc       FP64[n], overwritten.  k = 0 writes zeros.
+ */
+nk_status nk_bc_sources(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                        const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
+
+/*
+ * Forward phase only, for inspection: distance and shortest-path count from
+ * each of k sources (the breadth-first search with path counting that
+ * Brandes' algorithm runs per source).
+ *   sources  int32[k] DEVICE array;
+ *   d        int32[k*n] DEVICE, row i = source i, -1 = unreachable;
+ *   sigma    uint64[k*n] DEVICE, 0 = unreachable.
+ * Results are exact integers (bit-identical to any correct BFS).
+ */
+nk_status nk_sssp_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                         const int32_t *sources, int32_t k, int32_t *d, uint64_t *sigma, void *stream);
+
+/*
+ * Vertex-diameter bound for pair sampling (HOST output info[8]):
+ *   info = {x0, e1, a, e2, vd_ub, vd_lb, c0, c2} where x0 = vertex of
+ *   maximum degree (lowest id on ties), e1 = eccentricity of x0, a = lowest
+ *   id at distance e1 from x0, e2 = eccentricity of a (double sweep),
+ *   c0 = size of x0's component, c2 = largest other component,
+ *   vd_ub = max(min(2*e1+1, c0), c2) >= true vertex diameter,
+ *   vd_lb = e2 + 1.
+ * n = 0 gives all zeros.
+ */
+nk_status nk_vd_bound(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                      int32_t *info, void *stream);
+
+/*
+ * Riondato-Kornaropoulos sample size (host computation, constant c = 0.5):
+ *   r = ceil(0.5 / eps^2 * (floor(log2(max(vd - 2, 1))) + 1 + ln(1/delta))).
+ * Returns r, or -1 when eps or delta lies outside (0, 1).
+ */
+int64_t nk_rk_sample_size(double eps, double delta, int32_t vd);
+
+/*
+ * Pair-sampling betweenness with an additive guarantee (the paper's
+ * epsilon-approximation, Riondato and Kornaropoulos): r uniform ordered
+ * pairs (u, v), u != v, one uniformly chosen shortest u-v path each; with
+ * probability >= 1 - delta every |bc[v]/(n(n-1)) - BC(v)/(n(n-1))| <= eps.
+ *   eps, delta in (0, 1); seed selects the sample (counter-based
+ *   SplitMix64: pair j draws u from stream 1 and v from stream 2, step t of
+ *   its path walk draws from stream 3).
+ *   bc      FP64[n] DEVICE, counts[v] / r * n * (n-1);
+ *   counts  uint32[n] DEVICE or NULL: samples whose path has v inside;
+ *   r_out   HOST int64 or NULL: number of samples r;
+ *   vd_out  HOST int32 or NULL: the vertex-diameter bound used.
+ * n < 2 writes zeros and r = 0.
+ */
+nk_status nk_bc_pair_sample(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                            double eps, double delta, uint64_t seed, double *bc, uint32_t *counts,
+                            int64_t *r_out, int32_t *vd_out, void *stream);
+
+/*
+ * Pair-sampling counts for an explicit sample count r (no bound, no
+ * scaling): counts uint32[n] DEVICE.  Same sample sequence as
+ * nk_bc_pair_sample for the same seed.
+ */
+nk_status nk_pair_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                         int64_t r, uint64_t seed, uint32_t *counts, void *stream);
+
+/*
+ * Inspection of individual samples j0 .. j0+count-1 (DEVICE outputs):
+ *   uv     int32[count*2]  the pair (u, v);
+ *   len    int32[count]    number of interior path vertices, -1 if v is
+ *                          unreachable from u, -2 if more than maxlen;
+ *   path   int32[count*maxlen] interior vertices from v's side towards u.
+ */
+nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                          uint64_t seed, int64_t j0, int32_t count, int32_t maxlen,
+                          int32_t *uv, int32_t *len, int32_t *path, void *stream);
+
+/*
+ * Exact betweenness of G independent graphs in one persistent launch (the
+ * paper's recommended use on "large batches of smaller networks").
+ *   vtx_off  HOST int64[G+1]: graph g has vertices vtx_off[g] .. vtx_off[g+1]-1
+ *            of the concatenated vertex space;
+ *   arc_off  HOST int64[G+1]: its arcs are colidx_cat[arc_off[g] .. arc_off[g+1]);
+ *   rowptr_cat DEVICE int32[vtx_off[G] + G]: graph g's local rowptr (n_g+1
+ *            entries, starting at 0) at offset vtx_off[g] + g;
+ *   colidx_cat DEVICE int32[arc_off[G]]: local vertex ids;
+ *   bc_cat   DEVICE FP64[vtx_off[G]], overwritten.
+ * Every graph obeys the CSR rules above; all sources of all graphs run.
+ */
+nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                              const int32_t *rowptr_cat, const int32_t *colidx_cat, double *bc_cat,
+                              void *stream);
+
+/*
+ * Statistics of the calling thread's last nk_bc_exact / nk_bc_sources /
+ * nk_bc_exact_batched / pair-sampling call (HOST out[12]):
+ *   out[0] sources (or samples) processed     out[1] vertices reached
+ *   out[2] arcs scanned, forward              out[3] arcs scanned, backward
+ *   out[4] shortest-path DAG arcs             out[5] levels run top-down
+ *   out[6] levels run bottom-up               out[7] workgroups launched
+ *   out[8] main kernel time in microseconds (HIP events on the call's stream)
+ *   out[9] threads per workgroup              out[10] 1 if the visited bitmap sat in LDS
+ *   out[11] arcs of reached vertices (sum of their degrees, over sources)
+ */
+nk_status nk_last_stats(int64_t *out);
+
+/*
+ * Tuning of the per-source kernel (a6: direction switch and tiling).
+ *   block      threads per workgroup: 256, 512 or 1024 (0 = automatic);
+ *   bu_ratio   run a level bottom-up when the arcs of still-unvisited
+ *              vertices are below bu_ratio x the frontier's arcs
+ *              (0 = never bottom-up);
+ *   wg_per_cu  resident workgroups per compute unit requested (0 = as many
+ *              as fit);
+ *   flags      bit 0: keep the visited bitmap in global memory even when it
+ *              would fit in LDS (for testing that placement).
+ * nk_set_tuning applies to later calls from every thread.
+ */
+typedef struct {
+    int32_t block;
+    float bu_ratio;
+    int32_t wg_per_cu;
+    int32_t flags;
+} nk_tuning;
+
+nk_status nk_set_tuning(const nk_tuning *t);
+nk_status nk_get_tuning(nk_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NK_BC_H */

@@ -1,0 +1,239 @@
+"""ctypes binding of libnkbc.so: the C ABI of include/nk_bc.h under the same
+names.  Argument marshalling only -- every step of the computation runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream.
+
+Device arrays are torch tensors on the current HIP device:
+  rowptr, colidx, sources  int32, contiguous;
+  bc                       float64;
+  sigma                    int64 tensor holding uint64 bit patterns;
+  counts                   int32 tensor holding uint32 counts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnkbc.so")
+_lib = None
+
+NK_OK = 0
+NK_E_INVALID_ARG = -1
+NK_E_INVALID_GRAPH = -2
+NK_E_SIGMA_OVERFLOW = -3
+NK_E_NO_MEMORY = -4
+NK_E_HIP = -5
+NK_E_BUDGET = -6
+NK_E_TIMEOUT = -7
+NK_E_INTERNAL = -8
+
+EXPORTS = [
+    "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
+    "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
+    "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
+]
+
+
+class NkError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"nk status {code}: {message}")
+        self.code = code
+
+
+class NkTuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("bu_ratio", ctypes.c_float), ("wg_per_cu", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+def load():
+    """Loads libnkbc.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1403_3005_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp, i32p, i64p = c.c_void_p, c.POINTER(c.c_int32), c.POINTER(c.c_int64)
+    g = [vp, vp, c.c_int32, c.c_int64]
+    sig = {
+        "nk_last_error": (c.c_char_p, []),
+        "nk_version": (c.c_char_p, []),
+        "nk_shutdown": (None, []),
+        "nk_validate_graph": (c.c_int32, g + [c.c_int32, vp]),
+        "nk_bc_exact": (c.c_int32, g + [vp, vp]),
+        "nk_bc_sources": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
+        "nk_sssp_counts": (c.c_int32, g + [vp, c.c_int32, vp, vp, vp]),
+        "nk_vd_bound": (c.c_int32, g + [i32p, vp]),
+        "nk_rk_sample_size": (c.c_int64, [c.c_double, c.c_double, c.c_int32]),
+        "nk_bc_pair_sample": (c.c_int32, g + [c.c_double, c.c_double, c.c_uint64, vp, vp, i64p, i32p, vp]),
+        "nk_pair_counts": (c.c_int32, g + [c.c_int64, c.c_uint64, vp, vp]),
+        "nk_sample_paths": (c.c_int32, g + [c.c_uint64, c.c_int64, c.c_int32, c.c_int32, vp, vp, vp, vp]),
+        "nk_bc_exact_batched": (c.c_int32, [c.c_int32, i64p, i64p, vp, vp, vp, vp]),
+        "nk_last_stats": (c.c_int32, [i64p]),
+        "nk_set_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
+        "nk_get_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != NK_OK:
+        msg = load().nk_last_error().decode(errors="replace")
+        raise NkError(code, msg)
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _graph(rowptr, colidx):
+    rp = _dev(rowptr, torch.int32, "rowptr")
+    ci = _dev(colidx, torch.int32, "colidx")
+    n = rowptr.numel() - 1
+    m = colidx.numel()
+    return rp, ci, n, m
+
+
+def nk_version() -> str:
+    return load().nk_version().decode()
+
+
+def nk_shutdown():
+    load().nk_shutdown()
+
+
+def nk_validate_graph(rowptr, colidx, strict: bool = False, stream=None):
+    rp, ci, n, m = _graph(rowptr, colidx)
+    _check(load().nk_validate_graph(rp, ci, n, m, 1 if strict else 0, _stream(stream)))
+
+
+def nk_bc_exact(rowptr, colidx, bc=None, stream=None):
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if bc is None:
+        bc = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    _check(load().nk_bc_exact(rp, ci, n, m, _dev(bc, torch.float64, "bc"), _stream(stream)))
+    return bc
+
+
+def nk_bc_sources(rowptr, colidx, sources, scale: float = 1.0, bc=None, stream=None):
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if bc is None:
+        bc = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    k = sources.numel()
+    sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
+    _check(load().nk_bc_sources(rp, ci, n, m, sp, k, float(scale), _dev(bc, torch.float64, "bc"), _stream(stream)))
+    return bc
+
+
+def nk_sssp_counts(rowptr, colidx, sources, stream=None):
+    """(d int32[k, n], sigma int64[k, n] holding uint64 bits)."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    k = sources.numel()
+    d = torch.empty((k, n), dtype=torch.int32, device=rowptr.device)
+    sg = torch.empty((k, n), dtype=torch.int64, device=rowptr.device)
+    if k > 0 and n > 0:
+        _check(load().nk_sssp_counts(rp, ci, n, m, _dev(sources, torch.int32, "sources"), k,
+                                     _dev(d, torch.int32, "d"), _dev(sg, torch.int64, "sigma"), _stream(stream)))
+    return d, sg
+
+
+def nk_vd_bound(rowptr, colidx, stream=None) -> dict:
+    rp, ci, n, m = _graph(rowptr, colidx)
+    info = (ctypes.c_int32 * 8)()
+    _check(load().nk_vd_bound(rp, ci, n, m, info, _stream(stream)))
+    keys = ["x0", "e1", "a", "e2", "vd_ub", "vd_lb", "c0", "c2"]
+    return {k: int(v) for k, v in zip(keys, info)}
+
+
+def nk_rk_sample_size(eps: float, delta: float, vd: int) -> int:
+    return int(load().nk_rk_sample_size(eps, delta, vd))
+
+
+def nk_bc_pair_sample(rowptr, colidx, eps: float, delta: float, seed: int, stream=None):
+    """(bc float64[n], counts int32[n] holding uint32, r, vd)."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    bc = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    cnt = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
+    r = ctypes.c_int64(0)
+    vd = ctypes.c_int32(0)
+    _check(load().nk_bc_pair_sample(rp, ci, n, m, eps, delta, seed, _dev(bc, torch.float64, "bc"),
+                                    _dev(cnt, torch.int32, "counts"), ctypes.byref(r), ctypes.byref(vd),
+                                    _stream(stream)))
+    return bc, cnt, int(r.value), int(vd.value)
+
+
+def nk_pair_counts(rowptr, colidx, r: int, seed: int, stream=None):
+    rp, ci, n, m = _graph(rowptr, colidx)
+    cnt = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
+    _check(load().nk_pair_counts(rp, ci, n, m, r, seed, _dev(cnt, torch.int32, "counts"), _stream(stream)))
+    return cnt
+
+
+def nk_sample_paths(rowptr, colidx, seed: int, j0: int, count: int, maxlen: int, stream=None):
+    """(uv int32[count, 2], len int32[count], path int32[count, maxlen])."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    dev = rowptr.device
+    uv = torch.empty((count, 2), dtype=torch.int32, device=dev)
+    ln = torch.empty(count, dtype=torch.int32, device=dev)
+    path = torch.full((count, max(maxlen, 1)), -1, dtype=torch.int32, device=dev)
+    _check(load().nk_sample_paths(rp, ci, n, m, seed, j0, count, maxlen, _dev(uv, torch.int32, "uv"),
+                                  _dev(ln, torch.int32, "len"), _dev(path, torch.int32, "path"), _stream(stream)))
+    return uv, ln, path
+
+
+def nk_bc_exact_batched(vtx_off, arc_off, rowptr_cat, colidx_cat, stream=None):
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    ao = np.ascontiguousarray(arc_off, dtype=np.int64)
+    G = vo.shape[0] - 1
+    bc = torch.empty(int(vo[-1]), dtype=torch.float64, device=rowptr_cat.device)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ci = _dev(colidx_cat, torch.int32, "colidx_cat") if colidx_cat.numel() else ctypes.c_void_p(0)
+    _check(load().nk_bc_exact_batched(G, vo.ctypes.data_as(i64p), ao.ctypes.data_as(i64p),
+                                      _dev(rowptr_cat, torch.int32, "rowptr_cat"), ci,
+                                      _dev(bc, torch.float64, "bc_cat") if bc.numel() else ctypes.c_void_p(0),
+                                      _stream(stream)))
+    return bc
+
+
+STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",
+             "kernel_us", "block", "bitmap_lds", "arcs_reached"]
+
+
+def nk_last_stats() -> dict:
+    out = (ctypes.c_int64 * 12)()
+    _check(load().nk_last_stats(out))
+    return {k: int(v) for k, v in zip(STAT_KEYS, out)}
+
+
+def nk_set_tuning(block: int = 0, bu_ratio: float = 1.0, wg_per_cu: int = 0, flags: int = 0):
+    t = NkTuning(block, bu_ratio, wg_per_cu, flags)
+    _check(load().nk_set_tuning(ctypes.byref(t)))
+
+
+def nk_get_tuning() -> dict:
+    t = NkTuning()
+    _check(load().nk_get_tuning(ctypes.byref(t)))
+    return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags}

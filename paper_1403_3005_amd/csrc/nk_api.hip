@@ -1,0 +1,811 @@
+// Host runtime and C ABI of libnkbc.so (declarations and contracts in
+// include/nk_bc.h).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "nk_runtime.h"
+
+namespace nk {
+
+// ------------------------------------------------------------------ errors --
+
+static thread_local std::string t_err;
+static thread_local int64_t t_stats[12];
+
+nk_status fail(nk_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+void clear_error() { t_err.clear(); }
+
+nk_status map_err(int32_t err) {
+    if (err & kErrGraph) return fail(NK_E_INVALID_GRAPH, "CSR structure check failed");
+    if (err & kErrArg) return fail(NK_E_INVALID_ARG, "a source or sample index is out of range");
+    if (err & kErrOverflow) return fail(NK_E_SIGMA_OVERFLOW, "a shortest-path count needs 2^64 or more");
+    if (err & kErrInternal) return fail(NK_E_INTERNAL, "internal capacity check tripped");
+    return NK_OK;
+}
+
+// ------------------------------------------------------------ device info --
+
+static std::mutex g_dev_mu;
+static DevInfo g_dev[64];
+static bool g_dev_ok[64];
+
+nk_status dev_info(DevInfo *out) {
+    int dev = 0;
+    NK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(NK_E_HIP, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev_ok[dev]) {
+        DevInfo d;
+        d.device = dev;
+        int cus = 0, lds = 0;
+        NK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        NK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        d.cus = cus;
+        d.lds_per_block = (size_t)lds;
+        g_dev[dev] = d;
+        g_dev_ok[dev] = true;
+    }
+    *out = g_dev[dev];
+    return NK_OK;
+}
+
+// ------------------------------------------------------------ scratch pool --
+
+struct PoolBlock {
+    void *ptr;
+    size_t bytes;
+    int device;
+    bool busy;
+};
+static std::mutex g_pool_mu;
+static std::vector<PoolBlock> g_pool;
+
+nk_status Scratch::get(size_t bytes, void **out) {
+    int dev = 0;
+    NK_HIP(hipGetDevice(&dev));
+    bytes = (bytes + 255) & ~(size_t)255;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        int best = -1;
+        for (size_t i = 0; i < g_pool.size(); ++i) {
+            const PoolBlock &b = g_pool[i];
+            if (b.busy || b.device != dev || b.bytes < bytes || b.bytes > 2 * bytes + (64u << 20)) continue;
+            if (best < 0 || b.bytes < g_pool[best].bytes) best = (int)i;
+        }
+        if (best >= 0) {
+            g_pool[best].busy = true;
+            held_.push_back(g_pool[best].ptr);
+            *out = g_pool[best].ptr;
+            return NK_OK;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // release idle blocks of this device and retry once
+        std::vector<void *> idle;
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            for (size_t i = 0; i < g_pool.size();) {
+                if (!g_pool[i].busy && g_pool[i].device == dev) {
+                    idle.push_back(g_pool[i].ptr);
+                    g_pool.erase(g_pool.begin() + i);
+                } else {
+                    ++i;
+                }
+            }
+        }
+        for (void *q : idle) (void)hipFree(q);
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(NK_E_NO_MEMORY, "hipMalloc of %zu bytes failed", bytes);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        g_pool.push_back(PoolBlock{p, bytes, dev, true});
+    }
+    held_.push_back(p);
+    *out = p;
+    return NK_OK;
+}
+
+void Scratch::release_all() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (void *p : held_)
+        for (auto &b : g_pool)
+            if (b.ptr == p) b.busy = false;
+    held_.clear();
+}
+
+Scratch::~Scratch() { release_all(); }
+
+void pool_clear() {
+    std::vector<PoolBlock> keep, drop;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (auto &b : g_pool) (b.busy ? keep : drop).push_back(b);
+        g_pool = keep;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &b : drop) {
+        (void)hipSetDevice(b.device);
+        (void)hipFree(b.ptr);
+    }
+    (void)hipSetDevice(cur);
+}
+
+size_t pool_bytes_in_use() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    size_t s = 0;
+    for (auto &b : g_pool)
+        if (b.busy) s += b.bytes;
+    return s;
+}
+
+// ------------------------------------------------------------------ tuning --
+
+static std::mutex g_tune_mu;
+static nk_tuning g_tune = {0, 1.0f, 0, 0};
+
+nk_tuning tuning_get() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune;
+}
+
+void tuning_set(const nk_tuning &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = t;
+}
+
+// ------------------------------------------------------------------- stats --
+
+void stats_clear() { memset(t_stats, 0, sizeof(t_stats)); }
+
+void stats_record(const DevStatus &st, int grid, int block, bool lds, float kernel_ms) {
+    t_stats[0] = (int64_t)st.stat[kStSources];
+    t_stats[1] = (int64_t)st.stat[kStReached];
+    t_stats[2] = (int64_t)st.stat[kStArcsFwd];
+    t_stats[3] = (int64_t)st.stat[kStArcsBwd];
+    t_stats[4] = (int64_t)st.stat[kStDag];
+    t_stats[5] = (int64_t)st.stat[kStTd];
+    t_stats[6] = (int64_t)st.stat[kStBu];
+    t_stats[7] = grid;
+    t_stats[8] = (int64_t)llround((double)kernel_ms * 1000.0);
+    t_stats[9] = block;
+    t_stats[10] = lds ? 1 : 0;
+    t_stats[11] = (int64_t)st.stat[kStArcsReached];
+}
+
+static thread_local DevStatus *t_host_status = nullptr;
+static thread_local hipEvent_t t_ev[2] = {nullptr, nullptr};
+
+DevStatus *host_status() {
+    if (!t_host_status) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        t_host_status = (DevStatus *)p;
+    }
+    return t_host_status;
+}
+
+nk_status thread_events(hipEvent_t *ev0, hipEvent_t *ev1) {
+    if (!t_ev[0]) {
+        NK_HIP(hipEventCreate(&t_ev[0]));
+        NK_HIP(hipEventCreate(&t_ev[1]));
+    }
+    *ev0 = t_ev[0];
+    *ev1 = t_ev[1];
+    return NK_OK;
+}
+
+nk_status finish(DevStatus *dst, DevStatus *host, hipStream_t s) {
+    NK_HIP(hipMemcpyAsync(host, dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+    return map_err(host->err);
+}
+
+// Arc indices inside a tile are int32 and run up to 4 * BLOCK past the
+// tile's arc count, so m keeps a margin below 2^31.
+static const long long kMaxArcs = 2147483647LL - 65536;
+
+nk_status check_graph_args(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m) {
+    if (n < 0) return fail(NK_E_INVALID_ARG, "n = %d is negative", n);
+    if (m < 0 || m > kMaxArcs) return fail(NK_E_INVALID_ARG, "m = %lld outside [0, 2^31 - 2^16]", (long long)m);
+    if (n > 0 && !rowptr) return fail(NK_E_INVALID_ARG, "rowptr is NULL");
+    if (m > 0 && !colidx) return fail(NK_E_INVALID_ARG, "colidx is NULL");
+    return NK_OK;
+}
+
+// ----------------------------------------------------------------- planner --
+
+static int auto_block(int32_t n_max) {
+    if (n_max < 20000) return 256;
+    if (n_max < 200000) return 512;
+    return 1024;
+}
+
+nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan) {
+    DevInfo di;
+    nk_status st = dev_info(&di);
+    if (st != NK_OK) return st;
+    nk_tuning t = tuning_get();
+    int block = t.block;
+    if (block != 256 && block != 512 && block != 1024) block = auto_block(n_max);
+    const long long words = ((long long)n_max + 31) / 32;
+    const size_t bm_bytes = (size_t)words * 4;
+    bool lds = false;
+    {
+        KernelRef probe = brandes_kernel(mode, block, true);
+        hipFuncAttributes attr;
+        NK_HIP(hipFuncGetAttributes(&attr, probe.fn));
+        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1);
+    }
+    KernelRef kr = brandes_kernel(mode, block, lds);
+    size_t dyn = lds ? bm_bytes : 0;
+    if (lds) NK_HIP(hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    int occ = 0;
+    NK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kr.fn, block, dyn));
+    if (occ < 1) return fail(NK_E_INTERNAL, "kernel does not fit a compute unit (block %d, lds %zu)", block, dyn);
+    if (t.wg_per_cu > 0 && t.wg_per_cu < occ) occ = t.wg_per_cu;
+    long long grid = (long long)di.cus * occ;
+    if (ntasks < grid) grid = ntasks;
+    if (max_slots > 0 && grid > max_slots) grid = max_slots;
+    if (grid < 1) grid = 1;
+    plan->mode = mode;
+    plan->block = block;
+    plan->lds = lds;
+    plan->grid = (int)grid;
+    plan->dyn_lds = dyn;
+    plan->stride = (((long long)n_max + 2) + 63) / 64 * 64;
+    plan->bm_words = (words + 63) / 64 * 64;
+    plan->kernel = kr;
+    return NK_OK;
+}
+
+nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
+    const long long slots = plan.grid;
+    const long long cells = slots * plan.stride;
+    nk_status st;
+    if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.coef)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.d)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.list)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.cand)) != NK_OK) return st;
+    p.bmg = nullptr;
+    if (!plan.lds)
+        if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
+    p.stride = plan.stride;
+    p.bm_words = plan.bm_words;
+    p.bu_ratio = tuning_get().bu_ratio;
+    NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
+    if (ev0) NK_HIP(hipEventRecord(ev0, s));
+    plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
+    NK_HIP(hipGetLastError());
+    if (ev1) NK_HIP(hipEventRecord(ev1, s));
+    return NK_OK;
+}
+
+// --------------------------------------------------------- vertex diameter --
+
+// One breadth-first search from `src` (BFS mode, one workgroup): returns
+// eccentricity, lowest id at that distance and reached count.
+static nk_status bfs_once(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const uint32_t *iso,
+                          int32_t src, int32_t out[3], hipStream_t s) {
+    Scratch scr;
+    DevStatus *dst;
+    nk_status st;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    NK_HIP(launch_status_init(dst, s));
+    LaunchPlan plan;
+    if ((st = plan_launch(kModeBFS, n, 1, 1, &plan)) != NK_OK) return st;
+    Params p;
+    memset(&p, 0, sizeof(p));
+    p.rowptr = rowptr;
+    p.colidx = colidx;
+    p.n = n;
+    p.m = (int32_t)m;
+    p.ntasks = 1;
+    p.single_source = src;
+    p.iso = iso;
+    p.st = dst;
+    if ((st = launch_persistent(plan, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    if ((st = finish(dst, h, s)) != NK_OK) return st;
+    out[0] = h->info[0];
+    out[1] = h->info[1];
+    out[2] = h->info[2];
+    return NK_OK;
+}
+
+nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
+                        hipStream_t s) {
+    for (int i = 0; i < 8; ++i) info[i] = 0;
+    if (n == 0) return NK_OK;
+    Scratch scr;
+    DevStatus *dst;
+    unsigned long long *key;
+    uint32_t *iso;
+    int32_t *label, *size, *flag;
+    nk_status st;
+    const long long words = ((long long)n + 31) / 32;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    if ((st = scr.get(1, &key)) != NK_OK) return st;
+    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    if ((st = scr.get(n, &label)) != NK_OK) return st;
+    if ((st = scr.get(n, &size)) != NK_OK) return st;
+    if ((st = scr.get(2, &flag)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    NK_HIP(launch_fill_u64(key, 0ULL, 1, s));
+    NK_HIP(launch_argmax_degree(rowptr, n, key, s));
+    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    if ((st = finish(dst, h, s)) != NK_OK) return st;
+    unsigned long long k = 0;
+    NK_HIP(hipMemcpyAsync(&k, key, 8, hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+    const int32_t x0 = (int32_t)(0xffffffffULL - (k & 0xffffffffULL));
+    int32_t r1[3], r2[3];
+    if ((st = bfs_once(rowptr, colidx, n, m, iso, x0, r1, s)) != NK_OK) return st;
+    const int32_t e1 = r1[0], a = r1[1], c0 = r1[2];
+    if ((st = bfs_once(rowptr, colidx, n, m, iso, a, r2, s)) != NK_OK) return st;
+    const int32_t e2 = r2[0];
+    // largest component other than x0's
+    NK_HIP(launch_cc_init(label, n, s));
+    int32_t hflag = 1;
+    for (int it = 0; hflag && it < 100000; ++it) {
+        NK_HIP(launch_fill_i32(flag, 0, 1, s));
+        NK_HIP(launch_cc_hook(rowptr, colidx, n, label, flag, s));
+        NK_HIP(launch_cc_compress(label, n, s));
+        NK_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+        NK_HIP(hipStreamSynchronize(s));
+    }
+    if (hflag) return fail(NK_E_INTERNAL, "component labelling did not converge");
+    NK_HIP(launch_fill_i32(size, 0, n, s));
+    NK_HIP(launch_cc_sizes(label, n, size, s));
+    NK_HIP(launch_fill_i32(flag, 0, 1, s));
+    NK_HIP(launch_cc_other_max(label, size, n, x0, flag, s));
+    int32_t c2 = 0;
+    NK_HIP(hipMemcpyAsync(&c2, flag, 4, hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+    int32_t ub = 2 * e1 + 1;
+    if (ub > c0) ub = c0;
+    if (c2 > ub) ub = c2;
+    info[0] = x0;
+    info[1] = e1;
+    info[2] = a;
+    info[3] = e2;
+    info[4] = ub;
+    info[5] = e2 + 1;
+    info[6] = c0;
+    info[7] = c2;
+    return NK_OK;
+}
+
+}  // namespace nk
+
+using namespace nk;
+
+// ==================================================================== C ABI ==
+
+extern "C" {
+
+const char *nk_last_error(void) { return t_err.c_str(); }
+
+const char *nk_version(void) { return "nkbc 0.1 (gfx950)"; }
+
+void nk_shutdown(void) { pool_clear(); }
+
+nk_status nk_last_stats(int64_t *out) {
+    if (!out) return fail(NK_E_INVALID_ARG, "out is NULL");
+    memcpy(out, t_stats, sizeof(t_stats));
+    return NK_OK;
+}
+
+nk_status nk_set_tuning(const nk_tuning *t) {
+    clear_error();
+    if (!t) return fail(NK_E_INVALID_ARG, "tuning is NULL");
+    if (t->block != 0 && t->block != 256 && t->block != 512 && t->block != 1024)
+        return fail(NK_E_INVALID_ARG, "block must be 0, 256, 512 or 1024");
+    if (!(t->bu_ratio >= 0.0f) || t->wg_per_cu < 0) return fail(NK_E_INVALID_ARG, "bad tuning values");
+    tuning_set(*t);
+    return NK_OK;
+}
+
+nk_status nk_get_tuning(nk_tuning *t) {
+    if (!t) return fail(NK_E_INVALID_ARG, "tuning is NULL");
+    *t = tuning_get();
+    return NK_OK;
+}
+
+nk_status nk_validate_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t strict,
+                            void *stream) {
+    clear_error();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK || n == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, strict, dst, s));
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    return finish(dst, h, s);
+}
+
+// Shared body of nk_bc_exact / nk_bc_sources.
+static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                                 const int32_t *sources, long long k, double scale, double *bc, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n == 0) return NK_OK;
+    if (!bc) return fail(NK_E_INVALID_ARG, "bc is NULL");
+    if (k < 0) return fail(NK_E_INVALID_ARG, "k is negative");
+    if (k > 0 && !sources && k != n) return fail(NK_E_INVALID_ARG, "sources is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    uint32_t *iso;
+    const long long words = ((long long)n + 31) / 32;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    NK_HIP(launch_fill_f64(bc, 0.0, n, s));
+    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    LaunchPlan plan = {};
+    float ms = 0.0f;
+    if (k > 0) {
+        if ((st = plan_launch(kModeBC, n, k, 0, &plan)) != NK_OK) return st;
+        Params p;
+        memset(&p, 0, sizeof(p));
+        p.rowptr = rowptr;
+        p.colidx = colidx;
+        p.n = n;
+        p.m = (int32_t)m;
+        p.ntasks = k;
+        p.sources = sources;
+        p.bc = bc;
+        p.iso = iso;
+        p.st = dst;
+        hipEvent_t ev0, ev1;
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+        if (scale != 1.0) NK_HIP(launch_scale_f64(bc, scale, n, s));
+        st = finish(dst, h, s);
+        NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    } else {
+        st = finish(dst, h, s);
+    }
+    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    return st;
+}
+
+nk_status nk_bc_exact(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, double *bc,
+                      void *stream) {
+    return bc_sources_impl(rowptr, colidx, n, m, nullptr, n, 1.0, bc, stream);
+}
+
+nk_status nk_bc_sources(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
+                        int32_t k, double scale, double *bc, void *stream) {
+    if (k > 0 && !sources) {
+        clear_error();
+        return fail(NK_E_INVALID_ARG, "sources is NULL");
+    }
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream);
+}
+
+nk_status nk_sssp_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                         const int32_t *sources, int32_t k, int32_t *d, uint64_t *sigma, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n == 0 || k == 0) return NK_OK;
+    if (k < 0 || !sources || !d || !sigma) return fail(NK_E_INVALID_ARG, "bad sources / outputs");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    uint32_t *iso;
+    const long long words = ((long long)n + 31) / 32;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    NK_HIP(launch_fill_i32(d, -1, (long long)k * n, s));
+    NK_HIP(launch_fill_u64((unsigned long long *)sigma, 0ULL, (long long)k * n, s));
+    LaunchPlan plan;
+    if ((st = plan_launch(kModeSSSP, n, k, 0, &plan)) != NK_OK) return st;
+    Params p;
+    memset(&p, 0, sizeof(p));
+    p.rowptr = rowptr;
+    p.colidx = colidx;
+    p.n = n;
+    p.m = (int32_t)m;
+    p.ntasks = k;
+    p.sources = sources;
+    p.d_out = d;
+    p.sigma_out = (unsigned long long *)sigma;
+    p.iso = iso;
+    p.st = dst;
+    if ((st = launch_persistent(plan, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
+    st = finish(dst, h, s);
+    stats_record(*h, plan.grid, plan.block, plan.lds, 0.0f);
+    return st;
+}
+
+nk_status nk_vd_bound(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
+                      void *stream) {
+    clear_error();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (!info) return fail(NK_E_INVALID_ARG, "info is NULL");
+    return vd_bound_impl(rowptr, colidx, n, m, info, (hipStream_t)stream);
+}
+
+int64_t nk_rk_sample_size(double eps, double delta, int32_t vd) {
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0)) return -1;
+    int64_t x = (int64_t)vd - 2;
+    if (x < 1) x = 1;
+    int32_t fl = 0;
+    while ((x >> (fl + 1)) > 0) ++fl;
+    const double k = (double)(fl + 1) + (-log(delta));
+    const double rr = 0.5 / (eps * eps) * k;
+    return (int64_t)ceil(rr);
+}
+
+// Runs samples j0 .. j0+count-1 in pair mode.
+static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, long long count,
+                          unsigned long long seed, long long j0, uint32_t *counts, int32_t *uv, int32_t *len,
+                          int32_t *path, int32_t maxlen, DevStatus *dst, Scratch &scr, hipStream_t s,
+                          LaunchPlan *plan_out, hipEvent_t ev0, hipEvent_t ev1) {
+    nk_status st;
+    uint32_t *iso;
+    const long long words = ((long long)n + 31) / 32;
+    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    LaunchPlan plan;
+    if ((st = plan_launch(kModePair, n, count, 0, &plan)) != NK_OK) return st;
+    Params p;
+    memset(&p, 0, sizeof(p));
+    p.rowptr = rowptr;
+    p.colidx = colidx;
+    p.n = n;
+    p.m = (int32_t)m;
+    p.ntasks = count;
+    p.seed = seed;
+    p.j0 = j0;
+    p.counts = counts;
+    p.p_uv = uv;
+    p.p_len = len;
+    p.p_path = path;
+    p.maxlen = maxlen;
+    p.iso = iso;
+    p.st = dst;
+    if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+    *plan_out = plan;
+    return NK_OK;
+}
+
+nk_status nk_pair_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int64_t r,
+                         uint64_t seed, uint32_t *counts, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n == 0) return NK_OK;
+    if (!counts || r < 0) return fail(NK_E_INVALID_ARG, "counts is NULL or r < 0");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    NK_HIP(launch_fill_u32(counts, 0u, n, s));
+    LaunchPlan plan = {};
+    float ms = 0.0f;
+    if (n >= 2 && r > 0) {
+        hipEvent_t ev0, ev1;
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        if ((st = pair_run(rowptr, colidx, n, m, r, seed, 0, counts, nullptr, nullptr, nullptr, 0, dst, scr, s, &plan,
+                           ev0, ev1)) != NK_OK)
+            return st;
+        st = finish(dst, h, s);
+        NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    } else {
+        st = finish(dst, h, s);
+    }
+    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    return st;
+}
+
+nk_status nk_bc_pair_sample(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, double eps,
+                            double delta, uint64_t seed, double *bc, uint32_t *counts, int64_t *r_out,
+                            int32_t *vd_out, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0))
+        return fail(NK_E_INVALID_ARG, "eps and delta must lie in (0, 1)");
+    if (n == 0) {
+        if (r_out) *r_out = 0;
+        if (vd_out) *vd_out = 0;
+        return NK_OK;
+    }
+    if (!bc) return fail(NK_E_INVALID_ARG, "bc is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t info[8];
+    if ((st = vd_bound_impl(rowptr, colidx, n, m, info, s)) != NK_OK) return st;
+    const long long r = n >= 2 ? nk_rk_sample_size(eps, delta, info[4]) : 0;
+    if (r_out) *r_out = r;
+    if (vd_out) *vd_out = info[4];
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    uint32_t *cnt = counts;
+    if (!cnt && (st = scr.get(n, &cnt)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_fill_u32(cnt, 0u, n, s));
+    LaunchPlan plan = {};
+    float ms = 0.0f;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (r > 0) {
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        if ((st = pair_run(rowptr, colidx, n, m, r, seed, 0, cnt, nullptr, nullptr, nullptr, 0, dst, scr, s, &plan,
+                           ev0, ev1)) != NK_OK)
+            return st;
+    }
+    const double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
+    NK_HIP(launch_counts_to_bc(cnt, bc, scale, n, s));
+    st = finish(dst, h, s);
+    if (r > 0) NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    return st;
+}
+
+nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, uint64_t seed,
+                          int64_t j0, int32_t count, int32_t maxlen, int32_t *uv, int32_t *len, int32_t *path,
+                          void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n < 2) return fail(NK_E_INVALID_ARG, "pair sampling needs n >= 2");
+    if (count < 0 || j0 < 0 || maxlen < 0 || (count > 0 && (!uv || !len || (maxlen > 0 && !path))))
+        return fail(NK_E_INVALID_ARG, "bad sample range or outputs");
+    if (count == 0) return NK_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    LaunchPlan plan;
+    if ((st = pair_run(rowptr, colidx, n, m, count, seed, j0, nullptr, uv, len, maxlen > 0 ? path : nullptr, maxlen,
+                       dst, scr, s, &plan, nullptr, nullptr)) != NK_OK)
+        return st;
+    st = finish(dst, h, s);
+    stats_record(*h, plan.grid, plan.block, plan.lds, 0.0f);
+    return st;
+}
+
+nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *arc_off, const int32_t *rowptr_cat,
+                              const int32_t *colidx_cat, double *bc_cat, void *stream) {
+    clear_error();
+    stats_clear();
+    if (G < 0) return fail(NK_E_INVALID_ARG, "G is negative");
+    if (G == 0) return NK_OK;
+    if (!vtx_off || !arc_off) return fail(NK_E_INVALID_ARG, "offset tables are NULL");
+    if (vtx_off[0] != 0 || arc_off[0] != 0) return fail(NK_E_INVALID_ARG, "offsets must start at 0");
+    int32_t n_max = 0;
+    std::vector<long long> work(G);
+    for (int32_t g = 0; g < G; ++g) {
+        const long long ng = vtx_off[g + 1] - vtx_off[g], mg = arc_off[g + 1] - arc_off[g];
+        if (ng < 0 || mg < 0 || ng > 2147483647LL || mg > 2147483647LL)
+            return fail(NK_E_INVALID_ARG, "graph %d has bad offsets", g);
+        n_max = std::max<int32_t>(n_max, (int32_t)ng);
+        work[g] = ng * std::max<long long>(mg, 1);
+    }
+    const long long nv = vtx_off[G], na = arc_off[G];
+    if (nv == 0) return NK_OK;
+    if (!rowptr_cat || (na > 0 && !colidx_cat) || !bc_cat) return fail(NK_E_INVALID_ARG, "NULL graph or output");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    nk_status st;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t ng = (int32_t)(vtx_off[g + 1] - vtx_off[g]);
+        if (ng == 0) continue;
+        NK_HIP(launch_validate(rowptr_cat + vtx_off[g] + g, colidx_cat + arc_off[g], ng, arc_off[g + 1] - arc_off[g],
+                               0, dst, s));
+    }
+    NK_HIP(launch_fill_f64(bc_cat, 0.0, nv, s));
+    // largest graphs first so the tail of the launch is made of small tasks
+    std::vector<int32_t> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    std::vector<long long> task_pre(G + 1, 0);
+    for (int32_t i = 0; i < G; ++i) task_pre[i + 1] = task_pre[i] + (vtx_off[order[i] + 1] - vtx_off[order[i]]);
+    long long *d_vtx, *d_arc, *d_task;
+    int32_t *d_order;
+    if ((st = scr.get(G + 1, &d_vtx)) != NK_OK) return st;
+    if ((st = scr.get(G + 1, &d_arc)) != NK_OK) return st;
+    if ((st = scr.get(G + 1, &d_task)) != NK_OK) return st;
+    if ((st = scr.get(G, &d_order)) != NK_OK) return st;
+    NK_HIP(hipMemcpyAsync(d_vtx, vtx_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
+    NK_HIP(hipMemcpyAsync(d_arc, arc_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
+    NK_HIP(hipMemcpyAsync(d_task, task_pre.data(), sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
+    NK_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+    LaunchPlan plan;
+    if ((st = plan_launch(kModeBC, n_max, task_pre[G], 0, &plan)) != NK_OK) return st;
+    Params p;
+    memset(&p, 0, sizeof(p));
+    p.rowptr = rowptr_cat;
+    p.colidx = colidx_cat;
+    p.n = n_max;
+    p.G = G;
+    p.g_vtx = d_vtx;
+    p.g_arc = d_arc;
+    p.g_task = d_task;
+    p.g_order = d_order;
+    p.ntasks = task_pre[G];
+    p.bc = bc_cat;
+    p.st = dst;
+    hipEvent_t ev0, ev1;
+    if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+    if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+    st = finish(dst, h, s);
+    float ms = 0.0f;
+    NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal interface between the HIP kernels (nk_kernels.hip) and the host
+// runtime (nk_api.cpp, nk_server.cpp).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nk_device.h"
+
+namespace nk {
+
+// What a persistent Brandes launch computes per task.
+enum Mode : int {
+    kModeBC = 0,    // forward + dependency sweep, scores into bc
+    kModeSSSP = 1,  // forward only, d and sigma written out per task
+    kModePair = 2,  // forward truncated at the target, one path walk
+    kModeBFS = 3    // forward without path counts (eccentricity only)
+};
+
+// Everything a persistent launch reads.  Per-slot scratch arrays hold
+// `stride` elements per workgroup slot (slot = blockIdx.x).
+struct Params {
+    // graph: single graph, or G > 0 concatenated graphs
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    int32_t n;
+    int32_t m;
+    int32_t G;
+    int32_t pad0;
+    const long long *g_vtx;    // [G+1] vertex offsets
+    const long long *g_arc;    // [G+1] arc offsets
+    const long long *g_task;   // [G+1] task prefix in processing order
+    const int32_t *g_order;    // [G] processing order -> graph id
+    // tasks
+    long long ntasks;
+    const int32_t *sources;    // task -> source (NULL: task id is the source)
+    int32_t single_source;     // BFS mode
+    int32_t maxlen;            // pair inspection
+    // outputs
+    double *bc;
+    int32_t *d_out;
+    unsigned long long *sigma_out;
+    uint32_t *counts;
+    int32_t *p_uv;
+    int32_t *p_len;
+    int32_t *p_path;
+    unsigned long long seed;
+    long long j0;
+    // scratch
+    unsigned long long *sigma;
+    double *coef;
+    int32_t *d;
+    int32_t *list;
+    int32_t *lvl;
+    int32_t *cand;
+    uint32_t *bmg;             // global bitmaps (when not in LDS)
+    const uint32_t *iso;       // isolated-vertex bitmap of a single graph, or NULL
+    long long stride;          // per-slot elements of the n-sized arrays
+    long long bm_words;        // per-slot words of a global bitmap
+    float bu_ratio;
+    int32_t pad1;
+    DevStatus *st;
+};
+
+// Kernel handle for one (mode, block, bitmap placement) instantiation.
+struct KernelRef {
+    const void *fn;
+    void (*launch)(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Params &p);
+};
+
+KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds);
+
+// Small helper launches (all asynchronous on `s`).
+hipError_t launch_status_init(DevStatus *st, hipStream_t s);
+hipError_t launch_validate(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t strict,
+                           DevStatus *st, hipStream_t s);
+hipError_t launch_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, long long count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, long long count, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, long long count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, hipStream_t s);
+hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
+hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);
+hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s);
+hipError_t launch_cc_init(int32_t *label, int32_t n, hipStream_t s);
+hipError_t launch_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed,
+                          hipStream_t s);
+hipError_t launch_cc_compress(int32_t *label, int32_t n, hipStream_t s);
+hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipStream_t s);
+hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
+                               hipStream_t s);
+hipError_t launch_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv,
+                            hipStream_t s);
+
+}  // namespace nk

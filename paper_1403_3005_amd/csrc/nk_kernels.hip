@@ -1,0 +1,822 @@
+// HIP kernels for Brandes betweenness on gfx950.
+//
+// One persistent kernel runs whole tasks per workgroup: a task is one
+// source (exact / source-set / batched multi-graph forms), one sampled pair
+// (pair sampling) or one inspection source.  Per task the workgroup runs
+// Brandes' two phases (Brandes 2001, the algorithm the paper cites for
+// betweenness in "Heuristics and Approximation Algorithms" and Table 1):
+//
+//   forward   level-synchronous breadth-first search that counts shortest
+//             paths: sigma[w] = sum of sigma[v] over neighbours v one level
+//             closer to the source.  Each level runs either top-down (scan
+//             the arcs of the frontier list, 64-bit atomic adds into sigma
+//             of unvisited neighbours, the first adder appends the vertex)
+//             or bottom-up (scan all arcs of every unvisited vertex and sum
+//             sigma over neighbours in the frontier, no atomics, no early
+//             exit because every frontier neighbour contributes).  New
+//             vertices are compacted into the next level list with a wave
+//             ballot and one LDS atomic per wave.  The concatenated level
+//             lists are the visit order S of Brandes' algorithm.
+//
+//   backward  for levels from deepest to 1, every vertex v of the level
+//             pulls over its neighbours w one level deeper:
+//                 delta_v = sigma_v * sum_w (1 + delta_w) / sigma_w,
+//             stores coef_v = (1 + delta_v) / sigma_v for the level above
+//             and adds delta_v to bc[v] (FP64 atomic add).  This is the
+//             dependency recursion of Brandes' algorithm rearranged as a
+//             pull, so no vertex is written by two threads.
+//
+// Visited state lives in one bitmap (LDS when it fits, else a per-slot
+// global bitmap).  Isolated vertices start marked.  During the forward phase
+// a neighbour of a level-l vertex that is unmarked must be at level l+1,
+// and a marked neighbour of an unvisited vertex must be at level l; during
+// the backward phase levels are unmarked from the deepest up, so an
+// unmarked neighbour of a level-l vertex is at level l+1.  No distance
+// array is read on the hot path.
+//
+// Work inside a level is balanced over arcs, not vertices: a tile of up to
+// BLOCK listed vertices is staged in LDS with an exclusive prefix sum of
+// degrees, and each thread takes CHUNK consecutive arcs of the tile (one
+// binary search, then a forward walk), so hubs with 10^5 arcs and leaves
+// share the same loop and colidx reads stay contiguous per wave.
+#include "nk_kernels.h"
+
+namespace nk {
+
+constexpr int kChunk = 4;
+
+struct GView {
+    const int32_t *rp;
+    const int32_t *ci;
+    int32_t n;
+    int32_t m;
+    long long vbase;   // offset of vertex 0 in concatenated outputs
+};
+
+struct Scr {
+    unsigned long long *sigma;
+    double *coef;
+    int32_t *d;
+    int32_t *list;
+    int32_t *lvl;
+    int32_t *cand;
+};
+
+struct Counters {
+    unsigned long long arcs_fwd, arcs_bwd, dag, reached, tasks, td, bu, arcs_reached;
+};
+
+__device__ __forceinline__ bool bit_test(const uint32_t *bm, int32_t v) {
+    return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+__device__ __forceinline__ void bit_set(uint32_t *bm, int32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
+__device__ __forceinline__ void bit_clear(uint32_t *bm, int32_t v) { atomicAnd(&bm[v >> 5], ~(1u << (v & 31))); }
+
+// ---------------------------------------------------------------- forward --
+
+// Top-down expansion of level `lvl` (list[f0, f1)) into list[f1, ...).
+template <int BLOCK, int MODE>
+__device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+                         int32_t f0, int32_t f1, int32_t lvl, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t tb = f0; tb < f1; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, f1 - tb);
+        int32_t dg = 0;
+        if (tid < cnt) {
+            const int32_t v = s.list[tb + tid];
+            const int32_t a0 = g.rp[v];
+            dg = g.rp[v + 1] - a0;
+            sm.v[tid] = v;
+            sm.a0[tid] = a0;
+            sm.val.u[tid] = (MODE == kModeBFS) ? 1ULL : s.sigma[v];
+        }
+        int32_t total;
+        const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+        if (tid < cnt) sm.pre[tid] = ex;
+        if (tid == 0) sm.pre[cnt] = total;
+        __syncthreads();
+        if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            const int32_t i0 = rb + tid * kChunk;
+            int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const int32_t i = i0 + j;
+                bool fresh = false;
+                int32_t w = 0;
+                if (i < total) {
+                    while (sm.pre[k + 1] <= i) ++k;
+                    w = g.ci[sm.a0[k] + (i - sm.pre[k])];
+                    if (!bit_test(bm, w)) {
+                        const unsigned long long sv = sm.val.u[k];
+                        const unsigned long long old = atomicAdd(&s.sigma[w], sv);
+                        if (MODE != kModeBFS && old + sv < old) atomicOr(&p.st->err, kErrOverflow);
+                        c.dag++;
+                        if (old == 0ULL) {
+                            fresh = true;
+                            s.d[w] = lvl + 1;
+                        }
+                    }
+                }
+                wave_append(fresh, w, s.list + f1, &sm.count, g.n - f1, &p.st->err);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Bottom-up expansion: every unvisited vertex sums sigma over its marked
+// (= frontier) neighbours.
+template <int BLOCK, int MODE>
+__device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+                         int32_t f1, int32_t lvl, Counters &c) {
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int32_t nw = (g.n + 31) >> 5;
+    if (tid == 0) sm.redmin = 0;  // candidate counter
+    __syncthreads();
+    for (int32_t wb = 0; wb < nw; wb += BLOCK) {
+        const int32_t wi = wb + tid;
+        uint32_t bits = (wi < nw) ? ~bm[wi] : 0u;
+        const int32_t cnt = __popc(bits);
+        const int32_t incl = wave_incl_scan<int32_t>(cnt);
+        const int32_t wtot = __shfl(incl, kWave - 1, kWave);
+        int32_t base = 0;
+        if (lane == kWave - 1 && wtot > 0) base = atomicAdd(&sm.redmin, wtot);
+        base = __shfl(base, kWave - 1, kWave);
+        int32_t pos = base + incl - cnt;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            s.cand[pos++] = wi * 32 + b;
+        }
+    }
+    __syncthreads();
+    const int32_t nc = sm.redmin;
+    for (int32_t tb = 0; tb < nc; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, nc - tb);
+        int32_t dg = 0;
+        if (tid < cnt) {
+            const int32_t w = s.cand[tb + tid];
+            const int32_t a0 = g.rp[w];
+            dg = g.rp[w + 1] - a0;
+            sm.v[tid] = w;
+            sm.a0[tid] = a0;
+            sm.val.u[tid] = 0ULL;
+        }
+        int32_t total;
+        const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+        if (tid < cnt) sm.pre[tid] = ex;
+        if (tid == 0) sm.pre[cnt] = total;
+        __syncthreads();
+        if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            const int32_t i0 = rb + tid * kChunk;
+            if (i0 < total) {
+                int32_t k = tile_search(sm.pre, cnt, i0);
+                int32_t kcur = k;
+                unsigned long long acc = 0ULL;
+                const int32_t iend = min(i0 + kChunk, total);
+                for (int32_t i = i0; i < iend; ++i) {
+                    while (sm.pre[k + 1] <= i) ++k;
+                    if (k != kcur) {
+                        if (acc) {
+                            const unsigned long long old = atomicAdd(&sm.val.u[kcur], acc);
+                            if (old + acc < old) atomicOr(&p.st->err, kErrOverflow);
+                        }
+                        kcur = k;
+                        acc = 0ULL;
+                    }
+                    const int32_t v = g.ci[sm.a0[k] + (i - sm.pre[k])];
+                    if (bit_test(bm, v)) {
+                        const unsigned long long sv = (MODE == kModeBFS) ? 1ULL : s.sigma[v];
+                        const unsigned long long nacc = acc + sv;
+                        if (MODE != kModeBFS && nacc < acc) atomicOr(&p.st->err, kErrOverflow);
+                        acc = nacc;
+                        c.dag++;
+                    }
+                }
+                if (acc) {
+                    const unsigned long long old = atomicAdd(&sm.val.u[kcur], acc);
+                    if (MODE != kModeBFS && old + acc < old) atomicOr(&p.st->err, kErrOverflow);
+                }
+            }
+        }
+        __syncthreads();
+        bool fresh = false;
+        int32_t w = 0;
+        if (tid < cnt) {
+            const unsigned long long sum = sm.val.u[tid];
+            if (sum != 0ULL) {
+                w = sm.v[tid];
+                s.sigma[w] = sum;
+                s.d[w] = lvl + 1;
+                fresh = true;
+            }
+        }
+        wave_append(fresh, w, s.list + f1, &sm.count, g.n - f1, &p.st->err);
+        __syncthreads();
+    }
+}
+
+// Forward phase from `src`.  Returns the deepest non-empty level Ld; the
+// list holds levels 0..Ld at s.lvl[l] .. s.lvl[l+1].  In pair mode the
+// search stops after the level that reaches `target`.
+template <int BLOCK, int MODE>
+__device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+                           int32_t src, int32_t target, Counters &c) {
+    const int tid = threadIdx.x;
+    const int32_t nw = (g.n + 31) >> 5;
+    for (int32_t wi = tid; wi < nw; wi += BLOCK) {
+        uint32_t x = p.iso ? p.iso[wi] : 0u;
+        const int32_t hi = (wi + 1) * 32;
+        if (hi > g.n) x |= ~0u << (32 - (hi - g.n));   // padding bits beyond n stay marked
+        bm[wi] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bm[src >> 5] |= 1u << (src & 31);
+        s.sigma[src] = 1ULL;
+        s.d[src] = 0;
+        s.list[0] = src;
+        s.lvl[0] = 0;
+        s.lvl[1] = 1;
+        const long long dsrc = g.rp[src + 1] - g.rp[src];
+        sm.mf = dsrc;
+        sm.mu = (long long)g.m - dsrc;
+        c.arcs_reached += (unsigned long long)dsrc;
+        sm.lvl_lo[0] = 0;
+        sm.lvl_lo[1] = 1;
+        sm.flag = 0;
+    }
+    __syncthreads();
+    int32_t lvl = 0;
+    for (;;) {
+        const int32_t f0 = sm.lvl_lo[0], f1 = sm.lvl_lo[1];
+        if (MODE == kModePair && sm.flag) break;
+        const bool bu = (p.bu_ratio > 0.0f) && ((double)sm.mu < (double)p.bu_ratio * (double)sm.mf);
+        __syncthreads();
+        if (tid == 0) {
+            sm.count = 0;
+            sm.acc_mf = 0;
+            if (bu) c.bu++; else c.td++;
+        }
+        __syncthreads();
+        if (bu)
+            bu_level<BLOCK, MODE>(p, sm, bm, s, g, f1, lvl, c);
+        else
+            td_level<BLOCK, MODE>(p, sm, bm, s, g, f0, f1, lvl, c);
+        __syncthreads();
+        const int32_t nnew = sm.count < g.n - f1 ? sm.count : g.n - f1;
+        long long dsum = 0;
+        for (int32_t i = f1 + tid; i < f1 + nnew; i += BLOCK) {
+            const int32_t w = s.list[i];
+            bit_set(bm, w);
+            dsum += g.rp[w + 1] - g.rp[w];
+        }
+        dsum = wave_sum<long long>(dsum);
+        if (lane_id() == 0 && dsum) atomicAdd((unsigned long long *)&sm.acc_mf, (unsigned long long)dsum);
+        __syncthreads();
+        if (tid == 0) {
+            s.lvl[lvl + 2] = f1 + nnew;
+            sm.lvl_lo[0] = f1;
+            sm.lvl_lo[1] = f1 + nnew;
+            sm.mu -= sm.acc_mf;
+            sm.mf = sm.acc_mf;
+            c.arcs_reached += (unsigned long long)sm.acc_mf;
+            if (MODE == kModePair) sm.flag = bit_test(bm, target) ? 1 : 0;
+        }
+        __syncthreads();
+        if (nnew == 0) break;
+        ++lvl;
+    }
+    return lvl;
+}
+
+// --------------------------------------------------------------- backward --
+
+template <int BLOCK>
+__device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+                         int32_t Ld, double *bcg, Counters &c) {
+    const int tid = threadIdx.x;
+    if (Ld == 0) return;
+    {
+        const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
+        for (int32_t i = lo + tid; i < hi; i += BLOCK) {
+            const int32_t v = s.list[i];
+            s.coef[v] = 1.0 / (double)s.sigma[v];
+            bit_clear(bm, v);
+        }
+    }
+    __syncthreads();
+    for (int32_t l = Ld - 1; l >= 1; --l) {
+        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
+        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, hi - tb);
+            int32_t dg = 0;
+            if (tid < cnt) {
+                const int32_t v = s.list[tb + tid];
+                const int32_t a0 = g.rp[v];
+                dg = g.rp[v + 1] - a0;
+                sm.v[tid] = v;
+                sm.a0[tid] = a0;
+                sm.val.f[tid] = 0.0;
+            }
+            int32_t total;
+            const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+            if (tid < cnt) sm.pre[tid] = ex;
+            if (tid == 0) sm.pre[cnt] = total;
+            __syncthreads();
+            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                const int32_t i0 = rb + tid * kChunk;
+                if (i0 < total) {
+                    int32_t k = tile_search(sm.pre, cnt, i0);
+                    int32_t kcur = k;
+                    double acc = 0.0;
+                    const int32_t iend = min(i0 + kChunk, total);
+                    for (int32_t i = i0; i < iend; ++i) {
+                        while (sm.pre[k + 1] <= i) ++k;
+                        if (k != kcur) {
+                            if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                            kcur = k;
+                            acc = 0.0;
+                        }
+                        const int32_t w = g.ci[sm.a0[k] + (i - sm.pre[k])];
+                        if (!bit_test(bm, w)) acc += s.coef[w];
+                    }
+                    if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                }
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                const int32_t v = sm.v[tid];
+                const double sg = (double)s.sigma[v];
+                const double delta = sg * sm.val.f[tid];
+                s.coef[v] = (1.0 + delta) / sg;
+                if (delta != 0.0) atomicAdd(bcg + v, delta);
+            }
+            __syncthreads();
+        }
+        for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.list[i]);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------- path walk --
+
+// One wave walks from `target` back to `src`, at each vertex picking the
+// first predecessor (in adjacency order) whose running sigma sum exceeds a
+// uniform draw below sigma: predecessor p is taken with probability
+// sigma_p / sigma_w.  Interior vertices get counts[p] += 1.
+__device__ void walk_path(const Params &p, const uint32_t *bm, const Scr &s, const GView &g, int32_t src,
+                          int32_t target, long long j, long long task) {
+    const int lane = lane_id();
+    int32_t x = target;
+    unsigned long long t = 0;
+    int32_t len = 0;
+    bool ok = true;
+    while (x != src) {
+        const int32_t dx = s.d[x];
+        const unsigned long long r = bounded(draw(p.seed, 3, (unsigned long long)j, t), s.sigma[x]);
+        const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
+        unsigned long long carry = 0ULL;
+        int32_t pick = -1;
+        for (int32_t base = a0; base < a1; base += kWave) {
+            const int32_t e = base + lane;
+            int32_t pp = -1;
+            unsigned long long sp = 0ULL;
+            if (e < a1) {
+                pp = g.ci[e];
+                if (bit_test(bm, pp) && s.d[pp] == dx - 1) sp = s.sigma[pp];
+            }
+            const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
+            const unsigned long long mask = __ballot(e < a1 && carry + incl > r);
+            if (mask) {
+                pick = __shfl(pp, __ffsll((long long)mask) - 1, kWave);
+                break;
+            }
+            carry += __shfl(incl, kWave - 1, kWave);
+        }
+        if (pick < 0) {
+            ok = false;
+            if (lane == 0) atomicOr(&p.st->err, kErrInternal);
+            break;
+        }
+        if (pick != src) {
+            if (lane == 0) {
+                if (p.counts) atomicAdd(&p.counts[pick], 1u);
+                if (p.p_path && len < p.maxlen) p.p_path[task * p.maxlen + len] = pick;
+            }
+            ++len;
+        }
+        x = pick;
+        ++t;
+    }
+    if (lane == 0 && p.p_len) p.p_len[task] = !ok ? -3 : (len > p.maxlen ? -2 : len);
+}
+
+// ------------------------------------------------------------ the kernel --
+
+template <int BLOCK, bool BMLDS, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
+    extern __shared__ uint32_t lds_bm[];
+    __shared__ Tile<BLOCK> sm;
+    const int tid = threadIdx.x;
+    if (tid == 0) sm.flag = p.st->err & kErrGraph;
+    __syncthreads();
+    if (sm.flag) return;
+    __syncthreads();
+
+    const long long slot = blockIdx.x;
+    Scr s;
+    s.sigma = p.sigma + slot * p.stride;
+    s.coef = p.coef + slot * p.stride;
+    s.d = p.d + slot * p.stride;
+    s.list = p.list + slot * p.stride;
+    s.lvl = p.lvl + slot * p.stride;
+    s.cand = p.cand + slot * p.stride;
+    uint32_t *bm = BMLDS ? lds_bm : p.bmg + slot * p.bm_words;
+
+    Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (;;) {
+        if (tid == 0) sm.task = (long long)atomicAdd(&p.st->head, 1ULL);
+        __syncthreads();
+        const long long task = sm.task;
+        __syncthreads();
+        if (task >= p.ntasks) break;
+
+        GView g;
+        int32_t src = 0, target = -1;
+        long long j = 0;
+        if (p.G > 0) {
+            int32_t lo = 0, hi = p.G - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (p.g_task[mid] <= task) lo = mid; else hi = mid - 1;
+            }
+            const int32_t gid = p.g_order[lo];
+            const long long v0 = p.g_vtx[gid];
+            g.rp = p.rowptr + v0 + gid;
+            g.ci = p.colidx + p.g_arc[gid];
+            g.n = (int32_t)(p.g_vtx[gid + 1] - v0);
+            g.m = (int32_t)(p.g_arc[gid + 1] - p.g_arc[gid]);
+            g.vbase = v0;
+            src = (int32_t)(task - p.g_task[lo]);
+        } else {
+            g.rp = p.rowptr;
+            g.ci = p.colidx;
+            g.n = p.n;
+            g.m = p.m;
+            g.vbase = 0;
+            if (MODE == kModePair) {
+                j = p.j0 + task;
+                const int32_t a = (int32_t)bounded(draw(p.seed, 1, (unsigned long long)j, 0), (unsigned long long)p.n);
+                int32_t b = (int32_t)bounded(draw(p.seed, 2, (unsigned long long)j, 0), (unsigned long long)(p.n - 1));
+                if (b >= a) b += 1;
+                src = a;
+                target = b;
+                if (tid == 0 && p.p_uv) {
+                    p.p_uv[2 * task] = a;
+                    p.p_uv[2 * task + 1] = b;
+                }
+            } else if (MODE == kModeBFS) {
+                src = p.single_source;
+            } else {
+                src = p.sources ? p.sources[task] : (int32_t)task;
+            }
+        }
+        if (src < 0 || src >= g.n) {
+            if (tid == 0) atomicOr(&p.st->err, kErrArg);
+            continue;
+        }
+        // An isolated target is unreachable; its bitmap bit is pre-set, so it
+        // must not reach the "target visited" test of the forward phase.
+        if (MODE == kModePair && g.rp[target + 1] == g.rp[target]) {
+            if (tid == 0 && p.p_len) p.p_len[task] = -1;
+            continue;
+        }
+
+        const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, src, target, c);
+        const int32_t nreached = s.lvl[Ld + 1];
+        if (tid == 0) {
+            c.reached += (unsigned long long)nreached;
+            c.tasks++;
+        }
+
+        if (MODE == kModeBC) {
+            backward<BLOCK>(p, sm, bm, s, g, Ld, p.bc + g.vbase, c);
+        } else if (MODE == kModeSSSP) {
+            const long long row = task * (long long)g.n;
+            for (int32_t i = tid; i < nreached; i += BLOCK) {
+                const int32_t v = s.list[i];
+                p.d_out[row + v] = s.d[v];
+                p.sigma_out[row + v] = s.sigma[v];
+            }
+        } else if (MODE == kModePair) {
+            if (wave_id() == 0) {
+                if (sm.flag)
+                    walk_path(p, bm, s, g, src, target, j, task);
+                else if (lane_id() == 0 && p.p_len)
+                    p.p_len[task] = -1;
+            }
+        } else if (MODE == kModeBFS) {
+            // eccentricity of src and the lowest id at that distance
+            const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
+            int32_t mn = 0x7fffffff;
+            for (int32_t i = lo + tid; i < hi; i += BLOCK) mn = min(mn, s.list[i]);
+            mn = wave_min(mn);
+            if (lane_id() == 0) atomicMin(&p.st->info[1], mn);
+            if (tid == 0) {
+                p.st->info[0] = Ld;
+                p.st->info[2] = nreached;
+            }
+        }
+        __syncthreads();
+        for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.list[i]] = 0ULL;
+        __syncthreads();
+    }
+
+    // counters: wave sums, one atomic per wave and counter
+    unsigned long long dag = wave_sum<unsigned long long>(c.dag);
+    if (lane_id() == 0) atomicAdd(&p.st->stat[kStDag], dag);
+    if (tid == 0) {
+        atomicAdd(&p.st->stat[kStSources], c.tasks);
+        atomicAdd(&p.st->stat[kStReached], c.reached);
+        atomicAdd(&p.st->stat[kStArcsFwd], c.arcs_fwd);
+        atomicAdd(&p.st->stat[kStArcsBwd], c.arcs_bwd);
+        atomicAdd(&p.st->stat[kStTd], c.td);
+        atomicAdd(&p.st->stat[kStBu], c.bu);
+        atomicAdd(&p.st->stat[kStArcsReached], c.arcs_reached);
+    }
+}
+
+template <int BLOCK, bool BMLDS, int MODE>
+static void launch_brandes(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Params &p) {
+    hipLaunchKernelGGL((k_brandes<BLOCK, BMLDS, MODE>), grid, block, lds, s, p);
+}
+
+template <int BLOCK, bool BMLDS, int MODE>
+static KernelRef ref() {
+    return KernelRef{(const void *)&k_brandes<BLOCK, BMLDS, MODE>, &launch_brandes<BLOCK, BMLDS, MODE>};
+}
+
+template <int MODE>
+static KernelRef ref_mode(int block, bool lds) {
+    switch (block) {
+        case 256: return lds ? ref<256, true, MODE>() : ref<256, false, MODE>();
+        case 512: return lds ? ref<512, true, MODE>() : ref<512, false, MODE>();
+        default: return lds ? ref<1024, true, MODE>() : ref<1024, false, MODE>();
+    }
+}
+
+KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
+    switch (mode) {
+        case kModeBC: return ref_mode<kModeBC>(block, bitmap_in_lds);
+        case kModeSSSP: return ref_mode<kModeSSSP>(block, bitmap_in_lds);
+        case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
+        default: return ref_mode<kModeBFS>(block, bitmap_in_lds);
+    }
+}
+
+// ---------------------------------------------------------- small kernels --
+
+__global__ void k_status_init(DevStatus *st) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        st->err = 0;
+        st->pad = 0;
+        st->head = 0ULL;
+    }
+    if (t < 8) {
+        st->stat[t] = 0ULL;
+        st->info[t] = (t == 1) ? 0x7fffffff : 0;
+    }
+}
+
+__global__ void k_validate(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, DevStatus *st) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int bad = 0;
+    if (tid == 0 && (rowptr[0] != 0 || (int64_t)rowptr[n] != m)) bad = 1;
+    for (long long i = tid; i < n; i += stride)
+        if (rowptr[i + 1] < rowptr[i]) bad = 1;
+    for (long long e = tid; e < m; e += stride) {
+        const int32_t c = colidx[e];
+        if (c < 0 || c >= n) bad = 1;
+    }
+    if (bad) atomicOr(&st->err, kErrGraph);
+}
+
+// Simple-graph checks; runs only after the structural checks passed.
+__global__ void k_validate_strict(const int32_t *rowptr, const int32_t *colidx, int32_t n, DevStatus *st) {
+    if (st->err & kErrGraph) return;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (long long u = tid; u < n; u += stride) {
+        const int32_t a0 = rowptr[u], a1 = rowptr[u + 1];
+        for (int32_t e = a0; e < a1; ++e) {
+            const int32_t v = colidx[e];
+            if (v == u || (e > a0 && colidx[e - 1] >= v)) { bad = 1; break; }
+            int32_t lo = rowptr[v], hi = rowptr[v + 1];
+            bool found = false;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                const int32_t x = colidx[mid];
+                if (x == (int32_t)u) { found = true; break; }
+                if (x < (int32_t)u) lo = mid + 1; else hi = mid;
+            }
+            if (!found) { bad = 1; break; }
+        }
+    }
+    if (bad) atomicOr(&st->err, kErrGraph);
+}
+
+__global__ void k_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso) {
+    const int32_t nw = (n + 31) >> 5;
+    const int32_t wi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (wi >= nw) return;
+    uint32_t x = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int32_t v = wi * 32 + b;
+        if (v < n && rowptr[v + 1] == rowptr[v]) x |= 1u << b;
+    }
+    iso[wi] = x;
+}
+
+template <typename T>
+__global__ void k_fill(T *p, T v, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_scale(double *p, double scale, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] *= scale;
+}
+
+__global__ void k_counts_to_bc(const uint32_t *cnt, double *bc, double scale, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        bc[i] = (double)cnt[i] * scale;
+}
+
+// key = (degree << 32) | (0xffffffff - id): the maximum is the highest
+// degree with the lowest id.
+__global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    unsigned long long best = 0ULL;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const unsigned long long dg = (unsigned long long)(rowptr[v + 1] - rowptr[v]);
+        const unsigned long long k = (dg << 32) | (0xffffffffULL - (unsigned long long)v);
+        best = k > best ? k : best;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long y = __shfl_xor(best, off, kWave);
+        best = y > best ? y : best;
+    }
+    if (lane_id() == 0) atomicMax(key, best);
+}
+
+// Connected components by minimum-label hooking with pointer jumping.
+__global__ void k_cc_init(int32_t *label, int32_t n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) label[v] = (int32_t)v;
+}
+
+__global__ void k_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    int ch = 0;
+    for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        const int32_t lu = label[u];
+        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+            const int32_t v = colidx[e];
+            const int32_t lv = label[v];
+            if (lu < lv) {
+                atomicMin(&label[lv], lu);
+                ch = 1;
+            }
+        }
+    }
+    if (ch) atomicOr(changed, 1);
+}
+
+__global__ void k_cc_compress(int32_t *label, int32_t n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        int32_t l = label[v];
+        while (label[l] != l) l = label[l];
+        label[v] = l;
+    }
+}
+
+__global__ void k_cc_sizes(const int32_t *label, int32_t n, int32_t *size) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) atomicAdd(&size[label[v]], 1);
+}
+
+__global__ void k_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const int32_t root0 = label[x0];
+    int32_t best = 0;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        if (label[v] == (int32_t)v && (int32_t)v != root0) best = max(best, size[v]);
+    if (best) atomicMax(out, best);
+}
+
+__global__ void k_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const unsigned long long j = (unsigned long long)(j0 + i);
+        const int32_t a = (int32_t)bounded(draw(seed, 1, j, 0), (unsigned long long)n);
+        int32_t b = (int32_t)bounded(draw(seed, 2, j, 0), (unsigned long long)(n - 1));
+        if (b >= a) b += 1;
+        uv[2 * i] = a;
+        uv[2 * i + 1] = b;
+    }
+}
+
+static inline unsigned grid_for(long long count, int block) {
+    long long g = (count + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+hipError_t launch_status_init(DevStatus *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t strict,
+                           DevStatus *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(m > n ? m : n, 256)), dim3(256), 0, s, rowptr, colidx, n, m, st);
+    if (strict) hipLaunchKernelGGL(k_validate_strict, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colidx, n, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso, hipStream_t s) {
+    const long long nw = ((long long)n + 31) / 32;
+    hipLaunchKernelGGL(k_iso_bitmap, dim3(grid_for(nw, 256)), dim3(256), 0, s, rowptr, n, iso);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, double v, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(count, 256)), dim3(256), 0, s, p, scale, count);
+    return hipGetLastError();
+}
+hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_counts_to_bc, dim3(grid_for(count, 256)), dim3(256), 0, s, counts, bc, scale, count);
+    return hipGetLastError();
+}
+hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s) {
+    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, n, key);
+    return hipGetLastError();
+}
+hipError_t launch_cc_init(int32_t *label, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n);
+    return hipGetLastError();
+}
+hipError_t launch_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_hook, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colidx, n, label, changed);
+    return hipGetLastError();
+}
+hipError_t launch_cc_compress(int32_t *label, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n);
+    return hipGetLastError();
+}
+hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n, size);
+    return hipGetLastError();
+}
+hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_other_max, dim3(grid_for(n, 256)), dim3(256), 0, s, label, size, n, x0, out);
+    return hipGetLastError();
+}
+hipError_t launch_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_list, dim3(grid_for(count, 256)), dim3(256), 0, s, seed, j0, count, n, uv);
+    return hipGetLastError();
+}
+
+}  // namespace nk

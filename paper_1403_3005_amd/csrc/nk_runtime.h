@@ -1,0 +1,101 @@
+// Host runtime shared by the C ABI (nk_api.hip) and the serving loop
+// (nk_server.hip): error reporting, device properties, the pooled scratch
+// allocator, tuning state and the persistent-kernel runner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nk_bc.h"
+#include "nk_kernels.h"
+
+namespace nk {
+
+nk_status fail(nk_status code, const char *fmt, ...);
+void clear_error();
+
+#define NK_HIP(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return ::nk::fail(NK_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevInfo {
+    int device;
+    int cus;
+    size_t lds_per_block;
+};
+nk_status dev_info(DevInfo *out);
+
+// Pooled device scratch.  Blocks return to the pool when the holder is
+// destroyed; the pool keeps them for later calls until nk_shutdown.
+class Scratch {
+public:
+    Scratch() = default;
+    ~Scratch();
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    // Returns NK_OK and a device pointer of at least `bytes` bytes (256-byte aligned).
+    nk_status get(size_t bytes, void **out);
+    template <typename T>
+    nk_status get(long long count, T **out) {
+        return get((size_t)(count > 0 ? count : 1) * sizeof(T), (void **)out);
+    }
+    void release_all();
+
+private:
+    std::vector<void *> held_;
+};
+void pool_clear();
+size_t pool_bytes_in_use();
+
+nk_tuning tuning_get();
+void tuning_set(const nk_tuning &t);
+
+// Per-thread statistics of the last call (nk_last_stats).
+void stats_record(const DevStatus &st, int grid, int block, bool lds, float kernel_ms);
+void stats_clear();
+
+// Launch configuration chosen for a persistent Brandes launch.
+struct LaunchPlan {
+    int mode;
+    int block;
+    bool lds;
+    int grid;
+    size_t dyn_lds;
+    long long stride;
+    long long bm_words;
+    KernelRef kernel;
+};
+
+// Picks block size, bitmap placement and grid for graphs of at most n_max
+// vertices and `ntasks` tasks.  max_slots > 0 caps the grid.
+nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan);
+
+// Allocates per-slot scratch for `plan`, clears the path counts, fills the
+// scratch fields of `p` and launches the persistent kernel on `s`,
+// recording HIP events around it when ev0/ev1 are non-null.
+nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1);
+
+// Copies the status block to the host, synchronises `s` and maps error bits
+// to a status code.
+nk_status finish(DevStatus *dst, DevStatus *host, hipStream_t s);
+
+nk_status map_err(int32_t err);
+
+// Per-thread pinned status buffer and timing events.
+DevStatus *host_status();
+nk_status thread_events(hipEvent_t *ev0, hipEvent_t *ev1);
+
+// Graph argument checks shared by every entry point.
+nk_status check_graph_args(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m);
+
+// Vertex-diameter bound (see nk_vd_bound); runs synchronously on `s`.
+nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
+                        hipStream_t s);
+
+}  // namespace nk

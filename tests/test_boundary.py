@@ -1,0 +1,76 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/nk_bc.h declares; host-side argument checks and the sample
+size formula need no device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nk_bc.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_core_calls():
+    names = declared()
+    for need in ["nk_bc_exact", "nk_bc_sources", "nk_bc_pair_sample", "nk_sssp_counts", "nk_bc_exact_batched",
+                 "nk_last_error", "nk_vd_bound"]:
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1403_3005_amd as nk
+    lib = nk.load()
+    raw = ctypes.CDLL(nk._lib.LIB_PATH)
+    for name in declared():
+        assert hasattr(raw, name), name
+    assert nk.nk_version().startswith("nkbc")
+
+
+def test_binding_covers_header():
+    import paper_1403_3005_amd._lib as L
+    assert set(L.EXPORTS) == set(declared())
+
+
+def test_host_argument_checks():
+    import paper_1403_3005_amd as nk
+    lib = nk.load()
+    vp = ctypes.c_void_p
+    assert lib.nk_bc_exact(vp(0), vp(0), -1, 0, vp(0), vp(0)) == nk.NK_E_INVALID_ARG
+    assert b"negative" in lib.nk_last_error()
+    assert lib.nk_bc_exact(vp(0), vp(0), 0, 0, vp(0), vp(0)) == nk.NK_OK  # n = 0: nothing to do
+    assert lib.nk_bc_exact(vp(0), vp(0), 5, 0, vp(0), vp(0)) == nk.NK_E_INVALID_ARG  # rowptr NULL
+    assert lib.nk_bc_sources(vp(8), vp(8), 5, 10, vp(0), 3, 1.0, vp(8), vp(0)) == nk.NK_E_INVALID_ARG
+    assert lib.nk_bc_exact(vp(8), vp(8), 5, 2 ** 31, vp(8), vp(0)) == nk.NK_E_INVALID_ARG
+    r = ctypes.c_int64(0)
+    v = ctypes.c_int32(0)
+    assert lib.nk_bc_pair_sample(vp(8), vp(8), 5, 10, 0.0, 0.1, 1, vp(8), vp(0), ctypes.byref(r), ctypes.byref(v),
+                                 vp(0)) == nk.NK_E_INVALID_ARG
+    assert lib.nk_bc_pair_sample(vp(8), vp(8), 5, 10, 0.1, 1.0, 1, vp(8), vp(0), ctypes.byref(r), ctypes.byref(v),
+                                 vp(0)) == nk.NK_E_INVALID_ARG
+    assert lib.nk_bc_exact_batched(-1, None, None, vp(0), vp(0), vp(0), vp(0)) == nk.NK_E_INVALID_ARG
+
+
+def test_tuning_roundtrip():
+    import paper_1403_3005_amd as nk
+    old = nk.nk_get_tuning()
+    nk.nk_set_tuning(block=512, bu_ratio=2.0, wg_per_cu=1, flags=1)
+    assert nk.nk_get_tuning() == {"block": 512, "bu_ratio": 2.0, "wg_per_cu": 1, "flags": 1}
+    with pytest.raises(nk.NkError):
+        nk.nk_set_tuning(block=300)
+    nk.nk_set_tuning(**old)
+
+
+@pytest.mark.parametrize("eps,delta,vd", [(0.01, 0.1, 6), (0.01, 0.1, 10), (0.05, 0.1, 8), (0.02, 0.05, 40),
+                                          (0.3, 0.5, 1), (0.01, 0.1, 1000000)])
+def test_sample_size_matches_oracle(eps, delta, vd):
+    import oracle
+    import paper_1403_3005_amd as nk
+    assert nk.nk_rk_sample_size(eps, delta, vd) == oracle.rk_sample_size(eps, delta, vd)
+    assert nk.nk_rk_sample_size(1.5, delta, vd) == -1

@@ -1,0 +1,333 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  d and sigma bit-exact; scores within the tolerance in
+tests/nkutil.py."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_1403_3005_amd as nk
+from nkutil import assert_scores_close, ivec, upload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bruteforce_small.json")
+
+
+@pytest.fixture(autouse=True)
+def _default_tuning():
+    nk.nk_set_tuning(block=0, bu_ratio=1.0, wg_per_cu=0, flags=0)
+    yield
+    nk.nk_set_tuning(block=0, bu_ratio=1.0, wg_per_cu=0, flags=0)
+
+
+def _exact(g):
+    rp, ci = upload(g)
+    return nk.nk_bc_exact(rp, ci).cpu().numpy()
+
+
+def _sssp_check(g, sources):
+    rp, ci = upload(g)
+    d, s = nk.nk_sssp_counts(rp, ci, ivec(sources))
+    d = d.cpu().numpy()
+    s = s.cpu().numpy().view(np.uint64)
+    for i, src in enumerate(sources):
+        od, os_ = oracle.sssp_counts(g.rowptr, g.colidx, int(src))
+        assert np.array_equal(d[i], od), (g.name, src)
+        assert np.array_equal(s[i], os_), (g.name, src)
+
+
+def test_golden_bruteforce():
+    with open(GOLDEN) as f:
+        cases = json.load(f)
+    for case in cases:
+        g = gg.Graph(case["n"], np.array(case["rowptr"], dtype=np.int32), np.array(case["colidx"], dtype=np.int32))
+        got = _exact(g)
+        for v, frac in enumerate(case["bc"]):
+            exact = Fraction(frac)
+            assert abs(Fraction(got[v]) - exact) <= Fraction(1, 10 ** 12) * max(1, abs(exact)), (case["name"], v)
+        rp, ci = upload(g)
+        d, s = nk.nk_sssp_counts(rp, ci, ivec(range(g.n)))
+        assert d.cpu().numpy().tolist() == case["d"]
+        assert s.cpu().numpy().view(np.uint64).astype(object).tolist() == case["sigma"]
+
+
+FAMILIES = [
+    lambda: gg.path(1), lambda: gg.path(2), lambda: gg.path(700), lambda: gg.star(3000), lambda: gg.cycle(501),
+    lambda: gg.cycle(64), lambda: gg.complete(40), lambda: gg.complete_bipartite(7, 300), lambda: gg.grid(30, 40),
+    lambda: gg.hypercube(10), lambda: gg.diamond_chain(40), lambda: gg.random_tree(3000, 9),
+    lambda: gg.disjoint_union([gg.grid(6, 7), gg.star(50), gg.path(1), gg.cycle(9), gg.complete(5)]),
+]
+
+
+@pytest.mark.parametrize("make", FAMILIES)
+def test_exact_families(make):
+    g = make()
+    assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), g.name)
+
+
+RANDOM = [
+    lambda: gg.erdos_renyi(1500, 4000, 21),
+    lambda: gg.erdos_renyi(3000, 2500, 22),  # many components
+    lambda: gg.barabasi_albert(4000, 4, 23),
+    lambda: gg.rmat(12, 16, 24),
+    lambda: gg.chung_lu(5000, 2.5, 20.0, 25),
+]
+
+
+@pytest.mark.parametrize("make", RANDOM)
+def test_exact_random(make):
+    g = make()
+    assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), g.name)
+
+
+@pytest.mark.parametrize("make", RANDOM + FAMILIES[2:6])
+def test_sssp_bit_exact(make):
+    g = make()
+    srcs = sorted(set([0, g.n - 1, g.n // 2, g.n // 3, int(np.argmax(g.degrees()))]))
+    _sssp_check(g, srcs)
+
+
+def test_exact_er2000_full():
+    """The exact all-sources workload: G(2000, 10000), seed 1."""
+    g = gg.workload_er2000()
+    assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), "er2000")
+    st = nk.nk_last_stats()
+    assert st["sources"] == 2000
+    _sssp_check(g, list(range(0, 2000, 97)))
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+@pytest.mark.parametrize("bu_ratio", [0.0, 1.0, 1e9])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_launch_variants(block, bu_ratio, flags):
+    """Every block size, direction policy (never / default / always bottom-up
+    after the first level) and bitmap placement gives the same result."""
+    nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, wg_per_cu=0, flags=flags)
+    g = gg.rmat(11, 8, 31)
+    src = gg.sample_sources(g.n, 64, 32)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources(rp, ci, ivec(src), g.n / 64).cpu().numpy()
+    st = nk.nk_last_stats()
+    assert st["block"] == block and st["bitmap_lds"] == (0 if flags else 1)
+    if bu_ratio == 0.0:
+        assert st["levels_bu"] == 0
+    if bu_ratio == 1e9:
+        assert st["levels_bu"] > 0
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, g.n / 64), "variant")
+    d, s = nk.nk_sssp_counts(rp, ci, ivec(src[:4]))
+    for i in range(4):
+        od, os_ = oracle.sssp_counts(g.rowptr, g.colidx, int(src[i]))
+        assert np.array_equal(d[i].cpu().numpy(), od)
+        assert np.array_equal(s[i].cpu().numpy().view(np.uint64), os_)
+
+
+def test_work_counters_match_oracle():
+    nk.nk_set_tuning(block=0, bu_ratio=0.0)  # top-down only: forward arcs = arcs of reached vertices
+    g = gg.barabasi_albert(3000, 3, 41)
+    src = gg.sample_sources(g.n, 100, 42)
+    rp, ci = upload(g)
+    nk.nk_bc_sources(rp, ci, ivec(src), 1.0)
+    st = nk.nk_last_stats()
+    reached, arcs, dag, depth = oracle.work_counts(g.rowptr, g.colidx, src)
+    assert st["sources"] == 100
+    assert st["reached"] == reached
+    assert st["arcs_fwd"] == arcs
+    assert st["arcs_reached"] == arcs
+    assert st["dag_arcs"] == dag
+    assert st["levels_td"] == depth + 100  # one extra (empty) expansion per source
+
+
+def test_sources_forms_and_duplicates():
+    g = gg.barabasi_albert(2000, 2, 51)
+    rp, ci = upload(g)
+    src = [5, 9, 5, 1999, 0]
+    got = nk.nk_bc_sources(rp, ci, ivec(src), 0.25).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, 0.25), "dups")
+    allsrc = nk.nk_bc_sources(rp, ci, ivec(range(g.n)), 1.0).cpu().numpy()
+    assert_scores_close(allsrc, _exact(g), "all-vs-exact")
+    zero = nk.nk_bc_sources(rp, ci, torch.zeros(0, dtype=torch.int32, device="cuda:0"), 3.0).cpu().numpy()
+    assert np.array_equal(zero, np.zeros(g.n))
+
+
+def test_rmat14_sampled_sources():
+    g = gg.rmat(14, 16, 2)
+    src = gg.sample_sources(g.n, 512, 2)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources(rp, ci, ivec(src), g.n / 512).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, g.n / 512), "rmat14")
+
+
+def test_edge_cases():
+    # isolated vertices only
+    g = gg.Graph(50, np.zeros(51, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    assert np.array_equal(_exact(g), np.zeros(50))
+    # a single vertex
+    g1 = gg.Graph(1, np.zeros(2, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    assert np.array_equal(_exact(g1), np.zeros(1))
+    # empty graph
+    g0 = gg.Graph(0, np.zeros(1, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    rp, ci = upload(g0)
+    assert nk.nk_bc_exact(rp, ci).numel() == 0
+
+
+def test_invalid_graph_and_args():
+    g = gg.cycle(100)
+    bad = g.colidx.copy()
+    bad[7] = 100
+    rp = torch.from_numpy(g.rowptr).cuda()
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_exact(rp, torch.from_numpy(bad).cuda())
+    assert e.value.code == nk.NK_E_INVALID_GRAPH
+    badrp = g.rowptr.copy()
+    badrp[10] = badrp[11] + 1
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_exact(torch.from_numpy(badrp).cuda(), torch.from_numpy(g.colidx).cuda())
+    assert e.value.code == nk.NK_E_INVALID_GRAPH
+    rp, ci = upload(g)
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_sources(rp, ci, ivec([3, 100]), 1.0)
+    assert e.value.code == nk.NK_E_INVALID_ARG
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_validate_graph(rp, torch.from_numpy(np.ascontiguousarray(g.colidx[::-1])).cuda(), strict=True)
+    assert e.value.code == nk.NK_E_INVALID_GRAPH
+    nk.nk_validate_graph(rp, ci, strict=True)
+    # the library still works after errors
+    assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), "after-errors")
+
+
+def test_sigma_overflow_boundary():
+    ok = gg.diamond_chain(63)
+    assert_scores_close(_exact(ok), oracle.bc_exact(ok.rowptr, ok.colidx), "diamonds63")
+    _sssp_check(ok, [0, 3 * 63])
+    bad = gg.diamond_chain(64)
+    rp, ci = upload(bad)
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_exact(rp, ci)
+    assert e.value.code == nk.NK_E_SIGMA_OVERFLOW
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_sssp_counts(rp, ci, ivec([0]))
+    assert e.value.code == nk.NK_E_SIGMA_OVERFLOW
+    # sources whose counts stay below 2^64 succeed on the same graph
+    got = nk.nk_bc_sources(rp, ci, ivec([96, 97]), 1.0).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources(bad.rowptr, bad.colidx, [96, 97]), "diamonds64-mid")
+    for rows, fits in [(34, True), (35, False)]:
+        grid = gg.grid(rows, rows)
+        rp, ci = upload(grid)
+        if fits:
+            _sssp_check(grid, [0])
+        else:
+            with pytest.raises(nk.NkError) as e:
+                nk.nk_bc_sources(rp, ci, ivec([0]), 1.0)
+            assert e.value.code == nk.NK_E_SIGMA_OVERFLOW
+
+
+def test_repeat_calls_deterministic_integers():
+    g = gg.rmat(12, 16, 61)
+    rp, ci = upload(g)
+    src = ivec(gg.sample_sources(g.n, 256, 62))
+    a = nk.nk_bc_sources(rp, ci, src, 1.0).cpu().numpy()
+    b = nk.nk_bc_sources(rp, ci, src, 1.0).cpu().numpy()
+    assert_scores_close(a, b, "repeat")
+    d1, s1 = nk.nk_sssp_counts(rp, ci, src[:8])
+    d2, s2 = nk.nk_sssp_counts(rp, ci, src[:8])
+    assert torch.equal(d1, d2) and torch.equal(s1, s2)
+
+
+# ----------------------------------------------------------- pair sampling --
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.star(40), lambda: gg.path(30), lambda: gg.grid(12, 15), lambda: gg.erdos_renyi(800, 1200, 71),
+    lambda: gg.barabasi_albert(1500, 2, 72), lambda: gg.disjoint_union([gg.star(30), gg.path(25), gg.cycle(7)]),
+    lambda: gg.chung_lu(20000, 2.5, 20.0, 73),
+])
+def test_vd_bound_matches_oracle(make):
+    g = make()
+    rp, ci = upload(g)
+    assert nk.nk_vd_bound(rp, ci) == oracle.vd_bound(g.rowptr, g.colidx)
+
+
+@pytest.mark.parametrize("make,r,seed", [
+    (lambda: gg.grid(8, 9), 3000, 5), (lambda: gg.erdos_renyi(600, 1500, 81), 2000, 6),
+    (lambda: gg.barabasi_albert(2000, 3, 82), 1500, 7), (lambda: gg.rmat(11, 16, 83), 1000, 8),
+    (lambda: gg.hypercube(9), 800, 9),
+])
+def test_pair_counts_bit_exact(make, r, seed):
+    g = make()
+    rp, ci = upload(g)
+    got = nk.nk_pair_counts(rp, ci, r, seed).cpu().numpy().view(np.uint32)
+    ref = oracle.pair_counts(g.rowptr, g.colidx, r, seed)
+    assert np.array_equal(got, ref)
+
+
+def test_sample_paths_bit_exact():
+    g = gg.barabasi_albert(3000, 2, 91)
+    rp, ci = upload(g)
+    uv, ln, path = nk.nk_sample_paths(rp, ci, 11, 100, 64, 32)
+    uv, ln, path = uv.cpu().numpy(), ln.cpu().numpy(), path.cpu().numpy()
+    for i in range(64):
+        u, v, interior = oracle.sample_path(g.rowptr, g.colidx, 11, 100 + i)
+        assert (uv[i, 0], uv[i, 1]) == (u, v)
+        if interior is None:
+            assert ln[i] == -1
+        else:
+            assert ln[i] == len(interior)
+            assert path[i, :ln[i]].tolist() == interior
+
+
+@pytest.mark.parametrize("make,eps,seed", [
+    (lambda: gg.barabasi_albert(400, 2, 101), 0.05, 3), (lambda: gg.grid(10, 10), 0.08, 4),
+    (lambda: gg.disjoint_union([gg.erdos_renyi(300, 500, 102), gg.path(40)]), 0.06, 5),
+])
+def test_pair_sample_matches_oracle(make, eps, seed):
+    g = make()
+    rp, ci = upload(g)
+    bc, cnt, r, vd = nk.nk_bc_pair_sample(rp, ci, eps, 0.1, seed)
+    obc, ocnt, orr, ovd = oracle.pair_sample(g.rowptr, g.colidx, eps, 0.1, seed)
+    assert (r, vd) == (orr, ovd)
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint32), ocnt)
+    assert_scores_close(bc.cpu().numpy(), obc, "pair-bc")
+
+
+# ----------------------------------------------------------------- batched --
+
+def _batched_inputs(graphs):
+    vtx = np.zeros(len(graphs) + 1, dtype=np.int64)
+    arc = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vtx[i + 1] = vtx[i] + g.n
+        arc[i + 1] = arc[i] + g.m
+    rp = np.concatenate([g.rowptr for g in graphs]).astype(np.int32)
+    ci = np.concatenate([g.colidx for g in graphs]).astype(np.int32) if arc[-1] else np.zeros(0, np.int32)
+    return vtx, arc, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+
+
+def test_batched_small_mixed():
+    sizes = gg.batched_sizes(24, 50, 3000, 111)
+    graphs = []
+    for i, n in enumerate(sizes):
+        graphs.append(gg.erdos_renyi(n, 4 * n, 200 + i) if i % 2 == 0 else gg.barabasi_albert(n, 4, 200 + i))
+    graphs.insert(5, gg.Graph(1, np.zeros(2, dtype=np.int32), np.zeros(0, dtype=np.int32)))
+    graphs.insert(9, gg.path(2))
+    vtx, arc, rp, ci = _batched_inputs(graphs)
+    got = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
+    for i, g in enumerate(graphs):
+        assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx), f"graph {i}")
+    assert nk.nk_last_stats()["sources"] == int(vtx[-1])
+
+
+def test_pair_isolated_targets():
+    """Pairs whose target (or source) is an isolated vertex add nothing."""
+    g = gg.disjoint_union([gg.star(20), gg.path(1), gg.path(1), gg.path(1), gg.cycle(6)])
+    rp, ci = upload(g)
+    got = nk.nk_pair_counts(rp, ci, 5000, 12).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, oracle.pair_counts(g.rowptr, g.colidx, 5000, 12))
+    uv, ln, path = nk.nk_sample_paths(rp, ci, 12, 0, 200, 8)
+    for i in range(200):
+        u, v, interior = oracle.sample_path(g.rowptr, g.colidx, 12, i)
+        assert ln[i].item() == (-1 if interior is None else len(interior))
