@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
@@ -97,6 +99,15 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        # one plain copy kernel: reads 1 GiB and writes 1 GiB of HBM
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4}), flush=True)
+        return
     print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
     g, src = gg.workload_rmat20(2)
     n, m = g.n, g.m
@@ -160,6 +171,12 @@ def main():
             "block": stats["block"],
             "levels_td": stats["levels_td"],
             "levels_bu": stats["levels_bu"],
+            "reached": stats["reached"],
+            "arcs_reached": stats["arcs_reached"],
+            "arcs_scanned_fwd": stats["arcs_fwd"],
+            "arcs_scanned_bwd": stats["arcs_bwd"],
+            "dag_arcs": stats["dag_arcs"],
+            "levels_bw_push": stats["levels_bw_push"],
         },
         "roofline": {
             "bound": "hbm",

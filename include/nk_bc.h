@@ -197,7 +197,7 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
 
 /*
  * Statistics of the calling thread's last nk_bc_exact / nk_bc_sources /
- * nk_bc_exact_batched / pair-sampling call (HOST out[12]):
+ * nk_bc_exact_batched / pair-sampling call (HOST out[16]):
  *   out[0] sources (or samples) processed     out[1] vertices reached
  *   out[2] arcs scanned, forward              out[3] arcs scanned, backward
  *   out[4] shortest-path DAG arcs             out[5] levels run top-down
@@ -205,19 +205,25 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
  *   out[8] main kernel time in microseconds (HIP events on the call's stream)
  *   out[9] threads per workgroup              out[10] 1 if the visited bitmap sat in LDS
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
+ *   out[12] dependency-sweep levels run by push   out[13..15] reserved
  */
 nk_status nk_last_stats(int64_t *out);
 
 /*
- * Tuning of the per-source kernel (a6: direction switch and tiling).
+ * Tuning of the per-source kernel: direction switches and tiling.
  *   block      threads per workgroup: 256, 512 or 1024 (0 = automatic);
  *   bu_ratio   run a level bottom-up when the arcs of still-unvisited
  *              vertices are below bu_ratio x the frontier's arcs
- *              (0 = never bottom-up);
+ *              (0 = never bottom-up; default 16);
  *   wg_per_cu  resident workgroups per compute unit requested (0 = as many
  *              as fit);
  *   flags      bit 0: keep the visited bitmap in global memory even when it
- *              would fit in LDS (for testing that placement).
+ *              would fit in LDS (for testing that placement);
+ *              bit 1: run single graphs under their own vertex ids instead
+ *              of the internal degree-descending relabelling;
+ *   bw_ratio   in the dependency sweep, handle level l by pushing from level
+ *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
+ *              of level l (0 = always pull; default 0.1).
  * nk_set_tuning applies to later calls from every thread.
  */
 typedef struct {
@@ -225,6 +231,8 @@ typedef struct {
     float bu_ratio;
     int32_t wg_per_cu;
     int32_t flags;
+    float bw_ratio;
+    int32_t reserved[3];
 } nk_tuning;
 
 nk_status nk_set_tuning(const nk_tuning *t);

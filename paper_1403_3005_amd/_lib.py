@@ -45,7 +45,7 @@ class NkError(RuntimeError):
 
 class NkTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("bu_ratio", ctypes.c_float), ("wg_per_cu", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("bw_ratio", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 def load():
@@ -219,21 +219,23 @@ def nk_bc_exact_batched(vtx_off, arc_off, rowptr_cat, colidx_cat, stream=None):
 
 
 STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",
-             "kernel_us", "block", "bitmap_lds", "arcs_reached"]
+             "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "reserved13", "reserved14",
+             "reserved15"]
 
 
 def nk_last_stats() -> dict:
-    out = (ctypes.c_int64 * 12)()
+    out = (ctypes.c_int64 * 16)()
     _check(load().nk_last_stats(out))
     return {k: int(v) for k, v in zip(STAT_KEYS, out)}
 
 
-def nk_set_tuning(block: int = 0, bu_ratio: float = 1.0, wg_per_cu: int = 0, flags: int = 0):
-    t = NkTuning(block, bu_ratio, wg_per_cu, flags)
+def nk_set_tuning(block: int = 0, bu_ratio: float = 16.0, wg_per_cu: int = 0, flags: int = 0, bw_ratio: float = 0.1):
+    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio)
     _check(load().nk_set_tuning(ctypes.byref(t)))
 
 
 def nk_get_tuning() -> dict:
     t = NkTuning()
     _check(load().nk_get_tuning(ctypes.byref(t)))
-    return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags}
+    return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
+            "bw_ratio": t.bw_ratio}

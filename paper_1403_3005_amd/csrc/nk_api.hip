@@ -18,7 +18,7 @@ namespace nk {
 // ------------------------------------------------------------------ errors --
 
 static thread_local std::string t_err;
-static thread_local int64_t t_stats[12];
+static thread_local int64_t t_stats[16];
 
 nk_status fail(nk_status code, const char *fmt, ...) {
     char buf[512];
@@ -166,7 +166,7 @@ size_t pool_bytes_in_use() {
 // ------------------------------------------------------------------ tuning --
 
 static std::mutex g_tune_mu;
-static nk_tuning g_tune = {0, 1.0f, 0, 0};
+static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, {0, 0, 0}};
 
 nk_tuning tuning_get() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -195,6 +195,8 @@ void stats_record(const DevStatus &st, int grid, int block, bool lds, float kern
     t_stats[9] = block;
     t_stats[10] = lds ? 1 : 0;
     t_stats[11] = (int64_t)st.stat[kStArcsReached];
+    t_stats[12] = (int64_t)st.stat[kStBwPush];
+    t_stats[13] = t_stats[14] = t_stats[15] = 0;
 }
 
 static thread_local DevStatus *t_host_status = nullptr;
@@ -292,9 +294,12 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     const long long cells = slots * plan.stride;
     nk_status st;
     if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
-    if ((st = scr.get(cells, &p.coef)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.dacc)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.d)) != NK_OK) return st;
-    if ((st = scr.get(cells, &p.list)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.ld)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.cand)) != NK_OK) return st;
     p.bmg = nullptr;
@@ -303,7 +308,9 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
     p.bu_ratio = tuning_get().bu_ratio;
+    p.bw_ratio = tuning_get().bw_ratio;
     NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
+    NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
     if (ev0) NK_HIP(hipEventRecord(ev0, s));
     plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
     NK_HIP(hipGetLastError());
@@ -435,7 +442,8 @@ nk_status nk_set_tuning(const nk_tuning *t) {
     if (!t) return fail(NK_E_INVALID_ARG, "tuning is NULL");
     if (t->block != 0 && t->block != 256 && t->block != 512 && t->block != 1024)
         return fail(NK_E_INVALID_ARG, "block must be 0, 256, 512 or 1024");
-    if (!(t->bu_ratio >= 0.0f) || t->wg_per_cu < 0) return fail(NK_E_INVALID_ARG, "bad tuning values");
+    if (!(t->bu_ratio >= 0.0f) || !(t->bw_ratio >= 0.0f) || t->wg_per_cu < 0)
+        return fail(NK_E_INVALID_ARG, "bad tuning values");
     tuning_set(*t);
     return NK_OK;
 }
@@ -462,6 +470,18 @@ nk_status nk_validate_graph(const int32_t *rowptr, const int32_t *colidx, int32_
     return finish(dst, h, s);
 }
 
+// The graph a single-graph call runs on: degree-relabelled unless tuning
+// flag bit 1 is set or the graph is tiny.
+static nk_status prepare_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, DevStatus *dst,
+                               Scratch &scr, hipStream_t s, Relabeled *g) {
+    g->rowptr = rowptr;
+    g->colidx = colidx;
+    g->perm = nullptr;
+    g->inv = nullptr;
+    if ((tuning_get().flags & 2) || n < 256) return NK_OK;
+    return relabel_graph(rowptr, colidx, n, m, dst, scr, s, g);
+}
+
 // Shared body of nk_bc_exact / nk_bc_sources.
 static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
                                  const int32_t *sources, long long k, double scale, double *bc, void *stream) {
@@ -485,26 +505,43 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     NK_HIP(launch_status_init(dst, s));
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
     NK_HIP(launch_fill_f64(bc, 0.0, n, s));
-    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
     LaunchPlan plan = {};
     float ms = 0.0f;
     if (k > 0) {
+        Relabeled g;
+        if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
+        const int32_t *src = sources;
+        double *acc = bc;
+        if (g.perm) {
+            if (sources) {
+                int32_t *mapped;
+                if ((st = scr.get(k, &mapped)) != NK_OK) return st;
+                NK_HIP(launch_map_sources(sources, (int32_t)k, g.perm, n, mapped, s));
+                src = mapped;
+            }
+            if ((st = scr.get(n, &acc)) != NK_OK) return st;
+            NK_HIP(launch_fill_f64(acc, 0.0, n, s));
+        }
         if ((st = plan_launch(kModeBC, n, k, 0, &plan)) != NK_OK) return st;
         Params p;
         memset(&p, 0, sizeof(p));
-        p.rowptr = rowptr;
-        p.colidx = colidx;
+        p.rowptr = g.rowptr;
+        p.colidx = g.colidx;
         p.n = n;
         p.m = (int32_t)m;
         p.ntasks = k;
-        p.sources = sources;
-        p.bc = bc;
+        p.sources = src;
+        p.bc = acc;
         p.iso = iso;
         p.st = dst;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
-        if (scale != 1.0) NK_HIP(launch_scale_f64(bc, scale, n, s));
+        if (g.perm)
+            NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
+        else if (scale != 1.0)
+            NK_HIP(launch_scale_f64(bc, scale, n, s));
         st = finish(dst, h, s);
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     } else {
@@ -547,21 +584,31 @@ nk_status nk_sssp_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n
     if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
     NK_HIP(launch_status_init(dst, s));
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
-    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    Relabeled g;
+    if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+    NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
+    const int32_t *src = sources;
+    if (g.perm) {
+        int32_t *mapped;
+        if ((st = scr.get(k, &mapped)) != NK_OK) return st;
+        NK_HIP(launch_map_sources(sources, k, g.perm, n, mapped, s));
+        src = mapped;
+    }
     NK_HIP(launch_fill_i32(d, -1, (long long)k * n, s));
     NK_HIP(launch_fill_u64((unsigned long long *)sigma, 0ULL, (long long)k * n, s));
     LaunchPlan plan;
     if ((st = plan_launch(kModeSSSP, n, k, 0, &plan)) != NK_OK) return st;
     Params p;
     memset(&p, 0, sizeof(p));
-    p.rowptr = rowptr;
-    p.colidx = colidx;
+    p.rowptr = g.rowptr;
+    p.colidx = g.colidx;
     p.n = n;
     p.m = (int32_t)m;
     p.ntasks = k;
-    p.sources = sources;
+    p.sources = src;
     p.d_out = d;
     p.sigma_out = (unsigned long long *)sigma;
+    p.inv = g.inv;
     p.iso = iso;
     p.st = dst;
     if ((st = launch_persistent(plan, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
@@ -590,7 +637,8 @@ int64_t nk_rk_sample_size(double eps, double delta, int32_t vd) {
     return (int64_t)ceil(rr);
 }
 
-// Runs samples j0 .. j0+count-1 in pair mode.
+// Runs samples j0 .. j0+count-1 in pair mode.  counts (original ids) is
+// accumulated, not cleared.
 static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, long long count,
                           unsigned long long seed, long long j0, uint32_t *counts, int32_t *uv, int32_t *len,
                           int32_t *path, int32_t maxlen, DevStatus *dst, Scratch &scr, hipStream_t s,
@@ -599,26 +647,36 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     uint32_t *iso;
     const long long words = ((long long)n + 31) / 32;
     if ((st = scr.get(words, &iso)) != NK_OK) return st;
-    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
+    Relabeled g;
+    if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+    NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
+    uint32_t *cnt = counts;
+    if (counts && g.perm) {
+        if ((st = scr.get(n, &cnt)) != NK_OK) return st;
+        NK_HIP(launch_fill_u32(cnt, 0u, n, s));
+    }
     LaunchPlan plan;
     if ((st = plan_launch(kModePair, n, count, 0, &plan)) != NK_OK) return st;
     Params p;
     memset(&p, 0, sizeof(p));
-    p.rowptr = rowptr;
-    p.colidx = colidx;
+    p.rowptr = g.rowptr;
+    p.colidx = g.colidx;
     p.n = n;
     p.m = (int32_t)m;
     p.ntasks = count;
     p.seed = seed;
     p.j0 = j0;
-    p.counts = counts;
+    p.counts = cnt;
     p.p_uv = uv;
     p.p_len = len;
     p.p_path = path;
     p.maxlen = maxlen;
+    p.perm = g.perm;
+    p.inv = g.inv;
     p.iso = iso;
     p.st = dst;
     if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+    if (counts && g.perm) NK_HIP(launch_gather_u32(cnt, g.perm, n, counts, s));
     *plan_out = plan;
     return NK_OK;
 }

@@ -28,11 +28,14 @@ struct DevStatus {
     int32_t err;
     int32_t pad;
     unsigned long long head;
-    unsigned long long stat[8];
-    int32_t info[8];
+    unsigned long long stat[12];
+    int32_t info[8];   // BFS mode: eccentricity, lowest far vertex, reached count
 };
 
-enum StatIdx { kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached };
+enum StatIdx {
+    kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached, kStBwPush,
+    kNumStats = 12
+};
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }

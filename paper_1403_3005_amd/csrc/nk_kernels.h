@@ -46,11 +46,18 @@ struct Params {
     int32_t *p_path;
     unsigned long long seed;
     long long j0;
+    // relabelling (degree order): perm maps original -> internal ids, inv
+    // internal -> original; both NULL when the graph runs as given
+    const int32_t *perm;
+    const int32_t *inv;
     // scratch
     unsigned long long *sigma;
-    double *coef;
+    double *dacc;
+    int32_t *ldeg;
     int32_t *d;
-    int32_t *list;
+    int32_t *lv;
+    int32_t *la;
+    int32_t *ld;
     int32_t *lvl;
     int32_t *cand;
     uint32_t *bmg;             // global bitmaps (when not in LDS)
@@ -58,7 +65,7 @@ struct Params {
     long long stride;          // per-slot elements of the n-sized arrays
     long long bm_words;        // per-slot words of a global bitmap
     float bu_ratio;
-    int32_t pad1;
+    float bw_ratio;
     DevStatus *st;
 };
 
@@ -89,7 +96,13 @@ hipError_t launch_cc_compress(int32_t *label, int32_t n, hipStream_t s);
 hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipStream_t s);
 hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
                                hipStream_t s);
-hipError_t launch_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv,
-                            hipStream_t s);
+
+// Degree-descending relabelling of a single graph (nk_relabel.hip).
+struct Relabeled {
+    const int32_t *rowptr;  // CSR in internal ids (the input when not relabelled)
+    const int32_t *colidx;
+    const int32_t *perm;    // original -> internal, or NULL
+    const int32_t *inv;     // internal -> original, or NULL
+};
 
 }  // namespace nk

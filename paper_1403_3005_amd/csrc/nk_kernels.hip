@@ -16,15 +16,18 @@
 //             exit because every frontier neighbour contributes).  New
 //             vertices are compacted into the next level list with a wave
 //             ballot and one LDS atomic per wave.  The concatenated level
-//             lists are the visit order S of Brandes' algorithm.
+//             lists are the visit order S of Brandes' algorithm; each entry
+//             carries the vertex, its first arc and its degree so later
+//             passes read adjacency bounds sequentially.
 //
 //   backward  for levels from deepest to 1, every vertex v of the level
 //             pulls over its neighbours w one level deeper:
 //                 delta_v = sigma_v * sum_w (1 + delta_w) / sigma_w,
-//             stores coef_v = (1 + delta_v) / sigma_v for the level above
-//             and adds delta_v to bc[v] (FP64 atomic add).  This is the
-//             dependency recursion of Brandes' algorithm rearranged as a
-//             pull, so no vertex is written by two threads.
+//             and replaces sigma_v in place by coef_v = (1 + delta_v) /
+//             sigma_v (the only value the level above reads), then adds
+//             delta_v to bc[v] (FP64 atomic add).  This is the dependency
+//             recursion of Brandes' algorithm rearranged as a pull, so no
+//             vertex is written by two threads.
 //
 // Visited state lives in one bitmap (LDS when it fits, else a per-slot
 // global bitmap).  Isolated vertices start marked.  During the forward phase
@@ -36,9 +39,11 @@
 //
 // Work inside a level is balanced over arcs, not vertices: a tile of up to
 // BLOCK listed vertices is staged in LDS with an exclusive prefix sum of
-// degrees, and each thread takes CHUNK consecutive arcs of the tile (one
+// degrees, and each thread takes kChunk consecutive arcs of the tile (one
 // binary search, then a forward walk), so hubs with 10^5 arcs and leaves
-// share the same loop and colidx reads stay contiguous per wave.
+// share the same loop.  Each thread first issues the column loads of its
+// whole chunk, then the bitmap tests, then the path-count atomics or loads,
+// so several global accesses per lane are in flight at once.
 #include "nk_kernels.h"
 
 namespace nk {
@@ -54,16 +59,19 @@ struct GView {
 };
 
 struct Scr {
-    unsigned long long *sigma;
-    double *coef;
+    unsigned long long *sigma;  // path counts; coef bits during the backward phase
+    double *dacc;               // push-mode dependency sums (kept at zero between uses)
+    int32_t *ldeg;              // degree sum of each level
     int32_t *d;
-    int32_t *list;
-    int32_t *lvl;
+    int32_t *lv;                // level lists: vertex
+    int32_t *la;                // first arc
+    int32_t *ld;                // degree
+    int32_t *lvl;               // level offsets
     int32_t *cand;
 };
 
 struct Counters {
-    unsigned long long arcs_fwd, arcs_bwd, dag, reached, tasks, td, bu, arcs_reached;
+    unsigned long long arcs_fwd, arcs_bwd, dag, reached, tasks, td, bu, arcs_reached, bw_push;
 };
 
 __device__ __forceinline__ bool bit_test(const uint32_t *bm, int32_t v) {
@@ -71,6 +79,46 @@ __device__ __forceinline__ bool bit_test(const uint32_t *bm, int32_t v) {
 }
 __device__ __forceinline__ void bit_set(uint32_t *bm, int32_t v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 __device__ __forceinline__ void bit_clear(uint32_t *bm, int32_t v) { atomicAnd(&bm[v >> 5], ~(1u << (v & 31))); }
+
+__device__ __forceinline__ double as_f64(unsigned long long x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ unsigned long long as_u64(double x) { return (unsigned long long)__double_as_longlong(x); }
+
+// Stages list entries [tb, tb+cnt) into the tile and returns the tile's arc
+// count.  Contains barriers.
+template <int BLOCK>
+__device__ __forceinline__ int32_t stage_list(Tile<BLOCK> &sm, const Scr &s, int32_t tb, int32_t cnt) {
+    const int tid = threadIdx.x;
+    int32_t dg = 0;
+    if (tid < cnt) {
+        sm.v[tid] = s.lv[tb + tid];
+        sm.a0[tid] = s.la[tb + tid];
+        dg = s.ld[tb + tid];
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+    if (tid < cnt) sm.pre[tid] = ex;
+    if (tid == 0) sm.pre[cnt] = total;
+    return total;
+}
+
+// Column indices of the thread's chunk [i0, i0 + kChunk) of the tile's arcs;
+// kk[j] = tile row of arc j, or -1 past the end.
+template <int BLOCK>
+__device__ __forceinline__ void load_chunk(const Tile<BLOCK> &sm, const GView &g, int32_t cnt, int32_t total,
+                                           int32_t i0, int32_t (&kk)[kChunk], int32_t (&w)[kChunk]) {
+    int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+        const int32_t i = i0 + j;
+        kk[j] = -1;
+        w[j] = 0;
+        if (i < total) {
+            while (sm.pre[k + 1] <= i) ++k;
+            kk[j] = k;
+            w[j] = g.ci[sm.a0[k] + (i - sm.pre[k])];
+        }
+    }
+}
 
 // ---------------------------------------------------------------- forward --
 
@@ -81,44 +129,30 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     const int tid = threadIdx.x;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
-        int32_t dg = 0;
-        if (tid < cnt) {
-            const int32_t v = s.list[tb + tid];
-            const int32_t a0 = g.rp[v];
-            dg = g.rp[v + 1] - a0;
-            sm.v[tid] = v;
-            sm.a0[tid] = a0;
-            sm.val.u[tid] = (MODE == kModeBFS) ? 1ULL : s.sigma[v];
-        }
-        int32_t total;
-        const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
-        if (tid < cnt) sm.pre[tid] = ex;
-        if (tid == 0) sm.pre[cnt] = total;
+        if (tid < cnt) sm.val.u[tid] = (MODE == kModeBFS) ? 1ULL : s.sigma[s.lv[tb + tid]];
+        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-            const int32_t i0 = rb + tid * kChunk;
-            int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
+            int32_t kk[kChunk], w[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+            bool act[kChunk];
+            unsigned long long add[kChunk], old[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                const int32_t i = i0 + j;
-                bool fresh = false;
-                int32_t w = 0;
-                if (i < total) {
-                    while (sm.pre[k + 1] <= i) ++k;
-                    w = g.ci[sm.a0[k] + (i - sm.pre[k])];
-                    if (!bit_test(bm, w)) {
-                        const unsigned long long sv = sm.val.u[k];
-                        const unsigned long long old = atomicAdd(&s.sigma[w], sv);
-                        if (MODE != kModeBFS && old + sv < old) atomicOr(&p.st->err, kErrOverflow);
-                        c.dag++;
-                        if (old == 0ULL) {
-                            fresh = true;
-                            s.d[w] = lvl + 1;
-                        }
-                    }
+                act[j] = kk[j] >= 0 && !bit_test(bm, w[j]);
+                add[j] = act[j] ? sm.val.u[kk[j]] : 0ULL;
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) old[j] = act[j] ? atomicAdd(&s.sigma[w[j]], add[j]) : 1ULL;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                if (act[j]) {
+                    c.dag++;
+                    if (MODE != kModeBFS && old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                    if ((MODE == kModeSSSP || MODE == kModePair) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
                 }
-                wave_append(fresh, w, s.list + f1, &sm.count, g.n - f1, &p.st->err);
+                wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
             }
         }
         __syncthreads();
@@ -171,35 +205,37 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-            const int32_t i0 = rb + tid * kChunk;
-            if (i0 < total) {
-                int32_t k = tile_search(sm.pre, cnt, i0);
-                int32_t kcur = k;
-                unsigned long long acc = 0ULL;
-                const int32_t iend = min(i0 + kChunk, total);
-                for (int32_t i = i0; i < iend; ++i) {
-                    while (sm.pre[k + 1] <= i) ++k;
-                    if (k != kcur) {
-                        if (acc) {
-                            const unsigned long long old = atomicAdd(&sm.val.u[kcur], acc);
-                            if (old + acc < old) atomicOr(&p.st->err, kErrOverflow);
-                        }
-                        kcur = k;
-                        acc = 0ULL;
+            int32_t kk[kChunk], v[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
+            unsigned long long sv[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const bool act = kk[j] >= 0 && bit_test(bm, v[j]);
+                sv[j] = act ? ((MODE == kModeBFS) ? 1ULL : s.sigma[v[j]]) : 0ULL;
+            }
+            int32_t kcur = kk[0];
+            unsigned long long acc = 0ULL;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                if (kk[j] < 0) continue;
+                if (kk[j] != kcur) {
+                    if (acc) {
+                        const unsigned long long o = atomicAdd(&sm.val.u[kcur], acc);
+                        if (MODE != kModeBFS && o + acc < o) atomicOr(&p.st->err, kErrOverflow);
                     }
-                    const int32_t v = g.ci[sm.a0[k] + (i - sm.pre[k])];
-                    if (bit_test(bm, v)) {
-                        const unsigned long long sv = (MODE == kModeBFS) ? 1ULL : s.sigma[v];
-                        const unsigned long long nacc = acc + sv;
-                        if (MODE != kModeBFS && nacc < acc) atomicOr(&p.st->err, kErrOverflow);
-                        acc = nacc;
-                        c.dag++;
-                    }
+                    kcur = kk[j];
+                    acc = 0ULL;
                 }
-                if (acc) {
-                    const unsigned long long old = atomicAdd(&sm.val.u[kcur], acc);
-                    if (MODE != kModeBFS && old + acc < old) atomicOr(&p.st->err, kErrOverflow);
+                if (sv[j]) {
+                    const unsigned long long nacc = acc + sv[j];
+                    if (MODE != kModeBFS && nacc < acc) atomicOr(&p.st->err, kErrOverflow);
+                    acc = nacc;
+                    c.dag++;
                 }
+            }
+            if (acc) {
+                const unsigned long long o = atomicAdd(&sm.val.u[kcur], acc);
+                if (MODE != kModeBFS && o + acc < o) atomicOr(&p.st->err, kErrOverflow);
             }
         }
         __syncthreads();
@@ -210,11 +246,25 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
             if (sum != 0ULL) {
                 w = sm.v[tid];
                 s.sigma[w] = sum;
-                s.d[w] = lvl + 1;
+                if (MODE == kModeSSSP || MODE == kModePair) s.d[w] = lvl + 1;
                 fresh = true;
             }
         }
-        wave_append(fresh, w, s.list + f1, &sm.count, g.n - f1, &p.st->err);
+        // block-ordered append: candidates are in id order, so the new level
+        // list comes out sorted and later per-vertex passes touch memory in
+        // increasing address order
+        int32_t nfresh;
+        const int32_t rank = block_excl_scan<BLOCK>(fresh ? 1 : 0, sm, nfresh);
+        const int32_t base = sm.count;
+        if (fresh) {
+            const int32_t pos = base + rank;
+            if (pos < g.n - f1)
+                s.lv[f1 + pos] = w;
+            else
+                atomicOr(&p.st->err, kErrInternal);
+        }
+        __syncthreads();
+        if (tid == 0) sm.count = base + nfresh;
         __syncthreads();
     }
 }
@@ -224,11 +274,11 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 // search stops after the level that reaches `target`.
 template <int BLOCK, int MODE>
 __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
-                           int32_t src, int32_t target, Counters &c) {
+                           const uint32_t *iso, int32_t src, int32_t target, Counters &c) {
     const int tid = threadIdx.x;
     const int32_t nw = (g.n + 31) >> 5;
     for (int32_t wi = tid; wi < nw; wi += BLOCK) {
-        uint32_t x = p.iso ? p.iso[wi] : 0u;
+        uint32_t x = iso ? iso[wi] : 0u;
         const int32_t hi = (wi + 1) * 32;
         if (hi > g.n) x |= ~0u << (32 - (hi - g.n));   // padding bits beyond n stay marked
         bm[wi] = x;
@@ -237,11 +287,15 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
     if (tid == 0) {
         bm[src >> 5] |= 1u << (src & 31);
         s.sigma[src] = 1ULL;
-        s.d[src] = 0;
-        s.list[0] = src;
+        if (MODE == kModeSSSP || MODE == kModePair) s.d[src] = 0;
+        const int32_t a0 = g.rp[src];
+        const int32_t dsrc = g.rp[src + 1] - a0;
+        s.lv[0] = src;
+        s.la[0] = a0;
+        s.ld[0] = dsrc;
         s.lvl[0] = 0;
         s.lvl[1] = 1;
-        const long long dsrc = g.rp[src + 1] - g.rp[src];
+        s.ldeg[0] = dsrc;
         sm.mf = dsrc;
         sm.mu = (long long)g.m - dsrc;
         c.arcs_reached += (unsigned long long)dsrc;
@@ -268,17 +322,23 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
             td_level<BLOCK, MODE>(p, sm, bm, s, g, f0, f1, lvl, c);
         __syncthreads();
         const int32_t nnew = sm.count < g.n - f1 ? sm.count : g.n - f1;
+        // mark the new level; record first arc and degree of each new vertex
         long long dsum = 0;
         for (int32_t i = f1 + tid; i < f1 + nnew; i += BLOCK) {
-            const int32_t w = s.list[i];
+            const int32_t w = s.lv[i];
             bit_set(bm, w);
-            dsum += g.rp[w + 1] - g.rp[w];
+            const int32_t a0 = g.rp[w];
+            const int32_t dg = g.rp[w + 1] - a0;
+            s.la[i] = a0;
+            s.ld[i] = dg;
+            dsum += dg;
         }
         dsum = wave_sum<long long>(dsum);
         if (lane_id() == 0 && dsum) atomicAdd((unsigned long long *)&sm.acc_mf, (unsigned long long)dsum);
         __syncthreads();
         if (tid == 0) {
             s.lvl[lvl + 2] = f1 + nnew;
+            s.ldeg[lvl + 1] = (int32_t)sm.acc_mf;
             sm.lvl_lo[0] = f1;
             sm.lvl_lo[1] = f1 + nnew;
             sm.mu -= sm.acc_mf;
@@ -295,6 +355,84 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
 
 // --------------------------------------------------------------- backward --
 
+// Level l by pull: every vertex v of level l sums coef over its unmarked
+// (= level l+1) neighbours.
+template <int BLOCK>
+__device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
+                        double *bcg, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, hi - tb);
+        if (tid < cnt) sm.val.f[tid] = 0.0;
+        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+        __syncthreads();
+        if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            int32_t kk[kChunk], w[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+            double cf[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                cf[j] = (kk[j] >= 0 && !bit_test(bm, w[j])) ? as_f64(s.sigma[w[j]]) : 0.0;
+            int32_t kcur = kk[0];
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                if (kk[j] < 0) continue;
+                if (kk[j] != kcur) {
+                    if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                    kcur = kk[j];
+                    acc = 0.0;
+                }
+                acc += cf[j];
+            }
+            if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            const int32_t v = sm.v[tid];
+            const double sg = (double)s.sigma[v];
+            const double delta = sg * sm.val.f[tid];
+            s.sigma[v] = as_u64((1.0 + delta) / sg);
+            if (delta != 0.0) atomicAdd(bcg + v, delta);
+        }
+        __syncthreads();
+    }
+}
+
+// Level l by push: every vertex w of level l+1 (list[lo1, hi1)) adds its
+// coef to dacc of its marked (= level l) neighbours; then each vertex v of
+// level l (list[lo, hi)) takes delta_v = sigma_v * dacc[v] and clears dacc.
+template <int BLOCK>
+__device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
+                        int32_t lo1, int32_t hi1, double *bcg, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t tb = lo1; tb < hi1; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, hi1 - tb);
+        if (tid < cnt) sm.val.f[tid] = as_f64(s.sigma[s.lv[tb + tid]]);
+        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+        __syncthreads();
+        if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            int32_t kk[kChunk], v[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                if (kk[j] >= 0 && bit_test(bm, v[j])) atomicAdd(s.dacc + v[j], sm.val.f[kk[j]]);
+        }
+        __syncthreads();
+    }
+    for (int32_t i = lo + tid; i < hi; i += BLOCK) {
+        const int32_t v = s.lv[i];
+        const double sg = (double)s.sigma[v];
+        const double delta = sg * s.dacc[v];
+        s.dacc[v] = 0.0;
+        s.sigma[v] = as_u64((1.0 + delta) / sg);
+        if (delta != 0.0) atomicAdd(bcg + v, delta);
+    }
+    __syncthreads();
+}
+
 template <int BLOCK>
 __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
                          int32_t Ld, double *bcg, Counters &c) {
@@ -303,62 +441,23 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     {
         const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
         for (int32_t i = lo + tid; i < hi; i += BLOCK) {
-            const int32_t v = s.list[i];
-            s.coef[v] = 1.0 / (double)s.sigma[v];
+            const int32_t v = s.lv[i];
+            s.sigma[v] = as_u64(1.0 / (double)s.sigma[v]);
             bit_clear(bm, v);
         }
     }
     __syncthreads();
     for (int32_t l = Ld - 1; l >= 1; --l) {
-        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
-        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
-            const int32_t cnt = min(BLOCK, hi - tb);
-            int32_t dg = 0;
-            if (tid < cnt) {
-                const int32_t v = s.list[tb + tid];
-                const int32_t a0 = g.rp[v];
-                dg = g.rp[v + 1] - a0;
-                sm.v[tid] = v;
-                sm.a0[tid] = a0;
-                sm.val.f[tid] = 0.0;
-            }
-            int32_t total;
-            const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
-            if (tid < cnt) sm.pre[tid] = ex;
-            if (tid == 0) sm.pre[cnt] = total;
-            __syncthreads();
-            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
-            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                const int32_t i0 = rb + tid * kChunk;
-                if (i0 < total) {
-                    int32_t k = tile_search(sm.pre, cnt, i0);
-                    int32_t kcur = k;
-                    double acc = 0.0;
-                    const int32_t iend = min(i0 + kChunk, total);
-                    for (int32_t i = i0; i < iend; ++i) {
-                        while (sm.pre[k + 1] <= i) ++k;
-                        if (k != kcur) {
-                            if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
-                            kcur = k;
-                            acc = 0.0;
-                        }
-                        const int32_t w = g.ci[sm.a0[k] + (i - sm.pre[k])];
-                        if (!bit_test(bm, w)) acc += s.coef[w];
-                    }
-                    if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
-                }
-            }
-            __syncthreads();
-            if (tid < cnt) {
-                const int32_t v = sm.v[tid];
-                const double sg = (double)s.sigma[v];
-                const double delta = sg * sm.val.f[tid];
-                s.coef[v] = (1.0 + delta) / sg;
-                if (delta != 0.0) atomicAdd(bcg + v, delta);
-            }
-            __syncthreads();
+        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1], hi1 = s.lvl[l + 2];
+        // scan whichever side of the level pair has fewer arcs
+        const bool push = (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
+        if (push) {
+            if (tid == 0) c.bw_push++;
+            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, c);
+        } else {
+            bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, c);
         }
-        for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.list[i]);
+        for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
         __syncthreads();
     }
 }
@@ -406,7 +505,7 @@ __device__ void walk_path(const Params &p, const uint32_t *bm, const Scr &s, con
         if (pick != src) {
             if (lane == 0) {
                 if (p.counts) atomicAdd(&p.counts[pick], 1u);
-                if (p.p_path && len < p.maxlen) p.p_path[task * p.maxlen + len] = pick;
+                if (p.p_path && len < p.maxlen) p.p_path[task * p.maxlen + len] = p.inv ? p.inv[pick] : pick;
             }
             ++len;
         }
@@ -431,14 +530,17 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     const long long slot = blockIdx.x;
     Scr s;
     s.sigma = p.sigma + slot * p.stride;
-    s.coef = p.coef + slot * p.stride;
+    s.dacc = p.dacc + slot * p.stride;
+    s.ldeg = p.ldeg + slot * p.stride;
     s.d = p.d + slot * p.stride;
-    s.list = p.list + slot * p.stride;
+    s.lv = p.lv + slot * p.stride;
+    s.la = p.la + slot * p.stride;
+    s.ld = p.ld + slot * p.stride;
     s.lvl = p.lvl + slot * p.stride;
     s.cand = p.cand + slot * p.stride;
     uint32_t *bm = BMLDS ? lds_bm : p.bmg + slot * p.bm_words;
 
-    Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
+    Counters c = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         if (tid == 0) sm.task = (long long)atomicAdd(&p.st->head, 1ULL);
         __syncthreads();
@@ -474,12 +576,12 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 const int32_t a = (int32_t)bounded(draw(p.seed, 1, (unsigned long long)j, 0), (unsigned long long)p.n);
                 int32_t b = (int32_t)bounded(draw(p.seed, 2, (unsigned long long)j, 0), (unsigned long long)(p.n - 1));
                 if (b >= a) b += 1;
-                src = a;
-                target = b;
                 if (tid == 0 && p.p_uv) {
                     p.p_uv[2 * task] = a;
                     p.p_uv[2 * task + 1] = b;
                 }
+                src = p.perm ? p.perm[a] : a;
+                target = p.perm ? p.perm[b] : b;
             } else if (MODE == kModeBFS) {
                 src = p.single_source;
             } else {
@@ -497,7 +599,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             continue;
         }
 
-        const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, src, target, c);
+        const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, p.G > 0 ? nullptr : p.iso, src, target, c);
         const int32_t nreached = s.lvl[Ld + 1];
         if (tid == 0) {
             c.reached += (unsigned long long)nreached;
@@ -509,9 +611,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
         } else if (MODE == kModeSSSP) {
             const long long row = task * (long long)g.n;
             for (int32_t i = tid; i < nreached; i += BLOCK) {
-                const int32_t v = s.list[i];
-                p.d_out[row + v] = s.d[v];
-                p.sigma_out[row + v] = s.sigma[v];
+                const int32_t v = s.lv[i];
+                const int32_t o = p.inv ? p.inv[v] : v;
+                p.d_out[row + o] = s.d[v];
+                p.sigma_out[row + o] = s.sigma[v];
             }
         } else if (MODE == kModePair) {
             if (wave_id() == 0) {
@@ -521,10 +624,13 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                     p.p_len[task] = -1;
             }
         } else if (MODE == kModeBFS) {
-            // eccentricity of src and the lowest id at that distance
+            // eccentricity of src and the lowest (original) id at that distance
             const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
             int32_t mn = 0x7fffffff;
-            for (int32_t i = lo + tid; i < hi; i += BLOCK) mn = min(mn, s.list[i]);
+            for (int32_t i = lo + tid; i < hi; i += BLOCK) {
+                const int32_t v = s.lv[i];
+                mn = min(mn, p.inv ? p.inv[v] : v);
+            }
             mn = wave_min(mn);
             if (lane_id() == 0) atomicMin(&p.st->info[1], mn);
             if (tid == 0) {
@@ -533,7 +639,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             }
         }
         __syncthreads();
-        for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.list[i]] = 0ULL;
+        for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.lv[i]] = 0ULL;
         __syncthreads();
     }
 
@@ -548,6 +654,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
         atomicAdd(&p.st->stat[kStTd], c.td);
         atomicAdd(&p.st->stat[kStBu], c.bu);
         atomicAdd(&p.st->stat[kStArcsReached], c.arcs_reached);
+        atomicAdd(&p.st->stat[kStBwPush], c.bw_push);
     }
 }
 
@@ -588,10 +695,8 @@ __global__ void k_status_init(DevStatus *st) {
         st->pad = 0;
         st->head = 0ULL;
     }
-    if (t < 8) {
-        st->stat[t] = 0ULL;
-        st->info[t] = (t == 1) ? 0x7fffffff : 0;
-    }
+    if (t < kNumStats) st->stat[t] = 0ULL;
+    if (t < 8) st->info[t] = (t == 1) ? 0x7fffffff : 0;
 }
 
 __global__ void k_validate(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, DevStatus *st) {
@@ -726,18 +831,6 @@ __global__ void k_cc_other_max(const int32_t *label, const int32_t *size, int32_
     if (best) atomicMax(out, best);
 }
 
-__global__ void k_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        const unsigned long long j = (unsigned long long)(j0 + i);
-        const int32_t a = (int32_t)bounded(draw(seed, 1, j, 0), (unsigned long long)n);
-        int32_t b = (int32_t)bounded(draw(seed, 2, j, 0), (unsigned long long)(n - 1));
-        if (b >= a) b += 1;
-        uv[2 * i] = a;
-        uv[2 * i + 1] = b;
-    }
-}
-
 static inline unsigned grid_for(long long count, int block) {
     long long g = (count + block - 1) / block;
     if (g < 1) g = 1;
@@ -811,11 +904,6 @@ hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipSt
 hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
                                hipStream_t s) {
     hipLaunchKernelGGL(k_cc_other_max, dim3(grid_for(n, 256)), dim3(256), 0, s, label, size, n, x0, out);
-    return hipGetLastError();
-}
-hipError_t launch_pair_list(unsigned long long seed, long long j0, long long count, int32_t n, int32_t *uv,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_pair_list, dim3(grid_for(count, 256)), dim3(256), 0, s, seed, j0, count, n, uv);
     return hipGetLastError();
 }
 

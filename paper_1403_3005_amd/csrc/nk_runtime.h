@@ -94,6 +94,16 @@ nk_status thread_events(hipEvent_t *ev0, hipEvent_t *ev1);
 // Graph argument checks shared by every entry point.
 nk_status check_graph_args(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m);
 
+// Degree-order relabelling (nk_relabel.hip).  Kernels skip their work when
+// the structural check already failed.
+nk_status relabel_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const DevStatus *st,
+                        Scratch &scr, hipStream_t s, Relabeled *out);
+hipError_t launch_map_sources(const int32_t *src, int32_t k, const int32_t *perm, int32_t n, int32_t *out,
+                              hipStream_t s);
+hipError_t launch_gather_scale(const double *in, const int32_t *perm, int32_t n, double scale, double *out,
+                               hipStream_t s);
+hipError_t launch_gather_u32(const uint32_t *in, const int32_t *perm, int32_t n, uint32_t *out, hipStream_t s);
+
 // Vertex-diameter bound (see nk_vd_bound); runs synchronously on `s`.
 nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
                         hipStream_t s);

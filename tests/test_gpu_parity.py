@@ -21,9 +21,9 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bru
 
 @pytest.fixture(autouse=True)
 def _default_tuning():
-    nk.nk_set_tuning(block=0, bu_ratio=1.0, wg_per_cu=0, flags=0)
+    nk.nk_set_tuning()
     yield
-    nk.nk_set_tuning(block=0, bu_ratio=1.0, wg_per_cu=0, flags=0)
+    nk.nk_set_tuning()
 
 
 def _exact(g):
@@ -103,22 +103,29 @@ def test_exact_er2000_full():
 
 
 @pytest.mark.parametrize("block", [256, 512, 1024])
-@pytest.mark.parametrize("bu_ratio", [0.0, 1.0, 1e9])
-@pytest.mark.parametrize("flags", [0, 1])
-def test_launch_variants(block, bu_ratio, flags):
-    """Every block size, direction policy (never / default / always bottom-up
-    after the first level) and bitmap placement gives the same result."""
-    nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, wg_per_cu=0, flags=flags)
+@pytest.mark.parametrize("bu_ratio", [0.0, 16.0, 1e9])
+@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("bw_ratio", [0.0, 0.1, 1e9])
+def test_launch_variants(block, bu_ratio, flags, bw_ratio):
+    """Every block size, forward direction policy (never / default / always
+    bottom-up after the first level), backward policy (always pull / default
+    / always push), bitmap placement and vertex order (relabelled or as given)
+    gives the same result."""
+    nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, wg_per_cu=0, flags=flags, bw_ratio=bw_ratio)
     g = gg.rmat(11, 8, 31)
     src = gg.sample_sources(g.n, 64, 32)
     rp, ci = upload(g)
     got = nk.nk_bc_sources(rp, ci, ivec(src), g.n / 64).cpu().numpy()
     st = nk.nk_last_stats()
-    assert st["block"] == block and st["bitmap_lds"] == (0 if flags else 1)
+    assert st["block"] == block and st["bitmap_lds"] == (0 if flags & 1 else 1)
     if bu_ratio == 0.0:
         assert st["levels_bu"] == 0
     if bu_ratio == 1e9:
         assert st["levels_bu"] > 0
+    if bw_ratio == 0.0:
+        assert st["levels_bw_push"] == 0
+    if bw_ratio == 1e9:
+        assert st["levels_bw_push"] > 0
     assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, g.n / 64), "variant")
     d, s = nk.nk_sssp_counts(rp, ci, ivec(src[:4]))
     for i in range(4):
