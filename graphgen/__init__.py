@@ -320,3 +320,33 @@ def serving_pool(count: int = 64, seed: int = 5, rmat_scales=(14, 20), ba_range=
     for i, n in enumerate(sizes):
         pool.append(barabasi_albert(n, 4, draw(seed, 64, i, 0)))
     return pool
+
+
+# --------------------------------------------------------- request streams --
+
+REQUEST_KINDS = (("k", 64), ("k", 256), ("k", 1024), ("eps", 0.05), ("eps", 0.02))
+
+
+def request_stream(count: int, qps: float, pool_sizes, seed: int = 5, kinds=REQUEST_KINDS, delta: float = 0.1):
+    """A Poisson request stream over a graph pool: arrival times with
+    exponential gaps of mean 1/qps, graph uniform over the pool, kind uniform
+    over `kinds` (k sampled sources, or pair sampling at a given epsilon), and
+    a per-request seed.  Sources of k-requests are drawn here (distinct,
+    uniform).  Request i uses draws (seed, 80, i, 0..3)."""
+    out = []
+    t = 0.0
+    for i in range(count):
+        u = ((draw(seed, 80, i, 0) >> 11) + 0.5) * (1.0 / 9007199254740992.0)
+        t += -math.log(u) / qps
+        g = int((draw(seed, 80, i, 1) * len(pool_sizes)) >> 64)
+        kind, val = kinds[int((draw(seed, 80, i, 2) * len(kinds)) >> 64)]
+        rseed = draw(seed, 80, i, 3)
+        req = {"id": i, "t": t, "graph": g, "seed": rseed}
+        n = pool_sizes[g]
+        if kind == "k":
+            req["sources"] = sample_sources(n, min(int(val), n), rseed)
+        else:
+            req["eps"] = float(val)
+            req["delta"] = delta
+        out.append(req)
+    return out

@@ -238,6 +238,52 @@ typedef struct {
 nk_status nk_set_tuning(const nk_tuning *t);
 nk_status nk_get_tuning(nk_tuning *t);
 
+/*
+ * Serving: betweenness queries on a resident pool of graphs with continuous
+ * batching and admission by HBM budget (the paper's use case of many
+ * analyses over many networks, run as a long-lived service).
+ *
+ * nk_server_create: hbm_budget_bytes bounds the device memory of resident
+ *   graphs plus running requests; n_slots (1..16, 0 = 4) requests run at once,
+ *   each on its own stream with 1/n_slots of the compute units.
+ * nk_server_add_graph: copies the CSR (DEVICE pointers, same rules as above)
+ *   into server memory, relabels it, computes its vertex-diameter bound.
+ *   NK_E_BUDGET if it does not fit.  Not concurrent with other calls on the
+ *   same server.
+ * nk_server_submit: queues a request and returns at once.
+ *   sources  HOST int32[k] (copied), k > 0: betweenness summed over these
+ *            sources, scaled by n / k;
+ *   k = 0:   pair sampling with eps, delta and seed (as nk_bc_pair_sample);
+ *   bc_out   HOST double[n] that receives the scores; it must stay valid
+ *            until nk_server_wait returns for the ticket.
+ *   NK_E_BUDGET if the request can never fit beside the resident graphs.
+ * Requests start in arrival order as soon as a slot is free and their
+ *   footprint fits the budget left by the graphs and the running requests.
+ * nk_server_wait: blocks until the request is done (timeout_s < 0: no limit),
+ *   returns its status (NK_E_TIMEOUT if not done in time; the ticket stays
+ *   valid then) and its latency from submit to scores in host memory
+ *   (latency_s, HOST, may be NULL).  A ticket is released once waited.
+ * nk_server_poll: *done = 1 when the request has finished.
+ * nk_server_stats: HOST out[8] = {completed, failed, p50 latency ms, p99
+ *   latency ms, max latency ms, GTEPS (sources or samples x undirected edges
+ *   over the span from first submit to last completion), most requests in
+ *   flight, device bytes in use}.  nk_server_reset_stats clears them.
+ * nk_server_destroy: waits for running requests, drops queued ones, frees
+ *   everything.
+ */
+typedef struct nk_server nk_server;
+
+nk_status nk_server_create(size_t hbm_budget_bytes, int32_t n_slots, nk_server **out);
+nk_status nk_server_add_graph(nk_server *server, const int32_t *rowptr, const int32_t *colidx, int32_t n,
+                              int64_t m, int32_t *graph_id);
+nk_status nk_server_submit(nk_server *server, int32_t graph_id, const int32_t *sources, int32_t k, double eps,
+                           double delta, uint64_t seed, double *bc_out, int64_t *ticket);
+nk_status nk_server_wait(nk_server *server, int64_t ticket, double timeout_s, double *latency_s);
+nk_status nk_server_poll(nk_server *server, int64_t ticket, int32_t *done);
+nk_status nk_server_stats(nk_server *server, double *out);
+nk_status nk_server_reset_stats(nk_server *server);
+void nk_server_destroy(nk_server *server);
+
 #ifdef __cplusplus
 }
 #endif

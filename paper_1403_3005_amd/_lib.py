@@ -34,6 +34,8 @@ EXPORTS = [
     "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
+    "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
+    "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy",
 ]
 
 
@@ -76,6 +78,15 @@ def load():
         "nk_last_stats": (c.c_int32, [i64p]),
         "nk_set_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
         "nk_get_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
+        "nk_server_create": (c.c_int32, [c.c_size_t, c.c_int32, c.POINTER(vp)]),
+        "nk_server_add_graph": (c.c_int32, [vp, vp, vp, c.c_int32, c.c_int64, i32p]),
+        "nk_server_submit": (c.c_int32, [vp, c.c_int32, i32p, c.c_int32, c.c_double, c.c_double, c.c_uint64,
+                                         c.POINTER(c.c_double), i64p]),
+        "nk_server_wait": (c.c_int32, [vp, c.c_int64, c.c_double, c.POINTER(c.c_double)]),
+        "nk_server_poll": (c.c_int32, [vp, c.c_int64, i32p]),
+        "nk_server_stats": (c.c_int32, [vp, c.POINTER(c.c_double)]),
+        "nk_server_reset_stats": (c.c_int32, [vp]),
+        "nk_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -239,3 +250,73 @@ def nk_get_tuning() -> dict:
     _check(load().nk_get_tuning(ctypes.byref(t)))
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
             "bw_ratio": t.bw_ratio}
+
+
+class NkServer:
+    """Binding of the nk_server_* family: a resident graph pool served with
+    continuous batching (see include/nk_bc.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4):
+        self._h = ctypes.c_void_p(0)
+        _check(load().nk_server_create(int(hbm_budget_bytes), int(slots), ctypes.byref(self._h)))
+        self.n = []
+        self._out = {}
+
+    def add_graph(self, rowptr, colidx) -> int:
+        rp, ci, n, m = _graph(rowptr, colidx)
+        gid = ctypes.c_int32(0)
+        _check(load().nk_server_add_graph(self._h, rp, ci, n, m, ctypes.byref(gid)))
+        self.n.append(n)
+        return int(gid.value)
+
+    def submit(self, graph_id: int, sources=None, eps: float = 0.0, delta: float = 0.1, seed: int = 0) -> int:
+        """Queues a request; returns its ticket.  sources: host int32 array
+        (k-source request) or None (pair sampling with eps, delta, seed)."""
+        known = 0 <= graph_id < len(self.n)
+        out = np.zeros(self.n[graph_id] if known else 1, dtype=np.float64)  # unknown ids: the library rejects them
+        t = ctypes.c_int64(0)
+        if sources is not None:
+            src = np.ascontiguousarray(sources, dtype=np.int32)
+            k = int(src.shape[0])
+            sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        else:
+            src, k, sp = None, 0, None
+        _check(load().nk_server_submit(self._h, graph_id, sp, k, float(eps), float(delta), int(seed),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(t)))
+        self._out[int(t.value)] = out
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(scores, latency in seconds) of a finished request."""
+        lat = ctypes.c_double(0.0)
+        code = load().nk_server_wait(self._h, ticket, float(timeout), ctypes.byref(lat))
+        if code == NK_E_TIMEOUT:
+            raise TimeoutError(f"ticket {ticket} not done")
+        out = self._out.pop(ticket)
+        _check(code)
+        return out, float(lat.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32(0)
+        _check(load().nk_server_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def stats(self) -> dict:
+        out = (ctypes.c_double * 8)()
+        _check(load().nk_server_stats(self._h, out))
+        keys = ["completed", "failed", "p50_ms", "p99_ms", "max_ms", "gteps", "max_inflight", "device_bytes"]
+        return {k: float(v) for k, v in zip(keys, out)}
+
+    def reset_stats(self):
+        _check(load().nk_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            load().nk_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
