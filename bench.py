@@ -74,6 +74,38 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0):
     }
 
 
+def serving_run(qps: float, count: int) -> dict:
+    """Poisson request stream over a resident pool of 8 graphs (R-MAT scales
+    14-17 with edge factor 16, Barabasi-Albert m0 = 4 with n from 1e4 to
+    3e5); requests are k in {64, 256, 1024} sources or pair sampling at
+    eps in {0.05, 0.02}, delta 0.1.  Latency is submit to scores in host
+    memory."""
+    import torch
+
+    import graphgen as gg
+    import paper_1403_3005_amd as nk
+    from paper_1403_3005_amd.serving import latency_summary, replay
+
+    print("bench: serving: building the graph pool", file=sys.stderr, flush=True)
+    pool = [gg.rmat(14 + i, 16, gg.draw(5, 63, i, 0)) for i in range(4)]
+    pool += [gg.barabasi_albert(n, 4, gg.draw(5, 64, i, 0)) for i, n in enumerate([10_000, 30_000, 100_000, 300_000])]
+    dev = torch.device("cuda:0")
+    with nk.NkServer(64 << 30, slots=4) as server:
+        ids = [server.add_graph(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev)) for g in pool]
+        warm = gg.request_stream(8, 1e6, [g.n for g in pool], seed=55)
+        replay(server, ids, warm)
+        server.reset_stats()
+        reqs = gg.request_stream(count, qps, [g.n for g in pool], seed=5)
+        print(f"bench: serving {count} requests at {qps} QPS", file=sys.stderr, flush=True)
+        results, wall = replay(server, ids, reqs)
+        st = server.stats()
+    lat = latency_summary(results)
+    return {"qps_offered": qps, "requests": count, "wall_s": round(wall, 2), "p50_ms": round(lat["p50_ms"], 2),
+            "p99_ms": round(lat["p99_ms"], 2), "max_ms": round(lat["max_ms"], 2), "gteps": round(st["gteps"], 3),
+            "max_inflight": int(st["max_inflight"]), "slots": 4,
+            "pool": "R-MAT scales 14-17 (ef 16) + BA n in {1e4, 3e4, 1e5, 3e5} (m0 4)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +114,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) measurement")
+    ap.add_argument("--serving-qps", type=float, default=8.0)
+    ap.add_argument("--serving-requests", type=int, default=96)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
@@ -119,6 +155,14 @@ def main():
     sv = torch.from_numpy(src).to(dev)
     bc = torch.empty(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+
+    if not args.no_autotune:
+        # untimed setup: the project's autotuner picks block size and direction
+        # thresholds on 256 of the sources
+        t0 = time.perf_counter()
+        best = nk.nk_autotune(rp, ci, sv[:256].contiguous())
+        nk.nk_set_tuning(**best)
+        print(f"bench: autotuned in {time.perf_counter() - t0:.1f} s: {best}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         nk.nk_bc_sources(rp, ci, sv, scale, bc=bc, stream=stream)
@@ -189,6 +233,8 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    if not args.no_serving:
+        out["serving"] = serving_run(args.serving_qps, args.serving_requests)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, src, m_u)

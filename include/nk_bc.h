@@ -239,6 +239,23 @@ nk_status nk_set_tuning(const nk_tuning *t);
 nk_status nk_get_tuning(nk_tuning *t);
 
 /*
+ * Autotuner: times every candidate (block in {256, 512, 1024}, bu_ratio in
+ * {0, 2, 8, 16, 64}, bw_ratio in {0, 0.1, 0.25, 1}) with nk_bc_sources on
+ * the given sample of sources (DEVICE int32[k]) and returns the fastest in
+ * *best (HOST).  The current tuning is left unchanged.  If cache_path is not
+ * NULL the winner is stored there under the graph's shape bucket
+ * (floor log2 n, round log2 mean degree, round log2 max degree / mean
+ * degree) in a flat JSON object {"bucket": [block, bu_ratio, bw_ratio, ms]}.
+ */
+nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
+                      int32_t k, const char *cache_path, nk_tuning *best, void *stream);
+
+/* Cached tuning for a graph shape (n vertices, m arcs, maximum degree
+ * max_deg) from an autotuner cache file; NK_E_INVALID_ARG if absent.  Host
+ * only: needs no GPU. */
+nk_status nk_tuning_lookup(const char *cache_path, int32_t n, int64_t m, int64_t max_deg, nk_tuning *out);
+
+/*
  * Serving: betweenness queries on a resident pool of graphs with continuous
  * batching and admission by HBM budget (the paper's use case of many
  * analyses over many networks, run as a long-lived service).

@@ -35,7 +35,7 @@ EXPORTS = [
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
-    "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy",
+    "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy", "nk_autotune", "nk_tuning_lookup",
 ]
 
 
@@ -87,6 +87,8 @@ def load():
         "nk_server_stats": (c.c_int32, [vp, c.POINTER(c.c_double)]),
         "nk_server_reset_stats": (c.c_int32, [vp]),
         "nk_server_destroy": (None, [vp]),
+        "nk_autotune": (c.c_int32, g + [vp, c.c_int32, c.c_char_p, c.POINTER(NkTuning), vp]),
+        "nk_tuning_lookup": (c.c_int32, [c.c_char_p, c.c_int32, c.c_int64, c.c_int64, c.POINTER(NkTuning)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +252,27 @@ def nk_get_tuning() -> dict:
     _check(load().nk_get_tuning(ctypes.byref(t)))
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
             "bw_ratio": t.bw_ratio}
+
+
+def _tuning_dict(t) -> dict:
+    return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
+            "bw_ratio": t.bw_ratio}
+
+
+def nk_autotune(rowptr, colidx, sources, cache_path: str | None = None, stream=None) -> dict:
+    """Fastest tuning on a sample of sources (see include/nk_bc.h)."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    t = NkTuning()
+    cp = cache_path.encode() if cache_path else None
+    _check(load().nk_autotune(rp, ci, n, m, _dev(sources, torch.int32, "sources"), sources.numel(), cp,
+                              ctypes.byref(t), _stream(stream)))
+    return _tuning_dict(t)
+
+
+def nk_tuning_lookup(cache_path: str, n: int, m: int, max_deg: int) -> dict:
+    t = NkTuning()
+    _check(load().nk_tuning_lookup(cache_path.encode(), n, m, max_deg, ctypes.byref(t)))
+    return _tuning_dict(t)
 
 
 class NkServer:

@@ -74,3 +74,17 @@ def test_sample_size_matches_oracle(eps, delta, vd):
     import paper_1403_3005_amd as nk
     assert nk.nk_rk_sample_size(eps, delta, vd) == oracle.rk_sample_size(eps, delta, vd)
     assert nk.nk_rk_sample_size(1.5, delta, vd) == -1
+
+
+def test_tuning_cache_lookup(tmp_path):
+    """The autotuner's cache format and bucket key (host logic, no GPU)."""
+    import paper_1403_3005_amd as nk
+    path = tmp_path / "tune.json"
+    # n = 2^20, 31.4M arcs (mean degree ~30 -> 2^5), max degree 65k (skew 2^11)
+    path.write_text('{\n  "n20_d5_s11": [1024, 16, 0.1, 455.5],\n  "n10_d3_s1": [256, 2, 0, 1.0]\n}\n')
+    t = nk.nk_tuning_lookup(str(path), 1 << 20, 31399850, 64562)
+    assert t["block"] == 1024 and t["bu_ratio"] == 16.0 and abs(t["bw_ratio"] - 0.1) < 1e-6
+    t = nk.nk_tuning_lookup(str(path), 2000, 20000, 25)
+    assert t["block"] == 256 and t["bu_ratio"] == 2.0 and t["bw_ratio"] == 0.0
+    with pytest.raises(nk.NkError):
+        nk.nk_tuning_lookup(str(path), 100, 300, 10)

@@ -338,3 +338,19 @@ def test_pair_isolated_targets():
     for i in range(200):
         u, v, interior = oracle.sample_path(g.rowptr, g.colidx, 12, i)
         assert ln[i].item() == (-1 if interior is None else len(interior))
+
+
+def test_autotune_picks_a_valid_tuning(tmp_path):
+    g = gg.rmat(12, 16, 121)
+    rp, ci = upload(g)
+    src = ivec(gg.sample_sources(g.n, 64, 122))
+    before = nk.nk_get_tuning()
+    cache = str(tmp_path / "tune.json")
+    best = nk.nk_autotune(rp, ci, src, cache)
+    assert nk.nk_get_tuning() == before  # unchanged
+    assert best["block"] in (256, 512, 1024)
+    deg = g.degrees()
+    assert nk.nk_tuning_lookup(cache, g.n, g.m, int(deg.max())) == best
+    nk.nk_set_tuning(**best)
+    got = nk.nk_bc_sources(rp, ci, src, 1.0).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src.cpu().numpy()), "tuned")
