@@ -74,6 +74,102 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0):
     }
 
 
+def _timed(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def other_workload(args) -> dict:
+    """One JSON record for a non-headline configuration (same fields as the
+    headline line, metric per configuration)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_1403_3005_amd as nk
+
+    dev = torch.device("cuda:0")
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    rec = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "er2000":
+        g = gg.workload_er2000(1)
+        rp, ci = up(g.rowptr), up(g.colidx)
+        bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sec = _timed(lambda: nk.nk_bc_exact(rp, ci, bc=bc), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        t0 = time.perf_counter()
+        oracle.bc_exact(g.rowptr, g.colidx)
+        cpu = time.perf_counter() - t0
+        rec.update(metric="GTEPS, exact Brandes, all sources", unit="GTEPS", dtype="f64",
+                   value=round(g.n * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": "er2000_exact", "n": g.n, "arcs": g.m, "kernel_ms": st["kernel_us"] / 1e3,
+                           "block": st["block"], "workgroups": st["workgroups"]},
+                   cpu_baseline={"value": round(g.n * g.m_undirected / cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                                 "kind": "oracle", "sample": f"all 2000 sources, {cpu:.2f} s"})
+    elif args.workload == "chunglu4m":
+        print("bench: generating Chung-Lu n=4e6", file=sys.stderr, flush=True)
+        g = gg.workload_chung_lu4m(3)
+        rp, ci = up(g.rowptr), up(g.colidx)
+        box = {}
+
+        def run():
+            box["r"] = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
+
+        sec = _timed(run, args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        bc, cnt, r, vd = box["r"]
+        # oracle on a bounded sample of the same pairs
+        t0 = time.perf_counter()
+        oracle.pair_counts(g.rowptr, g.colidx, 8, 3)
+        cpu = (time.perf_counter() - t0) / 8
+        rec.update(metric="pair samples per second (Riondato-Kornaropoulos, eps 0.01, delta 0.1)",
+                   unit="samples/s", dtype="u64+f64", value=round(r / sec, 1), ms_per_step=round(sec * 1e3, 1),
+                   config={"workload": "chunglu4m_pairs", "n": g.n, "arcs": g.m, "r": r, "vd_bound": vd,
+                           "r_times_edges_gteps": round(r * g.m_undirected / sec / 1e9, 3),
+                           "kernel_ms": st["kernel_us"] / 1e3, "reached": st["reached"],
+                           "arcs_scanned_fwd": st["arcs_fwd"], "bitmap_lds": st["bitmap_lds"]},
+                   cpu_baseline={"value": round(1.0 / cpu, 2), "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                 "sample": "first 8 pairs of the same sample sequence"})
+    else:
+        count = 512 if args.workload == "batched512" else 64
+        hi = 200_000 if args.workload == "batched512" else 20_000
+        print(f"bench: generating {count} graphs", file=sys.stderr, flush=True)
+        graphs = gg.workload_batched(count, 1000, hi, 4)
+        vtx = np.zeros(count + 1, dtype=np.int64)
+        arc = np.zeros(count + 1, dtype=np.int64)
+        for i, g in enumerate(graphs):
+            vtx[i + 1] = vtx[i] + g.n
+            arc[i + 1] = arc[i] + g.m
+        rp = up(np.concatenate([g.rowptr for g in graphs]).astype(np.int32))
+        ci = up(np.concatenate([g.colidx for g in graphs]).astype(np.int32))
+        work = sum(g.n * g.m_undirected for g in graphs)
+        sec = _timed(lambda: nk.nk_bc_exact_batched(vtx, arc, rp, ci), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        small = sorted(graphs, key=lambda g: g.n)[:4]
+        t0 = time.perf_counter()
+        for g in small:
+            oracle.bc_exact(g.rowptr, g.colidx)
+        cpu = time.perf_counter() - t0
+        rec.update(metric="GTEPS, exact Brandes on a batch of graphs in one launch", unit="GTEPS", dtype="f64",
+                   value=round(work / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 1),
+                   config={"workload": f"batched{count}", "graphs": count, "n_total": int(vtx[-1]),
+                           "arcs_total": int(arc[-1]), "n_range": [1000, hi], "kernel_ms": st["kernel_us"] / 1e3,
+                           "block": st["block"], "workgroups": st["workgroups"]},
+                   cpu_baseline={"value": round(sum(g.n * g.m_undirected for g in small) / cpu / 1e9, 4),
+                                 "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                                 "sample": "the 4 smallest graphs of the batch, exact"})
+    return rec
+
+
 def serving_run(qps: float, count: int) -> dict:
     """Poisson request stream over a resident pool of 8 graphs (R-MAT scales
     14-17 with edge factor 16, Barabasi-Albert m0 = 4 with n from 1e4 to
@@ -118,6 +214,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--serving-qps", type=float, default=8.0)
     ap.add_argument("--serving-requests", type=int, default=96)
+    ap.add_argument("--workload", default="rmat20",
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64"],
+                    help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
@@ -143,6 +242,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 4}), flush=True)
+        return
+    if args.workload != "rmat20":
+        print(json.dumps(other_workload(args)), flush=True)
         return
     print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
     g, src = gg.workload_rmat20(2)
