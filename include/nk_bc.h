@@ -197,7 +197,7 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
 
 /*
  * Statistics of the calling thread's last nk_bc_exact / nk_bc_sources /
- * nk_bc_exact_batched / pair-sampling call (HOST out[16]):
+ * nk_bc_exact_batched / pair-sampling call (HOST out[32]):
  *   out[0] sources (or samples) processed     out[1] vertices reached
  *   out[2] arcs scanned, forward              out[3] arcs scanned, backward
  *   out[4] shortest-path DAG arcs             out[5] levels run top-down
@@ -206,6 +206,11 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
  *   out[9] threads per workgroup              out[10] 1 if the visited bitmap sat in LDS
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
  *   out[12] dependency-sweep levels run by push   out[13..15] reserved
+ *   out[16..23] shader-clock cycles per phase, summed over workgroups:
+ *           task set-up, top-down levels, bottom-up levels, level marking,
+ *           pull levels, push levels, path-count reset, everything else
+ *   out[24..29] cycles inside bottom-up levels (staging and scans, arc loop,
+ *           finalize) and pull levels (same three); out[30..31] reserved
  */
 nk_status nk_last_stats(int64_t *out);
 

@@ -233,11 +233,13 @@ def nk_bc_exact_batched(vtx_off, arc_off, rowptr_cat, colidx_cat, stream=None):
 
 STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",
              "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "reserved13", "reserved14",
-             "reserved15"]
+             "reserved15", "cyc_init", "cyc_topdown", "cyc_bottomup", "cyc_mark", "cyc_pull", "cyc_push",
+             "cyc_reset", "cyc_other", "sub_bu_stage", "sub_bu_arcs", "sub_bu_finalize", "sub_pull_stage",
+             "sub_pull_arcs", "sub_pull_finalize", "reserved30", "reserved31"]
 
 
 def nk_last_stats() -> dict:
-    out = (ctypes.c_int64 * 16)()
+    out = (ctypes.c_int64 * 32)()
     _check(load().nk_last_stats(out))
     return {k: int(v) for k, v in zip(STAT_KEYS, out)}
 

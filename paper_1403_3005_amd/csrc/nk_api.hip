@@ -18,7 +18,7 @@ namespace nk {
 // ------------------------------------------------------------------ errors --
 
 static thread_local std::string t_err;
-static thread_local int64_t t_stats[16];
+static thread_local int64_t t_stats[32];
 
 nk_status fail(nk_status code, const char *fmt, ...) {
     char buf[512];
@@ -197,6 +197,8 @@ void stats_record(const DevStatus &st, int grid, int block, bool lds, float kern
     t_stats[11] = (int64_t)st.stat[kStArcsReached];
     t_stats[12] = (int64_t)st.stat[kStBwPush];
     t_stats[13] = t_stats[14] = t_stats[15] = 0;
+    for (int i = 0; i < kNumPhases; ++i) t_stats[16 + i] = (int64_t)st.cycles[i];
+    for (int i = 0; i < 8; ++i) t_stats[24 + i] = (int64_t)st.sub[i];
 }
 
 static thread_local DevStatus *t_host_status = nullptr;

@@ -30,7 +30,13 @@ struct DevStatus {
     unsigned long long head;
     unsigned long long stat[12];
     int32_t info[8];   // BFS mode: eccentricity, lowest far vertex, reached count
+    unsigned long long cycles[8];  // shader clock cycles per phase, summed over workgroups
+    unsigned long long sub[8];     // shader clock cycles per sub-phase
 };
+
+enum PhaseIdx { kPhInit = 0, kPhTd, kPhBu, kPhMark, kPhPull, kPhPush, kPhReset, kPhOther, kNumPhases };
+// sub-phases of the bottom-up and pull levels (staging + scans, arc loop, finalize)
+enum SubIdx { kSbBuStage = 0, kSbBuArcs, kSbBuFin, kSbPlStage, kSbPlArcs, kSbPlFin, kNumSub };
 
 enum StatIdx {
     kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached, kStBwPush,
@@ -108,6 +114,10 @@ struct Tile {
     int32_t flag;
     int32_t levels;
     int32_t lvl_lo[2];
+    // timing (thread 0 only)
+    unsigned long long cyc[8];
+    unsigned long long sub[8];
+    long long t0, ts;
 };
 
 // Block-wide exclusive scan of one int per thread; returns the thread's

@@ -74,6 +74,29 @@ struct Counters {
     unsigned long long arcs_fwd, arcs_bwd, dag, reached, tasks, td, bu, arcs_reached, bw_push;
 };
 
+// Phase timing by thread 0 into LDS: phases end at block barriers, so
+// thread 0's clock brackets the workgroup's time in the phase.
+template <int BLOCK>
+__device__ __forceinline__ void phase_start(Tile<BLOCK> &sm) {
+    if (threadIdx.x == 0) sm.t0 = clock64();
+}
+template <int BLOCK>
+__device__ __forceinline__ void phase_end(Tile<BLOCK> &sm, int ph) {
+    if (threadIdx.x == 0) sm.cyc[ph] += (unsigned long long)(clock64() - sm.t0);
+}
+template <int BLOCK>
+__device__ __forceinline__ void sub_mark(Tile<BLOCK> &sm, int sb) {
+    if (threadIdx.x == 0) {
+        const long long now = clock64();
+        sm.sub[sb] += (unsigned long long)(now - sm.ts);
+        sm.ts = now;
+    }
+}
+template <int BLOCK>
+__device__ __forceinline__ void sub_start(Tile<BLOCK> &sm) {
+    if (threadIdx.x == 0) sm.ts = clock64();
+}
+
 __device__ __forceinline__ bool bit_test(const uint32_t *bm, int32_t v) {
     return (bm[v >> 5] >> (v & 31)) & 1u;
 }
@@ -187,6 +210,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     }
     __syncthreads();
     const int32_t nc = sm.redmin;
+    sub_start<BLOCK>(sm);
     for (int32_t tb = 0; tb < nc; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, nc - tb);
         int32_t dg = 0;
@@ -203,6 +227,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         if (tid < cnt) sm.pre[tid] = ex;
         if (tid == 0) sm.pre[cnt] = total;
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbBuStage);
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
             int32_t kk[kChunk], v[kChunk];
@@ -239,6 +264,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
             }
         }
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbBuArcs);
         bool fresh = false;
         int32_t w = 0;
         if (tid < cnt) {
@@ -258,14 +284,18 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         const int32_t base = sm.count;
         if (fresh) {
             const int32_t pos = base + rank;
-            if (pos < g.n - f1)
+            if (pos < g.n - f1) {
                 s.lv[f1 + pos] = w;
-            else
+                s.la[f1 + pos] = sm.a0[tid];
+                s.ld[f1 + pos] = dg;
+            } else {
                 atomicOr(&p.st->err, kErrInternal);
+            }
         }
         __syncthreads();
         if (tid == 0) sm.count = base + nfresh;
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbBuFin);
     }
 }
 
@@ -277,6 +307,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
                            const uint32_t *iso, int32_t src, int32_t target, Counters &c) {
     const int tid = threadIdx.x;
     const int32_t nw = (g.n + 31) >> 5;
+    phase_start<BLOCK>(sm);
     for (int32_t wi = tid; wi < nw; wi += BLOCK) {
         uint32_t x = iso ? iso[wi] : 0u;
         const int32_t hi = (wi + 1) * 32;
@@ -304,6 +335,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
         sm.flag = 0;
     }
     __syncthreads();
+    phase_end<BLOCK>(sm, kPhInit);
     int32_t lvl = 0;
     for (;;) {
         const int32_t f0 = sm.lvl_lo[0], f1 = sm.lvl_lo[1];
@@ -316,21 +348,30 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
             if (bu) c.bu++; else c.td++;
         }
         __syncthreads();
+        phase_start<BLOCK>(sm);
         if (bu)
             bu_level<BLOCK, MODE>(p, sm, bm, s, g, f1, lvl, c);
         else
             td_level<BLOCK, MODE>(p, sm, bm, s, g, f0, f1, lvl, c);
         __syncthreads();
+        if (bu) phase_end<BLOCK>(sm, kPhBu); else phase_end<BLOCK>(sm, kPhTd);
+        phase_start<BLOCK>(sm);
         const int32_t nnew = sm.count < g.n - f1 ? sm.count : g.n - f1;
-        // mark the new level; record first arc and degree of each new vertex
+        // mark the new level; a top-down level also records first arc and
+        // degree of each new vertex (the bottom-up append already did)
         long long dsum = 0;
         for (int32_t i = f1 + tid; i < f1 + nnew; i += BLOCK) {
             const int32_t w = s.lv[i];
             bit_set(bm, w);
-            const int32_t a0 = g.rp[w];
-            const int32_t dg = g.rp[w + 1] - a0;
-            s.la[i] = a0;
-            s.ld[i] = dg;
+            int32_t dg;
+            if (bu) {
+                dg = s.ld[i];
+            } else {
+                const int32_t a0 = g.rp[w];
+                dg = g.rp[w + 1] - a0;
+                s.la[i] = a0;
+                s.ld[i] = dg;
+            }
             dsum += dg;
         }
         dsum = wave_sum<long long>(dsum);
@@ -347,6 +388,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
             if (MODE == kModePair) sm.flag = bit_test(bm, target) ? 1 : 0;
         }
         __syncthreads();
+        phase_end<BLOCK>(sm, kPhMark);
         if (nnew == 0) break;
         ++lvl;
     }
@@ -361,11 +403,13 @@ template <int BLOCK>
 __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
                         double *bcg, Counters &c) {
     const int tid = threadIdx.x;
+    sub_start<BLOCK>(sm);
     for (int32_t tb = lo; tb < hi; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, hi - tb);
         if (tid < cnt) sm.val.f[tid] = 0.0;
         const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbPlStage);
         if (tid == 0) c.arcs_bwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
             int32_t kk[kChunk], w[kChunk];
@@ -389,6 +433,7 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
             if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
         }
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbPlArcs);
         if (tid < cnt) {
             const int32_t v = sm.v[tid];
             const double sg = (double)s.sigma[v];
@@ -397,6 +442,7 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
             if (delta != 0.0) atomicAdd(bcg + v, delta);
         }
         __syncthreads();
+        sub_mark<BLOCK>(sm, kSbPlFin);
     }
 }
 
@@ -451,12 +497,14 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         const int32_t lo = s.lvl[l], hi = s.lvl[l + 1], hi1 = s.lvl[l + 2];
         // scan whichever side of the level pair has fewer arcs
         const bool push = (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
+        phase_start<BLOCK>(sm);
         if (push) {
             if (tid == 0) c.bw_push++;
             bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, c);
         } else {
             bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, c);
         }
+        if (push) phase_end<BLOCK>(sm, kPhPush); else phase_end<BLOCK>(sm, kPhPull);
         for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
         __syncthreads();
     }
@@ -541,6 +589,12 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     uint32_t *bm = BMLDS ? lds_bm : p.bmg + slot * p.bm_words;
 
     Counters c = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (tid < 8) {
+        sm.cyc[tid] = 0;
+        sm.sub[tid] = 0;
+    }
+    __syncthreads();
+    const long long t_kernel = clock64();
     for (;;) {
         if (tid == 0) sm.task = (long long)atomicAdd(&p.st->head, 1ULL);
         __syncthreads();
@@ -639,8 +693,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             }
         }
         __syncthreads();
+        phase_start<BLOCK>(sm);
         for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.lv[i]] = 0ULL;
         __syncthreads();
+        phase_end<BLOCK>(sm, kPhReset);
     }
 
     // counters: wave sums, one atomic per wave and counter
@@ -655,6 +711,14 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
         atomicAdd(&p.st->stat[kStBu], c.bu);
         atomicAdd(&p.st->stat[kStArcsReached], c.arcs_reached);
         atomicAdd(&p.st->stat[kStBwPush], c.bw_push);
+        unsigned long long known = 0;
+        for (int i = 0; i < kNumPhases; ++i) {
+            if (i != kPhOther) known += sm.cyc[i];
+        }
+        const unsigned long long total = (unsigned long long)(clock64() - t_kernel);
+        sm.cyc[kPhOther] = total > known ? total - known : 0;
+        for (int i = 0; i < kNumPhases; ++i) atomicAdd(&p.st->cycles[i], sm.cyc[i]);
+        for (int i = 0; i < kNumSub; ++i) atomicAdd(&p.st->sub[i], sm.sub[i]);
     }
 }
 
@@ -696,6 +760,8 @@ __global__ void k_status_init(DevStatus *st) {
         st->head = 0ULL;
     }
     if (t < kNumStats) st->stat[t] = 0ULL;
+    if (t < kNumPhases) st->cycles[t] = 0ULL;
+    if (t < 8) st->sub[t] = 0ULL;
     if (t < 8) st->info[t] = (t == 1) ? 0x7fffffff : 0;
 }
 
