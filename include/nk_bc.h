@@ -180,8 +180,10 @@ nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t 
                           int32_t *uv, int32_t *len, int32_t *path, void *stream);
 
 /*
- * Exact betweenness of G independent graphs in one persistent launch (the
- * paper's recommended use on "large batches of smaller networks").
+ * Exact betweenness of G independent graphs (the paper's recommended use on
+ * large batches of smaller networks): one persistent launch of the
+ * all-in-LDS kernel for the graphs that fit one workgroup's LDS, one of the
+ * global-memory kernel for the rest, each draining (graph, source) tasks.
  *   vtx_off  HOST int64[G+1]: graph g has vertices vtx_off[g] .. vtx_off[g+1]-1
  *            of the concatenated vertex space;
  *   arc_off  HOST int64[G+1]: its arcs are colidx_cat[arc_off[g] .. arc_off[g+1]);
@@ -203,7 +205,10 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
  *   out[4] shortest-path DAG arcs             out[5] levels run top-down
  *   out[6] levels run bottom-up               out[7] workgroups launched
  *   out[8] main kernel time in microseconds (HIP events on the call's stream)
- *   out[9] threads per workgroup              out[10] 1 if the visited bitmap sat in LDS
+ *   out[9] threads per workgroup
+ *   out[10] kernel placement: 0 visited bitmap in global memory, 1 bitmap in
+ *           LDS, 2 whole graph in LDS (all-in-LDS kernel), 3 a batch split
+ *           between the all-in-LDS kernel and the LDS-bitmap kernel
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
  *   out[12] dependency-sweep levels run by push   out[13..15] reserved
  *   out[16..23] shader-clock cycles per phase, summed over workgroups:
@@ -226,6 +231,9 @@ nk_status nk_last_stats(int64_t *out);
  *              would fit in LDS (for testing that placement);
  *              bit 1: run single graphs under their own vertex ids instead
  *              of the internal degree-descending relabelling;
+ *              bit 2: never use the all-in-LDS kernel (which otherwise runs
+ *              betweenness on every graph whose CSR plus one source's state,
+ *              about 16 n + 4 m bytes, fits one workgroup's LDS);
  *   bw_ratio   in the dependency sweep, handle level l by pushing from level
  *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
  *              of level l (0 = always pull; default 0.1).

@@ -182,7 +182,7 @@ void tuning_set(const nk_tuning &t) {
 
 void stats_clear() { memset(t_stats, 0, sizeof(t_stats)); }
 
-void stats_record(const DevStatus &st, int grid, int block, bool lds, float kernel_ms) {
+void stats_record(const DevStatus &st, int grid, int block, int lds, float kernel_ms) {
     t_stats[0] = (int64_t)st.stat[kStSources];
     t_stats[1] = (int64_t)st.stat[kStReached];
     t_stats[2] = (int64_t)st.stat[kStArcsFwd];
@@ -193,7 +193,7 @@ void stats_record(const DevStatus &st, int grid, int block, bool lds, float kern
     t_stats[7] = grid;
     t_stats[8] = (int64_t)llround((double)kernel_ms * 1000.0);
     t_stats[9] = block;
-    t_stats[10] = lds ? 1 : 0;
+    t_stats[10] = lds;
     t_stats[11] = (int64_t)st.stat[kStArcsReached];
     t_stats[12] = (int64_t)st.stat[kStBwPush];
     t_stats[13] = t_stats[14] = t_stats[15] = 0;
@@ -288,6 +288,42 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     plan->bm_words = (words + 63) / 64 * 64;
     plan->kernel = kr;
     return NK_OK;
+}
+
+bool plan_lds(size_t dyn_bytes, int32_t n_max, long long ntasks, LaunchPlan *plan) {
+    nk_tuning t = tuning_get();
+    if (t.flags & 4) return false;
+    DevInfo di;
+    if (dev_info(&di) != NK_OK) {
+        clear_error();
+        return false;
+    }
+    int block = t.block;
+    // levels of graphs above ~1500 vertices fill a 1024-thread tile; smaller
+    // ones leave room for two 512-thread workgroups per compute unit
+    if (block != 256 && block != 512 && block != 1024) block = n_max >= 1500 ? 1024 : 512;
+    KernelRef kr = brandes_lds_kernel(block);
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, kr.fn) != hipSuccess) return false;
+    if (attr.sharedSizeBytes + dyn_bytes > di.lds_per_block) return false;
+    if (hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes) != hipSuccess)
+        return false;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kr.fn, block, dyn_bytes) != hipSuccess || occ < 1)
+        return false;
+    if (t.wg_per_cu > 0 && t.wg_per_cu < occ) occ = t.wg_per_cu;
+    long long grid = (long long)di.cus * occ;
+    if (ntasks < grid) grid = ntasks;
+    if (grid < 1) grid = 1;
+    plan->mode = kModeBC;
+    plan->block = block;
+    plan->lds = true;
+    plan->grid = (int)grid;
+    plan->dyn_lds = dyn_bytes;
+    plan->stride = 0;
+    plan->bm_words = 0;
+    plan->kernel = kr;
+    return true;
 }
 
 nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
@@ -509,7 +545,31 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     NK_HIP(launch_fill_f64(bc, 0.0, n, s));
     LaunchPlan plan = {};
     float ms = 0.0f;
-    if (k > 0) {
+    int where = 0;
+    if (k > 0 && plan_lds(lds_graph_bytes(n, m), n, k, &plan)) {
+        // the whole graph fits one workgroup's LDS: no relabelling, no scratch
+        Params p;
+        memset(&p, 0, sizeof(p));
+        p.rowptr = rowptr;
+        p.colidx = colidx;
+        p.n = n;
+        p.m = (int32_t)m;
+        p.ntasks = k;
+        p.sources = sources;
+        p.bc = bc;
+        p.st = dst;
+        hipEvent_t ev0, ev1;
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        NK_HIP(hipEventRecord(ev0, s));
+        plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
+        NK_HIP(hipGetLastError());
+        NK_HIP(hipEventRecord(ev1, s));
+        if (scale != 1.0) NK_HIP(launch_scale_f64(bc, scale, n, s));
+        st = finish(dst, h, s);
+        NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        where = 2;
+    } else if (k > 0) {
+        where = -1;
         Relabeled g;
         if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
         NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
@@ -549,7 +609,8 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     } else {
         st = finish(dst, h, s);
     }
-    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    if (where < 0) where = plan.lds ? 1 : 0;
+    stats_record(*h, plan.grid, plan.block, where, ms);
     return st;
 }
 
@@ -800,13 +861,11 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
     if (G == 0) return NK_OK;
     if (!vtx_off || !arc_off) return fail(NK_E_INVALID_ARG, "offset tables are NULL");
     if (vtx_off[0] != 0 || arc_off[0] != 0) return fail(NK_E_INVALID_ARG, "offsets must start at 0");
-    int32_t n_max = 0;
     std::vector<long long> work(G);
     for (int32_t g = 0; g < G; ++g) {
         const long long ng = vtx_off[g + 1] - vtx_off[g], mg = arc_off[g + 1] - arc_off[g];
         if (ng < 0 || mg < 0 || ng > 2147483647LL || mg > 2147483647LL)
             return fail(NK_E_INVALID_ARG, "graph %d has bad offsets", g);
-        n_max = std::max<int32_t>(n_max, (int32_t)ng);
         work[g] = ng * std::max<long long>(mg, 1);
     }
     const long long nv = vtx_off[G], na = arc_off[G];
@@ -819,52 +878,111 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
     if ((st = scr.get(1, &dst)) != NK_OK) return st;
     DevStatus *h = host_status();
     if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
-    NK_HIP(launch_status_init(dst, s));
-    for (int32_t g = 0; g < G; ++g) {
-        const int32_t ng = (int32_t)(vtx_off[g + 1] - vtx_off[g]);
-        if (ng == 0) continue;
-        NK_HIP(launch_validate(rowptr_cat + vtx_off[g] + g, colidx_cat + arc_off[g], ng, arc_off[g + 1] - arc_off[g],
-                               0, dst, s));
-    }
-    NK_HIP(launch_fill_f64(bc_cat, 0.0, nv, s));
-    // largest graphs first so the tail of the launch is made of small tasks
-    std::vector<int32_t> order(G);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
-    std::vector<long long> task_pre(G + 1, 0);
-    for (int32_t i = 0; i < G; ++i) task_pre[i + 1] = task_pre[i] + (vtx_off[order[i] + 1] - vtx_off[order[i]]);
-    long long *d_vtx, *d_arc, *d_task;
-    int32_t *d_order;
+    long long *d_vtx, *d_arc;
     if ((st = scr.get(G + 1, &d_vtx)) != NK_OK) return st;
     if ((st = scr.get(G + 1, &d_arc)) != NK_OK) return st;
-    if ((st = scr.get(G + 1, &d_task)) != NK_OK) return st;
-    if ((st = scr.get(G, &d_order)) != NK_OK) return st;
     NK_HIP(hipMemcpyAsync(d_vtx, vtx_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
     NK_HIP(hipMemcpyAsync(d_arc, arc_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
-    NK_HIP(hipMemcpyAsync(d_task, task_pre.data(), sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
-    NK_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
-    LaunchPlan plan;
-    if ((st = plan_launch(kModeBC, n_max, task_pre[G], 0, &plan)) != NK_OK) return st;
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate_batched(rowptr_cat, colidx_cat, d_vtx, d_arc, G, dst, s));
+    NK_HIP(launch_fill_f64(bc_cat, 0.0, nv, s));
+
+    // Graphs whose CSR and per-source state fit one workgroup's LDS run on
+    // the all-in-LDS kernel, the others on the global-memory kernel.  Each
+    // part takes its largest graphs first, so launch tails are made of
+    // small tasks.
+    size_t dyn_max = 0;
+    LaunchPlan probe;
+    const bool lds_ok = plan_lds(0, 1 << 20, 1, &probe);
+    size_t budget = 0;
+    if (lds_ok) {
+        hipFuncAttributes attr;
+        NK_HIP(hipFuncGetAttributes(&attr, probe.kernel.fn));
+        DevInfo di;
+        if ((st = dev_info(&di)) != NK_OK) return st;
+        budget = di.lds_per_block > attr.sharedSizeBytes ? di.lds_per_block - attr.sharedSizeBytes : 0;
+    }
+    std::vector<int32_t> small, large;
+    int32_t n_large = 0, n_small = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        const long long ng = vtx_off[g + 1] - vtx_off[g], mg = arc_off[g + 1] - arc_off[g];
+        if (ng == 0) continue;
+        const size_t b = lds_graph_bytes((int32_t)ng, mg);
+        if (lds_ok && b <= budget) {
+            small.push_back(g);
+            dyn_max = std::max(dyn_max, b);
+            n_small = std::max<int32_t>(n_small, (int32_t)ng);
+        } else {
+            large.push_back(g);
+            n_large = std::max<int32_t>(n_large, (int32_t)ng);
+        }
+    }
+    auto by_work = [&](int32_t a, int32_t b) { return work[a] > work[b]; };
+    std::stable_sort(small.begin(), small.end(), by_work);
+    std::stable_sort(large.begin(), large.end(), by_work);
+    auto tables = [&](const std::vector<int32_t> &ids, long long **d_task, int32_t **d_order,
+                      long long *ntasks) -> nk_status {
+        const int32_t K = (int32_t)ids.size();
+        std::vector<long long> pre(K + 1, 0);
+        for (int32_t i = 0; i < K; ++i) pre[i + 1] = pre[i] + (vtx_off[ids[i] + 1] - vtx_off[ids[i]]);
+        nk_status e;
+        if ((e = scr.get(K + 1, d_task)) != NK_OK) return e;
+        if ((e = scr.get(K, d_order)) != NK_OK) return e;
+        NK_HIP(hipMemcpyAsync(*d_task, pre.data(), sizeof(long long) * (K + 1), hipMemcpyHostToDevice, s));
+        NK_HIP(hipMemcpyAsync(*d_order, ids.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+        // the host vectors must outlive the copies
+        NK_HIP(hipStreamSynchronize(s));
+        *ntasks = pre[K];
+        return NK_OK;
+    };
     Params p;
     memset(&p, 0, sizeof(p));
     p.rowptr = rowptr_cat;
     p.colidx = colidx_cat;
-    p.n = n_max;
-    p.G = G;
     p.g_vtx = d_vtx;
     p.g_arc = d_arc;
-    p.g_task = d_task;
-    p.g_order = d_order;
-    p.ntasks = task_pre[G];
     p.bc = bc_cat;
     p.st = dst;
     hipEvent_t ev0, ev1;
     if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
-    if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+    LaunchPlan plan_s = {}, plan_l = {};
+    long long *t_small = nullptr, *t_large = nullptr;
+    int32_t *o_small = nullptr, *o_large = nullptr;
+    long long k_small = 0, k_large = 0;
+    if (!small.empty()) {
+        if ((st = tables(small, &t_small, &o_small, &k_small)) != NK_OK) return st;
+        if (!plan_lds(dyn_max, n_small, k_small, &plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
+    }
+    if (!large.empty()) {
+        if ((st = tables(large, &t_large, &o_large, &k_large)) != NK_OK) return st;
+        if ((st = plan_launch(kModeBC, n_large, k_large, 0, &plan_l)) != NK_OK) return st;
+    }
+    NK_HIP(hipEventRecord(ev0, s));
+    if (!small.empty()) {
+        p.n = 0;
+        p.G = (int32_t)small.size();
+        p.g_task = t_small;
+        p.g_order = o_small;
+        p.ntasks = k_small;
+        plan_s.kernel.launch(dim3(plan_s.grid), dim3(plan_s.block), plan_s.dyn_lds, s, p);
+        NK_HIP(hipGetLastError());
+    }
+    if (!large.empty()) {
+        if (!small.empty()) NK_HIP(launch_reset_head(dst, s));
+        p.n = n_large;
+        p.G = (int32_t)large.size();
+        p.g_task = t_large;
+        p.g_order = o_large;
+        p.ntasks = k_large;
+        if ((st = launch_persistent(plan_l, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
+    }
+    NK_HIP(hipEventRecord(ev1, s));
     st = finish(dst, h, s);
     float ms = 0.0f;
     NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    const int where = large.empty() ? 2 : (small.empty() ? (plan_l.lds ? 1 : 0) : 3);
+    const LaunchPlan &shown = large.empty() ? plan_s : plan_l;
+    stats_record(*h, shown.grid, shown.block, where, ms);
     return st;
 }
 

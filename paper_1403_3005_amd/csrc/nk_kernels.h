@@ -77,6 +77,15 @@ struct KernelRef {
 
 KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds);
 
+// All-in-LDS betweenness kernel for graphs whose CSR and per-source state
+// fit one workgroup's LDS (nk_lds.hip); lds_graph_bytes is its dynamic LDS
+// size for a graph of n vertices and m arcs.
+KernelRef brandes_lds_kernel(int block);
+size_t lds_graph_bytes(int32_t n, int64_t m);
+hipError_t launch_validate_batched(const int32_t *rowptr_cat, const int32_t *colidx_cat, const long long *g_vtx,
+                                   const long long *g_arc, int32_t G, DevStatus *st, hipStream_t s);
+hipError_t launch_reset_head(DevStatus *st, hipStream_t s);
+
 // Small helper launches (all asynchronous on `s`).
 hipError_t launch_status_init(DevStatus *st, hipStream_t s);
 hipError_t launch_validate(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t strict,

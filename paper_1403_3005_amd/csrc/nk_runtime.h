@@ -56,7 +56,8 @@ nk_tuning tuning_get();
 void tuning_set(const nk_tuning &t);
 
 // Per-thread statistics of the last call (nk_last_stats).
-void stats_record(const DevStatus &st, int grid, int block, bool lds, float kernel_ms);
+// lds: 0 global bitmap, 1 bitmap in LDS, 2 whole graph in LDS
+void stats_record(const DevStatus &st, int grid, int block, int lds, float kernel_ms);
 void stats_clear();
 
 // Launch configuration chosen for a persistent Brandes launch.
@@ -74,6 +75,11 @@ struct LaunchPlan {
 // Picks block size, bitmap placement and grid for graphs of at most n_max
 // vertices and `ntasks` tasks.  max_slots > 0 caps the grid.
 nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan);
+
+// All-in-LDS betweenness plan for graphs needing at most `dyn_bytes` of
+// dynamic LDS; returns false (and plans nothing) when they do not fit or
+// tuning flag bit 2 turns the path off.
+bool plan_lds(size_t dyn_bytes, int32_t n_max, long long ntasks, LaunchPlan *plan);
 
 // Allocates per-slot scratch for `plan`, clears the path counts, fills the
 // scratch fields of `p` and launches the persistent kernel on `s`,

@@ -65,10 +65,25 @@ FAMILIES = [
 ]
 
 
+# tuning flag bit 2 turns the all-in-LDS small-graph kernel off, so every
+# small graph below runs on both kernels
+PATHS = [0, 4]
+
+
+def _path_check(flags):
+    st = nk.nk_last_stats()
+    if flags & 4:
+        assert st["bitmap_lds"] in (0, 1)
+    return st
+
+
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("make", FAMILIES)
-def test_exact_families(make):
+def test_exact_families(make, flags):
+    nk.nk_set_tuning(flags=flags)
     g = make()
     assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), g.name)
+    _path_check(flags)
 
 
 RANDOM = [
@@ -80,10 +95,31 @@ RANDOM = [
 ]
 
 
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("make", RANDOM)
-def test_exact_random(make):
+def test_exact_random(make, flags):
+    nk.nk_set_tuning(flags=flags)
     g = make()
     assert_scores_close(_exact(g), oracle.bc_exact(g.rowptr, g.colidx), g.name)
+    _path_check(flags)
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_lds_path_used_and_exact(block):
+    """Graphs that fit one workgroup's LDS run on the all-in-LDS kernel at
+    every block size; results match the oracle on a tile-spanning hub, a
+    700-level path and a random graph."""
+    nk.nk_set_tuning(block=block)
+    for g in (gg.star(2500), gg.path(700), gg.erdos_renyi(2000, 6000, 71), gg.barabasi_albert(1200, 5, 72)):
+        got = _exact(g)
+        st = nk.nk_last_stats()
+        assert st["bitmap_lds"] == 2 and st["block"] == block, g.name
+        assert st["sources"] == g.n
+        assert_scores_close(got, oracle.bc_exact(g.rowptr, g.colidx), g.name)
+        src = gg.sample_sources(g.n, 37, 73)
+        rp, ci = upload(g)
+        got = nk.nk_bc_sources(rp, ci, ivec(src), 2.5).cpu().numpy()
+        assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, 2.5), g.name + " sources")
 
 
 @pytest.mark.parametrize("make", RANDOM + FAMILIES[2:6])
@@ -104,13 +140,14 @@ def test_exact_er2000_full():
 
 @pytest.mark.parametrize("block", [256, 512, 1024])
 @pytest.mark.parametrize("bu_ratio", [0.0, 16.0, 1e9])
-@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("flags", [4, 5, 6])
 @pytest.mark.parametrize("bw_ratio", [0.0, 0.1, 1e9])
 def test_launch_variants(block, bu_ratio, flags, bw_ratio):
-    """Every block size, forward direction policy (never / default / always
-    bottom-up after the first level), backward policy (always pull / default
-    / always push), bitmap placement and vertex order (relabelled or as given)
-    gives the same result."""
+    """Global-memory kernel (the all-in-LDS one is off): every block size,
+    forward direction policy (never / default / always bottom-up after the
+    first level), backward policy (always pull / default / always push),
+    bitmap placement and vertex order (relabelled or as given) gives the
+    same result."""
     nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, wg_per_cu=0, flags=flags, bw_ratio=bw_ratio)
     g = gg.rmat(11, 8, 31)
     src = gg.sample_sources(g.n, 64, 32)
@@ -134,8 +171,10 @@ def test_launch_variants(block, bu_ratio, flags, bw_ratio):
         assert np.array_equal(s[i].cpu().numpy().view(np.uint64), os_)
 
 
-def test_work_counters_match_oracle():
-    nk.nk_set_tuning(block=0, bu_ratio=0.0)  # top-down only: forward arcs = arcs of reached vertices
+@pytest.mark.parametrize("flags", PATHS)
+def test_work_counters_match_oracle(flags):
+    # top-down only (the all-in-LDS kernel always is): forward arcs = arcs of reached vertices
+    nk.nk_set_tuning(block=0, bu_ratio=0.0, flags=flags)
     g = gg.barabasi_albert(3000, 3, 41)
     src = gg.sample_sources(g.n, 100, 42)
     rp, ci = upload(g)
@@ -148,6 +187,7 @@ def test_work_counters_match_oracle():
     assert st["arcs_reached"] == arcs
     assert st["dag_arcs"] == dag
     assert st["levels_td"] == depth + 100  # one extra (empty) expansion per source
+    assert st["bitmap_lds"] == (2 if flags == 0 else 1)
 
 
 def test_sources_forms_and_duplicates():
@@ -314,7 +354,9 @@ def _batched_inputs(graphs):
     return vtx, arc, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
 
 
-def test_batched_small_mixed():
+@pytest.mark.parametrize("flags", PATHS)
+def test_batched_small_mixed(flags):
+    nk.nk_set_tuning(flags=flags)
     sizes = gg.batched_sizes(24, 50, 3000, 111)
     graphs = []
     for i, n in enumerate(sizes):
@@ -326,6 +368,20 @@ def test_batched_small_mixed():
     for i, g in enumerate(graphs):
         assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx), f"graph {i}")
     assert nk.nk_last_stats()["sources"] == int(vtx[-1])
+
+
+def test_batched_split_between_kernels():
+    """A batch holding graphs on both sides of the LDS limit: the small ones
+    run on the all-in-LDS kernel, the large ones on the global kernel, in
+    one call."""
+    graphs = [gg.erdos_renyi(900, 3600, 131), gg.barabasi_albert(9000, 4, 132), gg.path(3),
+              gg.erdos_renyi(12000, 48000, 133), gg.star(700)]
+    vtx, arc, rp, ci = _batched_inputs(graphs)
+    got = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
+    st = nk.nk_last_stats()
+    assert st["bitmap_lds"] == 3 and st["sources"] == int(vtx[-1])
+    for i, g in enumerate(graphs):
+        assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx, nthreads=8), f"graph {i}")
 
 
 def test_pair_isolated_targets():
