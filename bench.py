@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNEL = "k_brandes"
+# nk_last_stats "bitmap_lds" -> which kernel ran
+PLACEMENT = {0: "k_brandes (global bitmap)", 1: "k_brandes (LDS bitmap)", 2: "k_brandes_lds (all in LDS)",
+             3: "k_brandes_lds + k_brandes (LDS bitmap)"}
 
 
 def kernel_source_hash() -> str:
@@ -112,7 +115,8 @@ def other_workload(args) -> dict:
         rec.update(metric="GTEPS, exact Brandes, all sources", unit="GTEPS", dtype="f64",
                    value=round(g.n * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
                    config={"workload": "er2000_exact", "n": g.n, "arcs": g.m, "kernel_ms": st["kernel_us"] / 1e3,
-                           "block": st["block"], "workgroups": st["workgroups"]},
+                           "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"],
+                           "workgroups": st["workgroups"]},
                    cpu_baseline={"value": round(g.n * g.m_undirected / cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
                                  "kind": "oracle", "sample": f"all 2000 sources, {cpu:.2f} s"})
     elif args.workload == "chunglu4m":
@@ -183,6 +187,7 @@ def other_workload(args) -> dict:
                    config={"workload": f"batched{count}", "graphs": count, "n_total": int(vtx[-1]),
                            "arcs_total": int(arc[-1]), "n_range": [1000, hi], "launches": len(groups),
                            "last_launch_kernel_ms": st["kernel_us"] / 1e3,
+                           "kernels": PLACEMENT[st["bitmap_lds"]],
                            "block": st["block"], "workgroups": st["workgroups"]},
                    cpu_baseline={"value": round(sum(g.n * g.m_undirected for g in small) / cpu / 1e9, 4),
                                  "unit": "GTEPS", "cores": 1, "kind": "oracle",
