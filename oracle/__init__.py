@@ -4,8 +4,9 @@ Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package.  The GPU library and its Python binding
 never import it, and nothing here imports them.
 
-``brandes.c`` holds plain sequential Brandes (exact, source set, pair
-sampling) and is loaded through ctypes; ``bruteforce.py`` holds exact
+``brandes.c`` holds plain sequential Brandes (exact, source set, the
+linear-scaling source-set estimator, edge betweenness, pair sampling) and is
+loaded through ctypes; ``bruteforce.py`` holds exact
 rational all-simple-paths enumeration for graphs of at most a dozen
 vertices.  Status codes: 0 ok, -1 invalid argument, -2 invalid graph,
 -3 sigma overflow, -4 out of memory.
@@ -58,6 +59,8 @@ def _load():
         "or_sssp_counts": (c.c_int, g + [c.c_int32, i32p, u64p]),
         "or_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_bc_exact": (c.c_int, g + [f64p, c.c_int32]),
+        "or_bc_sources_linear": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
+        "or_edge_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, f64p, c.c_int32]),
         "or_work_counts": (c.c_int, g + [i32p, c.c_int32, i64p]),
         "or_mix64": (c.c_uint64, [c.c_uint64]),
         "or_draw": (c.c_uint64, [c.c_uint64] * 4),
@@ -139,6 +142,38 @@ def bc_exact(rowptr, colidx, nthreads: int = 1) -> np.ndarray:
     _check(_load().or_bc_exact(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
                                _ptr(bc, ctypes.c_double), nthreads), "bc_exact")
     return bc[:n]
+
+
+def bc_sources_linear(rowptr, colidx, sources, scale: float = 1.0, nthreads: int = 1) -> np.ndarray:
+    """Linear-scaling (Geisberger-Sanders-Schultes) dependencies summed over
+    `sources`, times `scale` (2 n / k gives the estimate of exact scores)."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    bc = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_bc_sources_linear(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                        _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double),
+                                        nthreads), "bc_sources_linear")
+    return bc[:n]
+
+
+def edge_bc(rowptr, colidx, sources=None, scale: float = 1.0, nthreads: int = 1):
+    """(ebc, bc): edge betweenness per arc (both arcs of an edge equal) and
+    vertex betweenness of the same run, over `sources` (default: all
+    vertices, exact), times `scale`."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    ebc = np.zeros(max(m, 1), dtype=np.float64)
+    bc = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_edge_bc_sources(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                      _ptr(src, ctypes.c_int32), k, float(scale), _ptr(ebc, ctypes.c_double),
+                                      _ptr(bc, ctypes.c_double), nthreads), "edge_bc")
+    return ebc[:m], bc[:n]
 
 
 def work_counts(rowptr, colidx, sources):

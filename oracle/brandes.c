@@ -12,6 +12,10 @@
  *   - exact: sum of dependencies over all sources (Table 1, "betweenness");
  *   - source set: sum over a given source list times a scale factor
  *     (Table 1, "ap. betweenness", sampling shortest-path trees);
+ *   - the linear-scaling source-set estimator of Geisberger, Sanders and
+ *     Schultes (the reference cited for that sampling);
+ *   - edge betweenness (section "Edge Centrality, Sparsification and Link
+ *     Prediction");
  *   - pair sampling (Riondato and Kornaropoulos, cited for the epsilon
  *     guarantee in "Heuristics and Approximation Algorithms").
  *
@@ -168,6 +172,67 @@ static int one_source(const graph_t *g, int32_t s, work_t *w, double *bc) {
     return status;
 }
 
+/*
+ * One source of the linear-scaling estimator of Geisberger, Sanders and
+ * Schultes (the "better approximation" the paper cites for betweenness from
+ * sampled shortest-path trees, section "Heuristics and Approximation
+ * Algorithms"): the pair (s, t) adds sigma_st(v) / sigma_st times the
+ * weight d(s, v) / d(s, t) to v.  Because the weight of t splits along the
+ * shortest-path DAG as d(s,v)/d(s,w) * d(s,w)/d(s,t), the accumulation in
+ * reverse visit order becomes
+ *     delta[v] += sigma[v] / sigma[w] * d[v] / d[w] * (1 + delta[w])
+ * for every predecessor v of w, and bc[w] += delta[w] for w != s.
+ */
+static int one_source_linear(const graph_t *g, int32_t s, work_t *w, double *bc) {
+    int32_t nS = 0;
+    int status = forward(g, s, w->d, w->sigma, w->S, &nS, w->queue);
+    if (status == OR_OK) {
+        for (int32_t i = nS - 1; i >= 0; --i) {
+            int32_t x = w->S[i];
+            for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+                int32_t v = g->colidx[e];
+                if (w->d[v] == w->d[x] - 1)
+                    w->delta[v] += (double)w->sigma[v] / (double)w->sigma[x] * ((double)w->d[v] / (double)w->d[x]) *
+                                   (1.0 + w->delta[x]);
+            }
+            if (x != s) bc[x] += w->delta[x];
+        }
+    }
+    work_reset(w, nS);
+    return status;
+}
+
+/*
+ * One source of Brandes' algorithm with edge dependencies (edge
+ * betweenness, named in the section "Edge Centrality, Sparsification and
+ * Link Prediction"): the shortest-path DAG arc v -> w carries
+ *     c = sigma[v] / sigma[w] * (1 + delta[w]),
+ * the share of shortest paths from s to w and beyond that use the edge
+ * {v, w}.  c is added to delta[v] (as in one_source) and to the score slot
+ * of the arc w -> v, which is the arc the accumulation scans; the two arcs
+ * of an edge are summed after all sources.
+ */
+static int one_source_edge(const graph_t *g, int32_t s, work_t *w, double *bc, double *ebc) {
+    int32_t nS = 0;
+    int status = forward(g, s, w->d, w->sigma, w->S, &nS, w->queue);
+    if (status == OR_OK) {
+        for (int32_t i = nS - 1; i >= 0; --i) {
+            int32_t x = w->S[i];
+            for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+                int32_t v = g->colidx[e];
+                if (w->d[v] == w->d[x] - 1) {
+                    double c = (double)w->sigma[v] / (double)w->sigma[x] * (1.0 + w->delta[x]);
+                    w->delta[v] += c;
+                    ebc[e] += c;
+                }
+            }
+            if (x != s && bc) bc[x] += w->delta[x];
+        }
+    }
+    work_reset(w, nS);
+    return status;
+}
+
 /* d (-1 = unreachable) and sigma of every vertex for one source. */
 int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
                    int32_t s, int32_t *d, uint64_t *sigma) {
@@ -185,11 +250,15 @@ int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     return st;
 }
 
+enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2 };
+
 typedef struct {
     const graph_t *g;
     const int32_t *src;
     int32_t lo, hi;
+    int kind;
     double *bc;
+    double *ebc;   /* per-arc accumulators (KIND_EDGE) */
     int status;
 } job_t;
 
@@ -199,7 +268,13 @@ static void *run_job(void *arg) {
     j->status = work_alloc(&w, j->g->n);
     if (j->status == OR_OK) {
         for (int32_t i = j->lo; i < j->hi; ++i) {
-            int st = one_source(j->g, j->src[i], &w, j->bc);
+            int st;
+            if (j->kind == KIND_LINEAR)
+                st = one_source_linear(j->g, j->src[i], &w, j->bc);
+            else if (j->kind == KIND_EDGE)
+                st = one_source_edge(j->g, j->src[i], &w, j->bc, j->ebc);
+            else
+                st = one_source(j->g, j->src[i], &w, j->bc);
             if (st != OR_OK) { j->status = st; break; }
         }
     }
@@ -208,23 +283,22 @@ static void *run_job(void *arg) {
 }
 
 /*
- * Betweenness summed over the sources src[0..k) in the given order
- * (duplicates count twice), then multiplied by `scale`.  nthreads <= 1 runs
- * sequentially; otherwise sources are split into contiguous blocks with a
- * private score array per thread, summed in thread order.
+ * Runs one_source (or a variant) over the sources src[0..k) in the given
+ * order (duplicates count twice).  nthreads <= 1 runs sequentially;
+ * otherwise sources are split into contiguous blocks with private score
+ * arrays per thread, summed in thread order.  bc (n) and ebc (m, KIND_EDGE
+ * only) are overwritten with the unscaled sums.
  */
-int or_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
-                  const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
-    int st = or_validate(n, m, rowptr, colidx);
-    if (st != OR_OK) return st;
-    if (k < 0 || (k > 0 && !src) || (n > 0 && !bc)) return OR_E_INVALID_ARG;
-    for (int32_t i = 0; i < k; ++i)
-        if (src[i] < 0 || src[i] >= n) return OR_E_INVALID_ARG;
+static int run_sources(const graph_t *g, int64_t m, const int32_t *src, int32_t k, int kind, double *bc,
+                       double *ebc, int32_t nthreads) {
+    const int32_t n = g->n;
     for (int32_t i = 0; i < n; ++i) bc[i] = 0.0;
+    if (ebc)
+        for (int64_t e = 0; e < m; ++e) ebc[e] = 0.0;
     if (n == 0 || k == 0) return OR_OK;
-    graph_t g = {n, rowptr, colidx};
+    int st;
     if (nthreads <= 1) {
-        job_t j = {&g, src, 0, k, bc, OR_OK};
+        job_t j = {g, src, 0, k, kind, bc, ebc, OR_OK};
         run_job(&j);
         st = j.status;
     } else {
@@ -233,17 +307,22 @@ int or_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *co
         pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
         if (!jobs || !th) { free(jobs); free(th); return OR_E_NO_MEMORY; }
         for (int32_t t = 0; t < nthreads; ++t) {
-            jobs[t].g = &g;
+            jobs[t].g = g;
             jobs[t].src = src;
             jobs[t].lo = (int32_t)((int64_t)k * t / nthreads);
             jobs[t].hi = (int32_t)((int64_t)k * (t + 1) / nthreads);
+            jobs[t].kind = kind;
             jobs[t].bc = (double *)calloc((size_t)n, sizeof(double));
-            jobs[t].status = jobs[t].bc ? OR_OK : OR_E_NO_MEMORY;
+            jobs[t].ebc = ebc ? (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double)) : NULL;
+            jobs[t].status = (jobs[t].bc && (!ebc || jobs[t].ebc)) ? OR_OK : OR_E_NO_MEMORY;
         }
+        char *started = (char *)calloc((size_t)nthreads, 1);
         for (int32_t t = 0; t < nthreads; ++t)
-            if (jobs[t].status == OR_OK) pthread_create(&th[t], NULL, run_job, &jobs[t]);
+            if (started && jobs[t].status == OR_OK) started[t] = pthread_create(&th[t], NULL, run_job, &jobs[t]) == 0;
         for (int32_t t = 0; t < nthreads; ++t)
-            if (jobs[t].bc) pthread_join(th[t], NULL);
+            if (started && started[t]) pthread_join(th[t], NULL);
+            else if (jobs[t].status == OR_OK) jobs[t].status = OR_E_NO_MEMORY;
+        free(started);
         st = OR_OK;
         for (int32_t t = 0; t < nthreads; ++t) {
             if (jobs[t].status != OR_OK && st == OR_OK) st = jobs[t].status;
@@ -251,13 +330,97 @@ int or_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *co
                 for (int32_t i = 0; i < n; ++i) bc[i] += jobs[t].bc[i];
                 free(jobs[t].bc);
             }
+            if (jobs[t].ebc) {
+                for (int64_t e = 0; e < m; ++e) ebc[e] += jobs[t].ebc[e];
+                free(jobs[t].ebc);
+            }
         }
         free(jobs);
         free(th);
     }
+    return st;
+}
+
+static int check_sources(int32_t n, const int32_t *src, int32_t k) {
+    if (k < 0 || (k > 0 && !src)) return OR_E_INVALID_ARG;
+    for (int32_t i = 0; i < k; ++i)
+        if (src[i] < 0 || src[i] >= n) return OR_E_INVALID_ARG;
+    return OR_OK;
+}
+
+/*
+ * Betweenness summed over the sources src[0..k) in the given order
+ * (duplicates count twice), then multiplied by `scale`.
+ */
+int or_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                  const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n > 0 && !bc) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    st = run_sources(&g, m, src, k, KIND_PLAIN, bc, NULL, nthreads);
     if (st == OR_OK && scale != 1.0)
         for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
     return st;
+}
+
+/*
+ * Linear-scaling estimator over the sources src[0..k): the sum of
+ * one_source_linear dependencies times `scale`.  Summed over every vertex
+ * as a source it is half of exact betweenness, so the unbiased estimate
+ * from k sampled sources uses scale = 2 n / k.
+ */
+int or_bc_sources_linear(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                         const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n > 0 && !bc) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    st = run_sources(&g, m, src, k, KIND_LINEAR, bc, NULL, nthreads);
+    if (st == OR_OK && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return st;
+}
+
+/*
+ * Edge betweenness over the sources src[0..k): ebc[e] for the arc e = u->v
+ * is the score of the undirected edge {u, v} -- the sum over the sources
+ * and every target t of the share of shortest s-t paths using the edge --
+ * times `scale`; both arcs of an edge hold the same value.  bc (optional)
+ * receives the vertex scores of the same run, times `scale`.  Needs the
+ * reverse of every arc (OR_E_INVALID_GRAPH otherwise).
+ */
+int or_edge_bc_sources(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                       const int32_t *src, int32_t k, double scale, double *ebc, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (m > 0 && !ebc) return OR_E_INVALID_ARG;
+    double *vb = bc ? bc : (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!vb) return OR_E_NO_MEMORY;
+    graph_t g = {n, rowptr, colidx};
+    st = run_sources(&g, m, src, k, KIND_EDGE, vb, ebc, nthreads);
+    if (!bc) free(vb);
+    if (st != OR_OK) return st;
+    /* an edge's score is the sum over its two arcs */
+    for (int32_t u = 0; u < n; ++u) {
+        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+            int32_t v = colidx[e];
+            if (v <= u) continue;
+            int32_t r = -1;
+            for (int32_t f = rowptr[v]; f < rowptr[v + 1]; ++f)
+                if (colidx[f] == u) { r = f; break; }
+            if (r < 0) return OR_E_INVALID_GRAPH;
+            double tot = (ebc[e] + ebc[r]) * scale;
+            ebc[e] = tot;
+            ebc[r] = tot;
+        }
+    }
+    if (bc && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return OR_OK;
 }
 
 /* Exact betweenness: every vertex is a source, in order 0..n-1. */

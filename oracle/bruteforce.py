@@ -63,3 +63,41 @@ def brute_force(rowptr, colidx):
             if through[v]:
                 bc[v] += Fraction(through[v], len(ps))
     return d, sigma, bc
+
+
+def linear_dependencies(rowptr, colidx, sources):
+    """Sum over s in `sources` and every t != s of sigma_st(v) / sigma_st *
+    d(s, v) / d(s, t), as exact Fractions: the linear-scaling estimator of
+    Geisberger, Sanders and Schultes written out from its definition (each
+    shortest s-t path through v weighted by v's relative distance from s)."""
+    n = len(rowptr) - 1
+    paths = all_pairs_paths(rowptr, colidx)
+    out = [Fraction(0)] * n
+    for s in sources:
+        for t in range(n):
+            ps = paths.get((s, t))
+            if not ps:
+                continue
+            dst = len(ps[0]) - 1
+            for p in ps:
+                for pos, v in enumerate(p[1:-1], start=1):
+                    out[v] += Fraction(pos, dst) / len(ps)
+    return out
+
+
+def edge_betweenness(rowptr, colidx):
+    """dict {(u, v): Fraction} with u < v: over ordered pairs (s, t), the
+    share of shortest s-t paths that use the edge {u, v}."""
+    paths = all_pairs_paths(rowptr, colidx)
+    out = {}
+    n = len(rowptr) - 1
+    for u in range(n):
+        for e in range(int(rowptr[u]), int(rowptr[u + 1])):
+            v = int(colidx[e])
+            if u < v:
+                out[(u, v)] = Fraction(0)
+    for (s, t), ps in paths.items():
+        for p in ps:
+            for a, b in zip(p[:-1], p[1:]):
+                out[(min(a, b), max(a, b))] += Fraction(1, len(ps))
+    return out
