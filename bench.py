@@ -54,19 +54,28 @@ def counter_traffic(workload: str):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0):
+def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = "plain"):
     """The oracle (plain Brandes, the paper's per-thread-array parallel
-    pattern) on a bounded prefix of the same source list."""
+    pattern; or its linear-scaling / edge form) on a bounded prefix of the
+    same source list."""
     import oracle
+
+    def run(sources, threads):
+        if kind == "linear":
+            oracle.bc_sources_linear(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
+        elif kind == "edge":
+            oracle.edge_bc(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
+        else:
+            oracle.bc_sources(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
 
     threads = max(1, min(16, os.cpu_count() or 1))
     probe = 16
     t0 = time.perf_counter()
-    oracle.bc_sources(g.rowptr, g.colidx, src[:probe], 1.0, nthreads=1)
+    run(src[:probe], 1)
     per_source = max((time.perf_counter() - t0) / probe, 1e-4)
     k = int(max(threads, min(len(src), int(target_s * threads / per_source) // threads * threads)))
     t0 = time.perf_counter()
-    oracle.bc_sources(g.rowptr, g.colidx, src[:k], 1.0, nthreads=threads)
+    run(src[:k], threads)
     dt = time.perf_counter() - t0
     return {
         "value": k * n_undirected / dt / 1e9,
@@ -103,7 +112,32 @@ def other_workload(args) -> dict:
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     rec = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
-    if args.workload == "er2000":
+    if args.workload in ("rmat20_linear", "rmat20_edge"):
+        print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
+        g, src = gg.workload_rmat20(2)
+        rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
+        k = len(src)
+        bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        if args.workload == "rmat20_linear":
+            scale = 2.0 * g.n / k
+            sec = _timed(lambda: nk.nk_bc_sources_linear(rp, ci, sv, scale, bc=bc), args.steps, args.warmup)
+            metric = "GTEPS, linear-scaling (Geisberger-Sanders-Schultes) source-sampled betweenness"
+        else:
+            scale = g.n / k
+            sec = _timed(lambda: nk.nk_edge_bc(rp, ci, sv, scale), args.steps, args.warmup)
+            metric = "GTEPS, source-sampled edge and vertex betweenness"
+        st = nk.nk_last_stats()
+        rec.update(metric=metric, unit="GTEPS", dtype="f64", value=round(k * g.m_undirected / sec / 1e9, 3),
+                   ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": args.workload + "_sources4096", "n": g.n, "arcs": g.m, "sources": k,
+                           "scale": scale, "kernel_ms": st["kernel_us"] / 1e3,
+                           "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"],
+                           "workgroups": st["workgroups"], "levels_bw_push": st["levels_bw_push"]})
+        if not args.no_cpu_baseline:
+            print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+            rec["cpu_baseline"] = cpu_baseline(g, src, g.m_undirected,
+                                               kind="linear" if args.workload == "rmat20_linear" else "edge")
+    elif args.workload == "er2000":
         g = gg.workload_er2000(1)
         rp, ci = up(g.rowptr), up(g.colidx)
         bc = torch.empty(g.n, dtype=torch.float64, device=dev)
@@ -240,7 +274,8 @@ def main():
     ap.add_argument("--serving-qps", type=float, default=8.0)
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64"],
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear",
+                             "rmat20_edge"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -111,6 +111,42 @@ nk_status nk_bc_sources(const int32_t *rowptr, const int32_t *colidx, int32_t n,
                         const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
 
 /*
+ * Linear-scaling estimator of Geisberger, Sanders and Schultes (the
+ * reference the paper cites for approximating betweenness from a few
+ * shortest-path trees, "Heuristics and Approximation Algorithms"): every
+ * pair (s, t) with s in the source list adds sigma_st(v) / sigma_st times
+ * d(s, v) / d(s, t) to v, so vertices near the sampled sources are not
+ * over-counted.  Summed over every vertex as a source this is half of
+ * exact betweenness; scale = 2 n / k gives the estimate of the exact
+ * (ordered-pair) scores.
+ *   sources  int32[k] DEVICE array as for nk_bc_sources (NULL with k = n:
+ *            every vertex);
+ *   bc       FP64[n] DEVICE, overwritten.
+ * Same errors as nk_bc_sources.
+ */
+nk_status nk_bc_sources_linear(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
+
+/*
+ * Edge betweenness (section "Edge Centrality, Sparsification and Link
+ * Prediction"): for the undirected edge {u, v}, the sum over ordered pairs
+ * (s, t), s in the source list, of the share of shortest s-t paths that
+ * use the edge, times `scale`.
+ *   sources  int32[k] DEVICE array, or NULL with k = n for every vertex
+ *            (exact edge betweenness);
+ *   ebc      FP64[m] DEVICE, overwritten: ebc[e] for arc e = u -> v holds
+ *            the score of edge {u, v}; both arcs of an edge hold the same
+ *            value;
+ *   bc       FP64[n] DEVICE or NULL: the vertex scores of the same run,
+ *            times `scale`.
+ * Needs the reverse of every arc and ascending adjacency (the CSR rules
+ * above); a missing reverse arc is NK_E_INVALID_GRAPH.  Runs under the
+ * caller's vertex ids (no internal relabelling).
+ */
+nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
+                     int32_t k, double scale, double *ebc, double *bc, void *stream);
+
+/*
  * Forward phase only, for inspection: distance and shortest-path count from
  * each of k sources (the breadth-first search with path counting that
  * Brandes' algorithm runs per source).

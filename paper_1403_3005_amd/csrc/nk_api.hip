@@ -520,9 +520,12 @@ static nk_status prepare_graph(const int32_t *rowptr, const int32_t *colidx, int
     return relabel_graph(rowptr, colidx, n, m, dst, scr, s, g);
 }
 
-// Shared body of nk_bc_exact / nk_bc_sources.
+// Shared body of nk_bc_exact / nk_bc_sources / nk_bc_sources_linear /
+// nk_edge_bc.  linear selects the linear-scaling estimator; ebc != NULL
+// also computes edge scores (global kernel, graph under its own ids).
 static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
-                                 const int32_t *sources, long long k, double scale, double *bc, void *stream) {
+                                 const int32_t *sources, long long k, double scale, double *bc, void *stream,
+                                 int linear = 0, double *ebc = nullptr) {
     clear_error();
     stats_clear();
     nk_status st = check_graph_args(rowptr, colidx, n, m);
@@ -543,10 +546,11 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     NK_HIP(launch_status_init(dst, s));
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
     NK_HIP(launch_fill_f64(bc, 0.0, n, s));
+    if (ebc) NK_HIP(launch_fill_f64(ebc, 0.0, m, s));
     LaunchPlan plan = {};
     float ms = 0.0f;
     int where = 0;
-    if (k > 0 && plan_lds(lds_graph_bytes(n, m), n, k, &plan)) {
+    if (k > 0 && !ebc && plan_lds(lds_graph_bytes(n, m), n, k, &plan)) {
         // the whole graph fits one workgroup's LDS: no relabelling, no scratch
         Params p;
         memset(&p, 0, sizeof(p));
@@ -558,6 +562,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.sources = sources;
         p.bc = bc;
         p.st = dst;
+        p.linear = linear;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         NK_HIP(hipEventRecord(ev0, s));
@@ -570,8 +575,10 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         where = 2;
     } else if (k > 0) {
         where = -1;
-        Relabeled g;
-        if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        Relabeled g = {rowptr, colidx, nullptr, nullptr};
+        // edge scores are kept per arc of the caller's CSR, so that run keeps its ids
+        if (!ebc)
+            if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
         NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
         const int32_t *src = sources;
         double *acc = bc;
@@ -597,6 +604,8 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.bc = acc;
         p.iso = iso;
         p.st = dst;
+        p.linear = linear;
+        p.ebc = ebc;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
@@ -604,6 +613,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
             NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
         else if (scale != 1.0)
             NK_HIP(launch_scale_f64(bc, scale, n, s));
+        if (ebc) NK_HIP(launch_edge_symmetrize(rowptr, colidx, n, ebc, scale, dst, s));
         st = finish(dst, h, s);
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     } else {
@@ -626,6 +636,38 @@ nk_status nk_bc_sources(const int32_t *rowptr, const int32_t *colidx, int32_t n,
         return fail(NK_E_INVALID_ARG, "sources is NULL");
     }
     return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream);
+}
+
+nk_status nk_bc_sources_linear(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double scale, double *bc, void *stream) {
+    if (k > 0 && !sources && k != n) {
+        clear_error();
+        return fail(NK_E_INVALID_ARG, "sources is NULL");
+    }
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, 1);
+}
+
+nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
+                     int32_t k, double scale, double *ebc, double *bc, void *stream) {
+    clear_error();
+    if (k > 0 && !sources && k != n) return fail(NK_E_INVALID_ARG, "sources is NULL");
+    if (m > 0 && !ebc) return fail(NK_E_INVALID_ARG, "ebc is NULL");
+    if (n < 0) return fail(NK_E_INVALID_ARG, "n = %d is negative", n);
+    if (n == 0) {
+        stats_clear();
+        return NK_OK;
+    }
+    double *vb = bc;
+    Scratch scr;
+    if (!vb) {
+        nk_status st = scr.get(n, &vb);
+        if (st != NK_OK) return st;
+    }
+    if (m == 0) {
+        // no arcs: every score is zero (the edge array is empty)
+        return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, vb, stream);
+    }
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, vb, stream, 0, ebc);
 }
 
 nk_status nk_sssp_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,

@@ -67,6 +67,12 @@ struct Params {
     float bu_ratio;
     float bw_ratio;
     DevStatus *st;
+    // estimator variants (BC mode): linear != 0 weights each pair (s, t)
+    // by d(s, v) / d(s, t) (linear scaling); ebc != NULL also accumulates
+    // the per-arc edge terms (single graph, pull sweep down to level 0)
+    int32_t linear;
+    int32_t pad1;
+    double *ebc;
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.
@@ -85,6 +91,10 @@ size_t lds_graph_bytes(int32_t n, int64_t m);
 hipError_t launch_validate_batched(const int32_t *rowptr_cat, const int32_t *colidx_cat, const long long *g_vtx,
                                    const long long *g_arc, int32_t G, DevStatus *st, hipStream_t s);
 hipError_t launch_reset_head(DevStatus *st, hipStream_t s);
+// Edge scores: ebc[e] = ebc[rev(e)] = (ebc[e] + ebc[rev(e)]) * scale for
+// every arc; a missing reverse arc raises kErrGraph.
+hipError_t launch_edge_symmetrize(const int32_t *rowptr, const int32_t *colidx, int32_t n, double *ebc,
+                                  double scale, DevStatus *st, hipStream_t s);
 
 // Small helper launches (all asynchronous on `s`).
 hipError_t launch_status_init(DevStatus *st, hipStream_t s);

@@ -401,7 +401,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
 // (= level l+1) neighbours.
 template <int BLOCK>
 __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
-                        double *bcg, Counters &c) {
+                        double *bcg, double wfac, double *ebc, bool add_bc, Counters &c) {
     const int tid = threadIdx.x;
     sub_start<BLOCK>(sm);
     for (int32_t tb = lo; tb < hi; tb += BLOCK) {
@@ -418,6 +418,17 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 #pragma unroll
             for (int j = 0; j < kChunk; ++j)
                 cf[j] = (kk[j] >= 0 && !bit_test(bm, w[j])) ? as_f64(s.sigma[w[j]]) : 0.0;
+            if (ebc) {
+                // edge term of the DAG arc v -> w: sigma_v * (1 + delta_w) / sigma_w
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    if (cf[j] != 0.0) {
+                        const int32_t k = kk[j];
+                        const double sv = (double)s.sigma[sm.v[k]];
+                        atomicAdd(ebc + sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]), sv * cf[j]);
+                    }
+                }
+            }
             int32_t kcur = kk[0];
             double acc = 0.0;
 #pragma unroll
@@ -437,9 +448,9 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
         if (tid < cnt) {
             const int32_t v = sm.v[tid];
             const double sg = (double)s.sigma[v];
-            const double delta = sg * sm.val.f[tid];
+            const double delta = sg * sm.val.f[tid] * wfac;
             s.sigma[v] = as_u64((1.0 + delta) / sg);
-            if (delta != 0.0) atomicAdd(bcg + v, delta);
+            if (add_bc && delta != 0.0) atomicAdd(bcg + v, delta);
         }
         __syncthreads();
         sub_mark<BLOCK>(sm, kSbPlFin);
@@ -451,7 +462,7 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // level l (list[lo, hi)) takes delta_v = sigma_v * dacc[v] and clears dacc.
 template <int BLOCK>
 __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
-                        int32_t lo1, int32_t hi1, double *bcg, Counters &c) {
+                        int32_t lo1, int32_t hi1, double *bcg, double wfac, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t tb = lo1; tb < hi1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, hi1 - tb);
@@ -471,7 +482,7 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
     for (int32_t i = lo + tid; i < hi; i += BLOCK) {
         const int32_t v = s.lv[i];
         const double sg = (double)s.sigma[v];
-        const double delta = sg * s.dacc[v];
+        const double delta = sg * s.dacc[v] * wfac;
         s.dacc[v] = 0.0;
         s.sigma[v] = as_u64((1.0 + delta) / sg);
         if (delta != 0.0) atomicAdd(bcg + v, delta);
@@ -493,16 +504,22 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         }
     }
     __syncthreads();
-    for (int32_t l = Ld - 1; l >= 1; --l) {
+    // edge scores need the source's own arcs too: sweep down to level 0
+    // (the source's dependency is not a score and is not added)
+    const int32_t lmin = p.ebc ? 0 : 1;
+    for (int32_t l = Ld - 1; l >= lmin; --l) {
         const int32_t lo = s.lvl[l], hi = s.lvl[l + 1], hi1 = s.lvl[l + 2];
+        // linear scaling: the pair weights d(s,v)/d(s,t) factor as l/(l+1)
+        // per DAG step from level l+1 to level l
+        const double wfac = p.linear ? (double)l / (double)(l + 1) : 1.0;
         // scan whichever side of the level pair has fewer arcs
-        const bool push = (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
+        const bool push = !p.ebc && (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
         phase_start<BLOCK>(sm);
         if (push) {
             if (tid == 0) c.bw_push++;
-            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, c);
+            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, c);
         } else {
-            bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, c);
+            bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, wfac, p.ebc, l >= 1, c);
         }
         if (push) phase_end<BLOCK>(sm, kPhPush); else phase_end<BLOCK>(sm, kPhPull);
         for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);

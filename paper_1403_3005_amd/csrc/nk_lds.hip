@@ -210,6 +210,8 @@ __device__ void lds_source(const Params &p, Tile<BLOCK> &sm, const LdsGraph &L, 
     __syncthreads();
     for (int32_t l = Ld - 1; l >= 1; --l) {
         const int32_t lo = L.lvl[l], hi = L.lvl[l + 1];
+        // linear scaling: pair weights d(s,v)/d(s,t) factor as l/(l+1) per DAG step
+        const double wfac = p.linear ? (double)l / (double)(l + 1) : 1.0;
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
             if (tid < cnt) sm.val.f[tid] = 0.0;
@@ -239,7 +241,7 @@ __device__ void lds_source(const Params &p, Tile<BLOCK> &sm, const LdsGraph &L, 
             if (tid < cnt) {
                 const int32_t v = sm.v[tid];
                 const double sg = (double)L.sig[v];
-                const double delta = sg * sm.val.f[tid];
+                const double delta = sg * sm.val.f[tid] * wfac;
                 L.sig[v] = lu64((1.0 + delta) / sg);
                 if (delta != 0.0) atomicAdd(bcg + v, delta);
             }
@@ -354,6 +356,40 @@ __global__ void k_validate_batched(const int32_t *rowptr_cat, const int32_t *col
     if (bad) atomicOr(&st->err, kErrGraph);
 }
 
+// One thread per arc e = u -> v with u < v: finds the reverse arc by binary
+// search in v's ascending adjacency and writes the scaled sum to both.
+__global__ void k_edge_symmetrize(const int32_t *rowptr, const int32_t *colidx, int32_t n, double *ebc, double scale,
+                                  DevStatus *st) {
+    if (st->err & kErrGraph) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long m = rowptr[n];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        // tail u of arc e: the last u with rowptr[u] <= e
+        int32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int32_t u = lo, v = colidx[e];
+        if (v <= u) continue;
+        int32_t a = rowptr[v], b = rowptr[v + 1] - 1;
+        int32_t r = -1;
+        while (a <= b) {
+            const int32_t mid = (a + b) >> 1;
+            const int32_t x = colidx[mid];
+            if (x == u) { r = mid; break; }
+            if (x < u) a = mid + 1; else b = mid - 1;
+        }
+        if (r < 0) {
+            atomicOr(&st->err, kErrGraph);
+            continue;
+        }
+        const double tot = (ebc[e] + ebc[r]) * scale;
+        ebc[e] = tot;
+        ebc[r] = tot;
+    }
+}
+
 __global__ void k_reset_head(DevStatus *st) {
     if (threadIdx.x == 0) st->head = 0ULL;
 }
@@ -377,6 +413,13 @@ hipError_t launch_validate_batched(const int32_t *rowptr_cat, const int32_t *col
                                    const long long *g_arc, int32_t G, DevStatus *st, hipStream_t s) {
     if (G <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_validate_batched, dim3(G, 16), dim3(256), 0, s, rowptr_cat, colidx_cat, g_vtx, g_arc, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_symmetrize(const int32_t *rowptr, const int32_t *colidx, int32_t n, double *ebc,
+                                  double scale, DevStatus *st, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_symmetrize, dim3(1024), dim3(256), 0, s, rowptr, colidx, n, ebc, scale, st);
     return hipGetLastError();
 }
 

@@ -1,0 +1,125 @@
+"""GPU parity of the linear-scaling estimator and of edge betweenness
+against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_1403_3005_amd as nk
+from nkutil import assert_scores_close, ivec, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _default_tuning():
+    nk.nk_set_tuning()
+    yield
+    nk.nk_set_tuning()
+
+
+GRAPHS = [
+    lambda: gg.path(300), lambda: gg.star(2500), lambda: gg.cycle(257), lambda: gg.grid(20, 27),
+    lambda: gg.complete_bipartite(5, 200), lambda: gg.random_tree(3000, 9), lambda: gg.erdos_renyi(2500, 6000, 81),
+    lambda: gg.barabasi_albert(4000, 4, 82), lambda: gg.rmat(12, 16, 83),
+    lambda: gg.disjoint_union([gg.grid(6, 7), gg.star(50), gg.path(1), gg.cycle(9), gg.complete(5)]),
+]
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+@pytest.mark.parametrize("make", GRAPHS)
+def test_linear_exact_sources(make, flags):
+    """All sources and a sampled set, on the all-in-LDS kernel where the
+    graph fits (flags 0) and on the global kernel (flags 4)."""
+    nk.nk_set_tuning(flags=flags)
+    g = make()
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_linear(rp, ci, None, 2.0).cpu().numpy()
+    ref = oracle.bc_sources_linear(g.rowptr, g.colidx, np.arange(g.n), 2.0, nthreads=8)
+    assert_scores_close(got, ref, g.name + " all")
+    k = min(g.n, 97)
+    src = gg.sample_sources(g.n, k, 84)
+    got = nk.nk_bc_sources_linear(rp, ci, ivec(src), 2.0 * g.n / k).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources_linear(g.rowptr, g.colidx, src, 2.0 * g.n / k), g.name + " sampled")
+
+
+def test_linear_all_sources_is_half_of_exact_on_gpu():
+    g = gg.barabasi_albert(3000, 3, 85)
+    rp, ci = upload(g)
+    lin = nk.nk_bc_sources_linear(rp, ci, None, 2.0).cpu().numpy()
+    assert_scores_close(lin, nk.nk_bc_exact(rp, ci).cpu().numpy(), "2 x linear vs exact")
+
+
+@pytest.mark.parametrize("block", [256, 1024])
+@pytest.mark.parametrize("bu_ratio", [0.0, 1e9])
+@pytest.mark.parametrize("bw_ratio", [0.0, 1e9])
+def test_linear_launch_variants(block, bu_ratio, bw_ratio):
+    """The level weight is applied in both the pull and the push sweep."""
+    nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, bw_ratio=bw_ratio, flags=4)
+    g = gg.rmat(11, 8, 86)
+    src = gg.sample_sources(g.n, 64, 87)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_linear(rp, ci, ivec(src), g.n / 32).cpu().numpy()
+    st = nk.nk_last_stats()
+    if bw_ratio > 1:
+        assert st["levels_bw_push"] > 0
+    assert_scores_close(got, oracle.bc_sources_linear(g.rowptr, g.colidx, src, g.n / 32), "linear variant")
+
+
+def test_linear_rmat14_sampled_relabelled():
+    g = gg.rmat(14, 16, 88)
+    src = gg.sample_sources(g.n, 256, 89)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_linear(rp, ci, ivec(src), 2.0 * g.n / 256).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources_linear(g.rowptr, g.colidx, src, 2.0 * g.n / 256, nthreads=8),
+                        "rmat14 linear")
+
+
+@pytest.mark.parametrize("make", GRAPHS)
+def test_edge_exact(make):
+    g = make()
+    rp, ci = upload(g)
+    ebc, bc = nk.nk_edge_bc(rp, ci)
+    oe, ob = oracle.edge_bc(g.rowptr, g.colidx, nthreads=8)
+    assert_scores_close(ebc.cpu().numpy(), oe, g.name + " edges")
+    assert_scores_close(bc.cpu().numpy(), ob, g.name + " vertices")
+
+
+@pytest.mark.parametrize("bu_ratio", [0.0, 16.0, 1e9])
+def test_edge_sampled_sources(bu_ratio):
+    nk.nk_set_tuning(bu_ratio=bu_ratio, bw_ratio=1e9)  # the edge sweep always pulls
+    g = gg.rmat(13, 16, 90)
+    src = gg.sample_sources(g.n, 200, 91)
+    rp, ci = upload(g)
+    ebc, bc = nk.nk_edge_bc(rp, ci, ivec(src), g.n / 200)
+    assert nk.nk_last_stats()["levels_bw_push"] == 0
+    oe, ob = oracle.edge_bc(g.rowptr, g.colidx, src, g.n / 200, nthreads=8)
+    assert_scores_close(ebc.cpu().numpy(), oe, "rmat13 edges")
+    assert_scores_close(bc.cpu().numpy(), ob, "rmat13 vertices")
+
+
+def test_edge_edge_cases_and_errors():
+    # no arcs
+    g = gg.Graph(20, np.zeros(21, dtype=np.int32), np.zeros(0, dtype=np.int32))
+    rp, ci = upload(g)
+    ebc, bc = nk.nk_edge_bc(rp, ci)
+    assert ebc.numel() == 0 and not bc.any()
+    # no sources
+    g = gg.cycle(12)
+    rp, ci = upload(g)
+    ebc, bc = nk.nk_edge_bc(rp, ci, torch.zeros(0, dtype=torch.int32, device="cuda:0"))
+    assert not ebc.any() and not bc.any()
+    # a missing reverse arc
+    rowptr = torch.tensor([0, 1, 1], dtype=torch.int32, device="cuda:0")
+    colidx = torch.tensor([1], dtype=torch.int32, device="cuda:0")
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_edge_bc(rowptr, colidx)
+    assert e.value.code == nk.NK_E_INVALID_GRAPH
+    # sources out of range
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_edge_bc(rp, ci, ivec([0, 12]))
+    assert e.value.code == nk.NK_E_INVALID_ARG
+    # the library still works
+    ebc, _ = nk.nk_edge_bc(rp, ci)
+    assert_scores_close(ebc.cpu().numpy(), oracle.edge_bc(g.rowptr, g.colidx)[0], "cycle after errors")
