@@ -605,41 +605,193 @@ static void pair_of(uint64_t seed, int64_t j, int32_t n, int32_t *u, int32_t *v)
 }
 
 /*
- * One sample: shortest-path counting BFS from u (forward phase above), then
- * a walk from v back to u.  At vertex w (step t) draw x = bounded(draw(seed,
- * 3, j, t), sigma[w]) and take the first predecessor p, in adjacency order,
- * whose running sum of sigma over predecessors exceeds x: p is chosen with
- * probability sigma[p] / sigma[w], so the path is uniform among the
- * shortest u-v paths.  Interior vertices are written to `interior`
- * (from v's side towards u).  Returns the number of interior vertices, -1
- * if v is unreachable from u, or OR_E_SIGMA_OVERFLOW - 100 on overflow.
+ * One side of the bidirectional search: distances d (-1 = not reached),
+ * path counts sigma from the side's root, its visit order S with level
+ * bounds lvl[0..depth+1].
  */
-static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u, int32_t v,
-                          work_t *w, int32_t *interior) {
-    int32_t nS;
-    int st = forward(g, u, w->d, w->sigma, w->S, &nS, w->queue);
-    int32_t len = 0;
-    if (st != OR_OK) { work_reset(w, nS); return OR_E_SIGMA_OVERFLOW - 100; }
-    if (w->d[v] < 0) { work_reset(w, nS); return -1; }
-    int32_t x = v;
+typedef struct {
+    int32_t *d;
+    uint64_t *sigma;
+    int32_t *S;
+    int32_t *lvl;     /* level l occupies S[lvl[l] .. lvl[l+1]) */
+    int32_t depth;    /* deepest complete level */
+    int64_t cost;     /* arcs leaving the deepest level */
+} side_t;
+
+/* Expands side x by one level: every arc y -> z out of level depth with z
+ * not yet reached by x adds sigma[y] to sigma[z]; the new level lists the
+ * new vertices in visit order.  Returns the number of new vertices, or -1
+ * on a path-count overflow. */
+static int32_t expand_level(const graph_t *g, side_t *x) {
+    int32_t lo = x->lvl[x->depth], hi = x->lvl[x->depth + 1], tail = hi;
+    int overflow = 0;
+    for (int32_t i = lo; i < hi; ++i) {
+        int32_t y = x->S[i];
+        for (int32_t e = g->rowptr[y]; e < g->rowptr[y + 1]; ++e) {
+            int32_t z = g->colidx[e];
+            if (x->d[z] < 0) {
+                x->d[z] = x->depth + 1;
+                x->S[tail++] = z;
+            }
+            if (x->d[z] == x->depth + 1) {
+                uint64_t sum;
+                if (__builtin_add_overflow(x->sigma[z], x->sigma[y], &sum)) overflow = 1;
+                x->sigma[z] = sum;
+            }
+        }
+    }
+    x->depth += 1;
+    x->lvl[x->depth + 1] = tail;
+    int64_t cost = 0;
+    for (int32_t i = hi; i < tail; ++i) cost += g->rowptr[x->S[i] + 1] - g->rowptr[x->S[i]];
+    x->cost = cost;
+    return overflow ? -1 : tail - hi;
+}
+
+static void side_start(const graph_t *g, side_t *x, int32_t root) {
+    x->d[root] = 0;
+    x->sigma[root] = 1;
+    x->S[0] = root;
+    x->lvl[0] = 0;
+    x->lvl[1] = 1;
+    x->depth = 0;
+    x->cost = g->rowptr[root + 1] - g->rowptr[root];
+}
+
+static void side_reset(side_t *x) {
+    for (int32_t i = 0; i < x->lvl[x->depth + 1]; ++i) {
+        x->d[x->S[i]] = -1;
+        x->sigma[x->S[i]] = 0;
+    }
+}
+
+/* Walks from `from` to the side's root: at w (step t) draws
+ * r = bounded(draw(seed, stream, j, t), sigma[w]) and takes the first
+ * neighbour p one level closer to the root, in adjacency order, whose
+ * running sigma sum exceeds r (so p has probability sigma[p] / sigma[w]).
+ * Writes the vertices strictly between `from` and the root to out in walk
+ * order and returns their number. */
+static int32_t walk_to_root(const graph_t *g, const side_t *x, int32_t from, uint64_t seed, uint64_t stream,
+                            int64_t j, int32_t *out) {
+    int32_t w = from, len = 0;
     uint64_t t = 0;
-    while (x != u) {
-        uint64_t r = or_bounded(or_draw(seed, 3, (uint64_t)j, t), w->sigma[x]);
+    while (x->d[w] > 0) {
+        uint64_t r = or_bounded(or_draw(seed, stream, (uint64_t)j, t), x->sigma[w]);
         uint64_t acc = 0;
         int32_t pick = -1;
-        for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+        for (int32_t e = g->rowptr[w]; e < g->rowptr[w + 1]; ++e) {
             int32_t p = g->colidx[e];
-            if (w->d[p] == w->d[x] - 1) {
-                acc += w->sigma[p];
+            if (x->d[p] == x->d[w] - 1) {
+                acc += x->sigma[p];
                 if (acc > r) { pick = p; break; }
             }
         }
-        if (pick != u) interior[len++] = pick;
-        x = pick;
+        if (x->d[pick] > 0) out[len++] = pick;
+        w = pick;
         ++t;
     }
-    work_reset(w, nS);
     return len;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * One sample: a uniformly random shortest u-v path, found by a balanced
+ * bidirectional breadth-first search with path counting.
+ *
+ * Search: side A grows from u, side B from v, one whole level at a time;
+ * the side whose deepest level has fewer leaving arcs grows next (A on
+ * ties).  The first time a new level of one side contains vertices already
+ * reached by the other side, those vertices M are exactly the vertices at
+ * distance d_A(z) from u on shortest u-v paths (every vertex of M has the
+ * other side's deepest distance), and sigma_uv = sum over z in M of
+ * sigma_A(z) * sigma_B(z).  A side whose new level is empty has exhausted
+ * its component: v is unreachable.
+ *
+ * Path: z in M is taken with probability sigma_A(z) sigma_B(z) / sigma_uv
+ * (the first z in increasing id order whose running weight sum exceeds
+ * bounded(draw(seed, 4, j, 0), sigma_uv)); then a walk from z to u on side
+ * A (draws of stream 3) and one from z to v on side B (stream 5), each
+ * choosing predecessors in proportion to their path counts.  Every shortest
+ * path is therefore drawn with probability 1 / sigma_uv.
+ *
+ * Interior vertices are written from v's side towards u.  Returns their
+ * number, -1 if v is unreachable, or OR_E_SIGMA_OVERFLOW - 100 when a path
+ * count (or sigma_uv) reaches 2^64.
+ */
+static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u, int32_t v,
+                          side_t *A, side_t *B, int32_t *interior, int32_t *scratch) {
+    side_start(g, A, u);
+    side_start(g, B, v);
+    int32_t result = -1;
+    for (;;) {
+        side_t *X = (A->cost <= B->cost) ? A : B;
+        side_t *Y = (X == A) ? B : A;
+        int32_t fresh = expand_level(g, X);
+        if (fresh < 0) { result = OR_E_SIGMA_OVERFLOW - 100; break; }
+        if (fresh == 0) { result = -1; break; }
+        /* meeting vertices, in increasing id order */
+        int32_t lo = X->lvl[X->depth], hi = X->lvl[X->depth + 1], nm = 0;
+        for (int32_t i = lo; i < hi; ++i)
+            if (Y->d[X->S[i]] >= 0) scratch[nm++] = X->S[i];
+        if (nm == 0) continue;
+        qsort(scratch, (size_t)nm, sizeof(int32_t), cmp_i32);
+        unsigned __int128 total = 0;
+        for (int32_t a = 0; a < nm; ++a)
+            total += (unsigned __int128)A->sigma[scratch[a]] * B->sigma[scratch[a]];
+        if (total >> 64) { result = OR_E_SIGMA_OVERFLOW - 100; break; }
+        uint64_t r = or_bounded(or_draw(seed, 4, (uint64_t)j, 0), (uint64_t)total);
+        unsigned __int128 acc = 0;
+        int32_t z = -1;
+        for (int32_t a = 0; a < nm; ++a) {
+            acc += (unsigned __int128)A->sigma[scratch[a]] * B->sigma[scratch[a]];
+            if (acc > r) { z = scratch[a]; break; }
+        }
+        /* v's side first, reversed so the list runs from v towards u */
+        int32_t len = walk_to_root(g, B, z, seed, 5, j, scratch);
+        for (int32_t a = 0; a < len; ++a) interior[a] = scratch[len - 1 - a];
+        if (z != u && z != v) interior[len++] = z;
+        len += walk_to_root(g, A, z, seed, 3, j, interior + len);
+        result = len;
+        break;
+    }
+    side_reset(A);
+    side_reset(B);
+    return result;
+}
+
+typedef struct {
+    int32_t *d[2], *S[2], *lvl[2], *scratch;
+    uint64_t *sigma[2];
+    side_t A, B;
+} pair_work_t;
+
+static int pair_work_alloc(pair_work_t *w, int32_t n) {
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    memset(w, 0, sizeof(*w));
+    for (int k = 0; k < 2; ++k) {
+        w->d[k] = (int32_t *)malloc(nn * sizeof(int32_t));
+        w->S[k] = (int32_t *)malloc(nn * sizeof(int32_t));
+        w->lvl[k] = (int32_t *)malloc((nn + 2) * sizeof(int32_t));
+        w->sigma[k] = (uint64_t *)calloc(nn, sizeof(uint64_t));
+        if (!w->d[k] || !w->S[k] || !w->lvl[k] || !w->sigma[k]) return OR_E_NO_MEMORY;
+        for (int32_t i = 0; i < n; ++i) w->d[k][i] = -1;
+    }
+    w->scratch = (int32_t *)malloc(nn * sizeof(int32_t));
+    if (!w->scratch) return OR_E_NO_MEMORY;
+    side_t A = {w->d[0], w->sigma[0], w->S[0], w->lvl[0], 0, 0};
+    side_t B = {w->d[1], w->sigma[1], w->S[1], w->lvl[1], 0, 0};
+    w->A = A;
+    w->B = B;
+    return OR_OK;
+}
+
+static void pair_work_free(pair_work_t *w) {
+    for (int k = 0; k < 2; ++k) { free(w->d[k]); free(w->S[k]); free(w->lvl[k]); free(w->sigma[k]); }
+    free(w->scratch);
 }
 
 /* The path sample j draws for an explicit pair (u, v) (for inspection). */
@@ -649,10 +801,10 @@ int or_sample_path_uv(int32_t n, int64_t m, const int32_t *rowptr, const int32_t
     if (st != OR_OK) return st;
     if (u < 0 || u >= n || v < 0 || v >= n || u == v) return OR_E_INVALID_ARG;
     graph_t g = {n, rowptr, colidx};
-    work_t w;
-    if (work_alloc(&w, n) != OR_OK) { work_free(&w); return OR_E_NO_MEMORY; }
-    int32_t l = sample_one(&g, seed, j, u, v, &w, interior);
-    work_free(&w);
+    pair_work_t w;
+    if (pair_work_alloc(&w, n) != OR_OK) { pair_work_free(&w); return OR_E_NO_MEMORY; }
+    int32_t l = sample_one(&g, seed, j, u, v, &w.A, &w.B, interior, w.scratch);
+    pair_work_free(&w);
     if (l < -1) return OR_E_SIGMA_OVERFLOW;
     *len = l;
     return OR_OK;
@@ -665,11 +817,11 @@ int or_sample_path(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     if (st != OR_OK) return st;
     if (n < 2) return OR_E_INVALID_ARG;
     graph_t g = {n, rowptr, colidx};
-    work_t w;
-    if (work_alloc(&w, n) != OR_OK) { work_free(&w); return OR_E_NO_MEMORY; }
+    pair_work_t w;
+    if (pair_work_alloc(&w, n) != OR_OK) { pair_work_free(&w); return OR_E_NO_MEMORY; }
     pair_of(seed, j, n, &uv[0], &uv[1]);
-    int32_t l = sample_one(&g, seed, j, uv[0], uv[1], &w, interior);
-    work_free(&w);
+    int32_t l = sample_one(&g, seed, j, uv[0], uv[1], &w.A, &w.B, interior, w.scratch);
+    pair_work_free(&w);
     if (l < -1) return OR_E_SIGMA_OVERFLOW;
     *len = l;
     return OR_OK;
@@ -683,18 +835,18 @@ int or_pair_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     for (int32_t i = 0; i < n; ++i) counts[i] = 0;
     if (n < 2 || r <= 0) return OR_OK;
     graph_t g = {n, rowptr, colidx};
-    work_t w;
+    pair_work_t w;
     int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (work_alloc(&w, n) != OR_OK || !interior) { work_free(&w); free(interior); return OR_E_NO_MEMORY; }
+    if (pair_work_alloc(&w, n) != OR_OK || !interior) { pair_work_free(&w); free(interior); return OR_E_NO_MEMORY; }
     st = OR_OK;
     for (int64_t j = 0; j < r; ++j) {
         int32_t u, v;
         pair_of(seed, j, n, &u, &v);
-        int32_t l = sample_one(&g, seed, j, u, v, &w, interior);
+        int32_t l = sample_one(&g, seed, j, u, v, &w.A, &w.B, interior, w.scratch);
         if (l < -1) { st = OR_E_SIGMA_OVERFLOW; break; }
         for (int32_t i = 0; i < l; ++i) counts[interior[i]]++;
     }
-    work_free(&w);
+    pair_work_free(&w);
     free(interior);
     return st;
 }

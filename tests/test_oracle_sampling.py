@@ -19,6 +19,7 @@ import pytest
 
 import graphgen as gg
 import oracle
+from oracle import bruteforce as bf
 
 
 def test_splitmix64_published_vector():
@@ -62,6 +63,51 @@ def test_path_walk_uniform_on_grid():
     assert chi2 < 43.8  # 99.9% quantile of chi-square with 19 degrees of freedom
     for p in list(counts)[:5]:
         assert _is_shortest_path(g, 0, 15, list(p))
+
+
+@pytest.mark.parametrize("make,u,v", [
+    (lambda: gg.grid(3, 5), 0, 14),                       # 15 paths, meeting weights differ
+    (lambda: gg.grid(4, 4), 5, 15),
+    (lambda: gg.barabasi_albert(12, 2, 8), None, None),   # pair with the most shortest paths
+    (lambda: gg.complete_bipartite(3, 4), 0, 1),          # u and v on the same side
+])
+def test_bidirectional_sampler_uniform_vs_enumeration(make, u, v):
+    """Frequencies of the sampled paths of one pair against every shortest
+    path enumerated by brute force: chi-square at the 99.9% level."""
+    g = make()
+    paths = bf.all_pairs_paths(g.rowptr, g.colidx)
+    if u is None:
+        (u, v), _ = max(paths.items(), key=lambda kv: (len(kv[1]), -kv[0][0], -kv[0][1]))
+    want = {tuple(reversed(p[1:-1])) for p in paths[(u, v)]}   # interior from v's side
+    assert len(want) >= 3
+    N = 400 * len(want)
+    counts = {}
+    for j in range(N):
+        p = tuple(oracle.sample_path_uv(g.rowptr, g.colidx, 7, j, u, v))
+        assert p in want
+        counts[p] = counts.get(p, 0) + 1
+    assert set(counts) == want
+    exp = N / len(want)
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    dof = len(want) - 1
+    assert chi2 < dof + 4.5 * math.sqrt(2 * dof) + 10
+
+
+def test_bidirectional_sampler_all_pairs_small():
+    """Every ordered pair of small random graphs: the sampled interior is a
+    shortest path of the brute-force enumeration; unreachable pairs give None."""
+    for seed in range(6):
+        g = gg.erdos_renyi(9, 9 + seed, 40 + seed)
+        paths = bf.all_pairs_paths(g.rowptr, g.colidx)
+        for u in range(g.n):
+            for v in range(g.n):
+                if u == v:
+                    continue
+                got = oracle.sample_path_uv(g.rowptr, g.colidx, seed, u * g.n + v, u, v)
+                if (u, v) not in paths:
+                    assert got is None
+                else:
+                    assert tuple(got) in {tuple(reversed(p[1:-1])) for p in paths[(u, v)]}
 
 
 def test_sampled_paths_are_shortest():
