@@ -266,7 +266,8 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         KernelRef probe = brandes_kernel(mode, block, true);
         hipFuncAttributes attr;
         NK_HIP(hipFuncGetAttributes(&attr, probe.fn));
-        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1);
+        // pair mode keeps two visited bitmaps (one per search side) in global memory
+        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1) && mode != kModePair;
     }
     KernelRef kr = brandes_kernel(mode, block, lds);
     size_t dyn = lds ? bm_bytes : 0;
@@ -343,6 +344,20 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     p.bmg = nullptr;
     if (!plan.lds)
         if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
+    if (plan.mode == kModePair) {
+        // second side of the bidirectional pair search; both bitmaps start
+        // empty and each sample clears what it touched
+        if ((st = scr.get(cells, &p.sigma2)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.d2)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.lv2)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.la2)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.ld2)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.lvl2)) != NK_OK) return st;
+        if ((st = scr.get(slots * plan.bm_words, &p.bmg2)) != NK_OK) return st;
+        NK_HIP(launch_fill_u64(p.sigma2, 0ULL, cells, s));
+        NK_HIP(launch_fill_u32(p.bmg, 0u, slots * plan.bm_words, s));
+        NK_HIP(launch_fill_u32(p.bmg2, 0u, slots * plan.bm_words, s));
+    }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
     p.bu_ratio = tuning_get().bu_ratio;

@@ -73,6 +73,15 @@ struct Params {
     int32_t linear;
     int32_t pad1;
     double *ebc;
+    // pair mode: the second side (grown from the pair's target) of the
+    // bidirectional search; both visited bitmaps live in global memory
+    unsigned long long *sigma2;
+    int32_t *d2;
+    int32_t *lv2;
+    int32_t *la2;
+    int32_t *ld2;
+    int32_t *lvl2;
+    uint32_t *bmg2;
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.

@@ -529,20 +529,23 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 
 // --------------------------------------------------------------- path walk --
 
-// One wave walks from `target` back to `src`, at each vertex picking the
-// first predecessor (in adjacency order) whose running sigma sum exceeds a
-// uniform draw below sigma: predecessor p is taken with probability
-// sigma_p / sigma_w.  Interior vertices get counts[p] += 1.
-__device__ void walk_path(const Params &p, const uint32_t *bm, const Scr &s, const GView &g, int32_t src,
-                          int32_t target, long long j, long long task) {
+// One wave walks from `from` to the root of one side of the bidirectional
+// search: at w (step t) it draws r = bounded(draw(seed, stream, j, t),
+// sigma[w]) and takes the first neighbour p in adjacency order that the
+// side reached one level closer to its root and whose running sigma sum
+// exceeds r (64 neighbours at a time: inclusive u64 scan, then a ballot).
+// emit(i, p) is called by lane 0 for step i = 1, 2, ... with the vertex
+// reached, the root included.  Returns false if no predecessor was found
+// (only possible after a reported overflow).
+template <typename Emit>
+__device__ bool walk_side(const Params &p, const uint32_t *bm, const unsigned long long *sigma, const int32_t *d,
+                          const GView &g, int32_t from, unsigned long long stream, long long j, Emit emit) {
     const int lane = lane_id();
-    int32_t x = target;
+    int32_t x = from;
     unsigned long long t = 0;
-    int32_t len = 0;
-    bool ok = true;
-    while (x != src) {
-        const int32_t dx = s.d[x];
-        const unsigned long long r = bounded(draw(p.seed, 3, (unsigned long long)j, t), s.sigma[x]);
+    while (d[x] > 0) {
+        const int32_t dx = d[x];
+        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, t), sigma[x]);
         const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         unsigned long long carry = 0ULL;
         int32_t pick = -1;
@@ -552,7 +555,7 @@ __device__ void walk_path(const Params &p, const uint32_t *bm, const Scr &s, con
             unsigned long long sp = 0ULL;
             if (e < a1) {
                 pp = g.ci[e];
-                if (bit_test(bm, pp) && s.d[pp] == dx - 1) sp = s.sigma[pp];
+                if (bit_test(bm, pp) && d[pp] == dx - 1) sp = sigma[pp];
             }
             const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
             const unsigned long long mask = __ballot(e < a1 && carry + incl > r);
@@ -562,22 +565,267 @@ __device__ void walk_path(const Params &p, const uint32_t *bm, const Scr &s, con
             }
             carry += __shfl(incl, kWave - 1, kWave);
         }
-        if (pick < 0) {
-            ok = false;
-            if (lane == 0) atomicOr(&p.st->err, kErrInternal);
-            break;
-        }
-        if (pick != src) {
-            if (lane == 0) {
-                if (p.counts) atomicAdd(&p.counts[pick], 1u);
-                if (p.p_path && len < p.maxlen) p.p_path[task * p.maxlen + len] = p.inv ? p.inv[pick] : pick;
-            }
-            ++len;
-        }
-        x = pick;
+        if (pick < 0) return false;
         ++t;
+        if (lane == 0) emit((int32_t)t, pick);
+        x = pick;
     }
-    if (lane == 0 && p.p_len) p.p_len[task] = !ok ? -3 : (len > p.maxlen ? -2 : len);
+    return true;
+}
+
+// Block-scope state of one bidirectional search (side 0 grows from u,
+// side 1 from v).
+struct BiState {
+    int32_t lo[2], hi[2], depth[2];  // deepest level of each side: list[lo, hi)
+    long long cost[2];               // arcs leaving that level
+    long long newcost;
+    int32_t nm;                      // meeting vertices collected
+    int32_t z;                       // chosen meeting vertex
+    int32_t result;                  // 0 searching, 1 met, -1 unreachable, -3 overflow
+    int32_t pad;
+    unsigned long long part_lo[16], part_hi[16];
+    unsigned long long total, r0;
+};
+
+// Block-wide 128-bit sum of one u64 per thread: (hi, lo) words.  Contains
+// barriers.
+template <int BLOCK>
+__device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long long &lo,
+                               unsigned long long &hi) {
+    unsigned long long l = x, h = 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long ol = __shfl_xor(l, off, kWave), oh = __shfl_xor(h, off, kWave);
+        const unsigned long long nl = l + ol;
+        h = h + oh + (nl < l ? 1ULL : 0ULL);
+        l = nl;
+    }
+    if (lane_id() == 0) {
+        bs.part_lo[wave_id()] = l;
+        bs.part_hi[wave_id()] = h;
+    }
+    __syncthreads();
+    lo = 0;
+    hi = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) {
+        const unsigned long long nl = lo + bs.part_lo[w];
+        hi += bs.part_hi[w] + (nl < lo ? 1ULL : 0ULL);
+        lo = nl;
+    }
+    __syncthreads();
+}
+
+// One pair sample by balanced bidirectional search, the procedure of the
+// oracle's sample_one: grow the side with fewer arcs leaving its deepest
+// level by one top-down level (side A on ties); stop at the first new
+// level holding vertices the other side already reached (set M), or when a
+// side's new level is empty (v unreachable).  z in M is drawn with
+// probability sigma_A(z) sigma_B(z) / sigma_uv -- the first z in
+// increasing original id whose running weight exceeds the draw, found by a
+// binary search on the id threshold with one block reduction per step --
+// then wave 0 walks z -> v on side B (draw stream 5) and z -> u on side A
+// (stream 3).  Interior vertices are counted and, for inspection, written
+// from v's side towards u.  Touched entries are cleared at the end, so the
+// next sample starts from zeroed path counts and empty bitmaps.
+template <int BLOCK>
+__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Scr &sa, const Scr &sb,
+                             uint32_t *bma, uint32_t *bmb, const GView &g, int32_t u, int32_t v, long long j,
+                             long long task, Counters &c) {
+    const int tid = threadIdx.x;
+    if (tid < 2) {
+        const Scr &x = tid == 0 ? sa : sb;
+        uint32_t *bm = tid == 0 ? bma : bmb;
+        const int32_t r = tid == 0 ? u : v;
+        const int32_t a0 = g.rp[r], dg = g.rp[r + 1] - a0;
+        x.sigma[r] = 1ULL;
+        x.d[r] = 0;
+        bit_set(bm, r);
+        x.lv[0] = r;
+        x.la[0] = a0;
+        x.ld[0] = dg;
+        x.lvl[0] = 0;
+        x.lvl[1] = 1;
+        bs.lo[tid] = 0;
+        bs.hi[tid] = 1;
+        bs.depth[tid] = 0;
+        bs.cost[tid] = dg;
+    }
+    if (tid == 0) {
+        bs.result = 0;
+        bs.nm = 0;
+        bs.pad = 0;   // set when any weight or partial sum wraps
+    }
+    __syncthreads();
+
+    // ---- search
+    while (bs.result == 0) {
+        const int X = bs.cost[0] <= bs.cost[1] ? 0 : 1;
+        const Scr &sx = X == 0 ? sa : sb;
+        uint32_t *bmx = X == 0 ? bma : bmb;
+        const uint32_t *bmy = X == 0 ? bmb : bma;
+        const int32_t lo = bs.lo[X], hi = bs.hi[X], dep = bs.depth[X];
+        __syncthreads();
+        if (tid == 0) {
+            sm.count = 0;
+            bs.newcost = 0;
+            c.td++;
+        }
+        __syncthreads();
+        td_level<BLOCK, kModePair>(p, sm, bmx, sx, g, lo, hi, dep, c);
+        __syncthreads();
+        const int32_t nnew = sm.count < g.n - hi ? sm.count : g.n - hi;
+        long long dsum = 0;
+        for (int32_t i0 = hi; i0 < hi + nnew; i0 += BLOCK) {
+            const int32_t i = i0 + tid;
+            const bool in = i < hi + nnew;
+            int32_t w = 0;
+            bool meet = false;
+            if (in) {
+                w = sx.lv[i];
+                bit_set(bmx, w);
+                const int32_t a0 = g.rp[w], dg = g.rp[w + 1] - a0;
+                sx.la[i] = a0;
+                sx.ld[i] = dg;
+                dsum += dg;
+                meet = bit_test(bmy, w);
+            }
+            // meeting vertices: new on side X and already reached by the other side
+            wave_append(meet, w, sa.cand, &bs.nm, g.n, &p.st->err);
+        }
+        dsum = wave_sum<long long>(dsum);
+        if (lane_id() == 0 && dsum) atomicAdd((unsigned long long *)&bs.newcost, (unsigned long long)dsum);
+        __syncthreads();
+        if (tid == 0) {
+            bs.lo[X] = hi;
+            bs.hi[X] = hi + nnew;
+            bs.depth[X] = dep + 1;
+            bs.cost[X] = bs.newcost;
+            sx.lvl[dep + 2] = hi + nnew;
+            if (nnew == 0)
+                bs.result = -1;
+            else if (bs.nm > 0)
+                bs.result = 1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) c.reached += (unsigned long long)(bs.hi[0] + bs.hi[1]);
+
+    // ---- meeting vertex
+    if (bs.result == 1) {
+        const int32_t nm = bs.nm;
+        unsigned long long *wt = reinterpret_cast<unsigned long long *>(sa.dacc);
+        unsigned long long mine = 0ULL;
+        bool wrap = false;
+        int32_t idlo = 0x7fffffff, idhi = -1;
+        for (int32_t i = tid; i < nm; i += BLOCK) {
+            const int32_t z = sa.cand[i];
+            const unsigned long long a = sa.sigma[z], b = sb.sigma[z];
+            const unsigned long long w = a * b;
+            if (__umul64hi(a, b) != 0ULL) wrap = true;
+            wt[i] = w;
+            const unsigned long long nw = mine + w;
+            if (nw < mine) wrap = true;
+            mine = nw;
+            const int32_t oid = p.inv ? p.inv[z] : z;
+            idlo = min(idlo, oid);
+            idhi = max(idhi, oid);
+        }
+        if (wrap) {
+            atomicOr(&p.st->err, kErrOverflow);
+            bs.pad = 1;
+        }
+        unsigned long long tlo, thi;
+        block_sum_u128<BLOCK>(mine, bs, tlo, thi);   // its barriers publish bs.pad
+        const bool anywrap = bs.pad != 0;             // block-uniform from here on
+        // id range of M for the threshold search
+        idlo = wave_min(idlo);
+        idhi = -wave_min(-idhi);
+        if (tid == 0) {
+            sm.redmin = 0x7fffffff;
+            sm.levels = -1;
+        }
+        __syncthreads();
+        if (lane_id() == 0) {
+            atomicMin(&sm.redmin, idlo);
+            atomicMax(&sm.levels, idhi);
+        }
+        __syncthreads();
+        int32_t tlo_id = sm.redmin, thi_id = sm.levels;
+        __syncthreads();
+        if (thi != 0ULL || anywrap) {
+            if (tid == 0) {
+                bs.result = -3;
+                atomicOr(&p.st->err, kErrOverflow);
+            }
+        } else {
+            const unsigned long long r0 = bounded(draw(p.seed, 4, (unsigned long long)j, 0), tlo);
+            // smallest original-id threshold T with sum of weights of ids <= T above r0
+            while (tlo_id < thi_id) {
+                const int32_t mid = tlo_id + ((thi_id - tlo_id) >> 1);
+                unsigned long long part = 0ULL;
+                for (int32_t i = tid; i < nm; i += BLOCK) {
+                    const int32_t z = sa.cand[i];
+                    const int32_t oid = p.inv ? p.inv[z] : z;
+                    if (oid <= mid) part += wt[i];
+                }
+                unsigned long long flo, fhi;
+                block_sum_u128<BLOCK>(part, bs, flo, fhi);
+                if (flo > r0)
+                    thi_id = mid;
+                else
+                    tlo_id = mid + 1;
+            }
+            for (int32_t i = tid; i < nm; i += BLOCK) {
+                const int32_t z = sa.cand[i];
+                if ((p.inv ? p.inv[z] : z) == tlo_id) bs.z = z;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- walks (wave 0)
+    if (wave_id() == 0) {
+        const int lane = lane_id();
+        if (bs.result == -1) {
+            if (lane == 0 && p.p_len) p.p_len[task] = -1;
+        } else if (bs.result == -3) {
+            if (lane == 0 && p.p_len) p.p_len[task] = -3;
+        } else {
+            const int32_t z = bs.z;
+            const int32_t kb = sb.d[z], ha = sa.d[z];
+            const int32_t nb = kb >= 1 ? kb - 1 : 0;
+            const int32_t zc = (kb >= 1 && ha >= 1) ? 1 : 0;
+            const int32_t len = nb + zc + (ha >= 1 ? ha - 1 : 0);
+            auto put = [&](int32_t pos, int32_t vtx) {
+                if (p.counts) atomicAdd(&p.counts[vtx], 1u);
+                if (p.p_path && pos < p.maxlen) p.p_path[task * p.maxlen + pos] = p.inv ? p.inv[vtx] : vtx;
+            };
+            // side B: steps 1 .. kb-1 are interior, listed from v's side
+            bool ok = walk_side(p, bmb, sb.sigma, sb.d, g, z, 5, j, [&](int32_t i, int32_t vtx) {
+                if (i < kb) put(kb - 1 - i, vtx);
+            });
+            if (lane == 0 && zc) put(nb, z);
+            ok = ok && walk_side(p, bma, sa.sigma, sa.d, g, z, 3, j, [&](int32_t i, int32_t vtx) {
+                if (i < ha) put(nb + zc + i - 1, vtx);
+            });
+            if (!ok && lane == 0) atomicOr(&p.st->err, kErrInternal);
+            if (lane == 0 && p.p_len) p.p_len[task] = !ok ? -3 : (len > p.maxlen ? -2 : len);
+        }
+    }
+    __syncthreads();
+
+    // ---- clear what this sample touched
+    for (int k = 0; k < 2; ++k) {
+        const Scr &x = k == 0 ? sa : sb;
+        uint32_t *bm = k == 0 ? bma : bmb;
+        for (int32_t i = tid; i < bs.hi[k]; i += BLOCK) {
+            const int32_t w = x.lv[i];
+            x.sigma[w] = 0ULL;
+            bm[w >> 5] = 0u;
+        }
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------ the kernel --
@@ -586,6 +834,7 @@ template <int BLOCK, bool BMLDS, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     extern __shared__ uint32_t lds_bm[];
     __shared__ Tile<BLOCK> sm;
+    __shared__ BiState bs;
     const int tid = threadIdx.x;
     if (tid == 0) sm.flag = p.st->err & kErrGraph;
     __syncthreads();
@@ -604,6 +853,18 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.lvl = p.lvl + slot * p.stride;
     s.cand = p.cand + slot * p.stride;
     uint32_t *bm = BMLDS ? lds_bm : p.bmg + slot * p.bm_words;
+    // pair mode: the target's side of the bidirectional search
+    Scr s2 = s;
+    uint32_t *bm2 = nullptr;
+    if (MODE == kModePair) {
+        s2.sigma = p.sigma2 + slot * p.stride;
+        s2.d = p.d2 + slot * p.stride;
+        s2.lv = p.lv2 + slot * p.stride;
+        s2.la = p.la2 + slot * p.stride;
+        s2.ld = p.ld2 + slot * p.stride;
+        s2.lvl = p.lvl2 + slot * p.stride;
+        bm2 = p.bmg2 + slot * p.bm_words;
+    }
 
     Counters c = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (tid < 8) {
@@ -663,10 +924,17 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             if (tid == 0) atomicOr(&p.st->err, kErrArg);
             continue;
         }
-        // An isolated target is unreachable; its bitmap bit is pre-set, so it
-        // must not reach the "target visited" test of the forward phase.
-        if (MODE == kModePair && g.rp[target + 1] == g.rp[target]) {
-            if (tid == 0 && p.p_len) p.p_len[task] = -1;
+        if (MODE == kModePair) {
+            // an isolated endpoint leaves the pair unreachable
+            if (g.rp[target + 1] == g.rp[target] || g.rp[src + 1] == g.rp[src]) {
+                if (tid == 0 && p.p_len) p.p_len[task] = -1;
+                if (tid == 0) c.tasks++;
+                continue;
+            }
+            phase_start<BLOCK>(sm);
+            bidir_sample<BLOCK>(p, sm, bs, s, s2, bm, bm2, g, src, target, j, task, c);
+            if (tid == 0) c.tasks++;
+            phase_end<BLOCK>(sm, kPhTd);
             continue;
         }
 
@@ -686,13 +954,6 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 const int32_t o = p.inv ? p.inv[v] : v;
                 p.d_out[row + o] = s.d[v];
                 p.sigma_out[row + o] = s.sigma[v];
-            }
-        } else if (MODE == kModePair) {
-            if (wave_id() == 0) {
-                if (sm.flag)
-                    walk_path(p, bm, s, g, src, target, j, task);
-                else if (lane_id() == 0 && p.p_len)
-                    p.p_len[task] = -1;
             }
         } else if (MODE == kModeBFS) {
             // eccentricity of src and the lowest (original) id at that distance
