@@ -375,35 +375,6 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
 
 // One breadth-first search from `src` (BFS mode, one workgroup): returns
 // eccentricity, lowest id at that distance and reached count.
-static nk_status bfs_once(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const uint32_t *iso,
-                          int32_t src, int32_t out[3], hipStream_t s) {
-    Scratch scr;
-    DevStatus *dst;
-    nk_status st;
-    if ((st = scr.get(1, &dst)) != NK_OK) return st;
-    NK_HIP(launch_status_init(dst, s));
-    LaunchPlan plan;
-    if ((st = plan_launch(kModeBFS, n, 1, 1, &plan)) != NK_OK) return st;
-    Params p;
-    memset(&p, 0, sizeof(p));
-    p.rowptr = rowptr;
-    p.colidx = colidx;
-    p.n = n;
-    p.m = (int32_t)m;
-    p.ntasks = 1;
-    p.single_source = src;
-    p.iso = iso;
-    p.st = dst;
-    if ((st = launch_persistent(plan, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
-    DevStatus *h = host_status();
-    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
-    if ((st = finish(dst, h, s)) != NK_OK) return st;
-    out[0] = h->info[0];
-    out[1] = h->info[1];
-    out[2] = h->info[2];
-    return NK_OK;
-}
-
 nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
                         hipStream_t s) {
     for (int i = 0; i < 8; ++i) info[i] = 0;
@@ -411,13 +382,13 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     Scratch scr;
     DevStatus *dst;
     unsigned long long *key;
-    uint32_t *iso;
-    int32_t *label, *size, *flag;
+    int32_t *d, *f0, *f1, *label, *size, *flag;
     nk_status st;
-    const long long words = ((long long)n + 31) / 32;
     if ((st = scr.get(1, &dst)) != NK_OK) return st;
     if ((st = scr.get(1, &key)) != NK_OK) return st;
-    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    if ((st = scr.get(n, &d)) != NK_OK) return st;
+    if ((st = scr.get(n, &f0)) != NK_OK) return st;
+    if ((st = scr.get(n, &f1)) != NK_OK) return st;
     if ((st = scr.get(n, &label)) != NK_OK) return st;
     if ((st = scr.get(n, &size)) != NK_OK) return st;
     if ((st = scr.get(2, &flag)) != NK_OK) return st;
@@ -427,35 +398,22 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
     NK_HIP(launch_fill_u64(key, 0ULL, 1, s));
     NK_HIP(launch_argmax_degree(rowptr, n, key, s));
-    NK_HIP(launch_iso_bitmap(rowptr, n, iso, s));
     if ((st = finish(dst, h, s)) != NK_OK) return st;
     unsigned long long k = 0;
     NK_HIP(hipMemcpyAsync(&k, key, 8, hipMemcpyDeviceToHost, s));
     NK_HIP(hipStreamSynchronize(s));
     const int32_t x0 = (int32_t)(0xffffffffULL - (k & 0xffffffffULL));
+    // first sweep from x0: e1, the lowest far vertex a, and |C(x0)|
     int32_t r1[3], r2[3];
-    if ((st = bfs_once(rowptr, colidx, n, m, iso, x0, r1, s)) != NK_OK) return st;
+    if ((st = grid_bfs(rowptr, colidx, n, x0, d, f0, f1, flag, s, r1)) != NK_OK) return st;
     const int32_t e1 = r1[0], a = r1[1], c0 = r1[2];
-    if ((st = bfs_once(rowptr, colidx, n, m, iso, a, r2, s)) != NK_OK) return st;
-    const int32_t e2 = r2[0];
-    // largest component other than x0's
-    NK_HIP(launch_cc_init(label, n, s));
-    int32_t hflag = 1;
-    for (int it = 0; hflag && it < 100000; ++it) {
-        NK_HIP(launch_fill_i32(flag, 0, 1, s));
-        NK_HIP(launch_cc_hook(rowptr, colidx, n, label, flag, s));
-        NK_HIP(launch_cc_compress(label, n, s));
-        NK_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
-        NK_HIP(hipStreamSynchronize(s));
-    }
-    if (hflag) return fail(NK_E_INTERNAL, "component labelling did not converge");
-    NK_HIP(launch_fill_i32(size, 0, n, s));
-    NK_HIP(launch_cc_sizes(label, n, size, s));
-    NK_HIP(launch_fill_i32(flag, 0, 1, s));
-    NK_HIP(launch_cc_other_max(label, size, n, x0, flag, s));
+    // largest component among the vertices the first sweep did not reach
     int32_t c2 = 0;
-    NK_HIP(hipMemcpyAsync(&c2, flag, 4, hipMemcpyDeviceToHost, s));
-    NK_HIP(hipStreamSynchronize(s));
+    if (c0 < n)
+        if ((st = largest_unreached_component(rowptr, colidx, n, d, label, size, flag, s, &c2)) != NK_OK) return st;
+    // second sweep from a
+    if ((st = grid_bfs(rowptr, colidx, n, a, d, f0, f1, flag, s, r2)) != NK_OK) return st;
+    const int32_t e2 = r2[0];
     int32_t ub = 2 * e1 + 1;
     if (ub > c0) ub = c0;
     if (c2 > ub) ub = c2;

@@ -29,7 +29,7 @@ struct DevStatus {
     int32_t pad;
     unsigned long long head;
     unsigned long long stat[12];
-    int32_t info[8];   // BFS mode: eccentricity, lowest far vertex, reached count
+    int32_t info[8];   // reserved
     unsigned long long cycles[8];  // shader clock cycles per phase, summed over workgroups
     unsigned long long sub[8];     // shader clock cycles per sub-phase
 };

@@ -13,8 +13,7 @@ namespace nk {
 enum Mode : int {
     kModeBC = 0,    // forward + dependency sweep, scores into bc
     kModeSSSP = 1,  // forward only, d and sigma written out per task
-    kModePair = 2,  // forward truncated at the target, one path walk
-    kModeBFS = 3    // forward without path counts (eccentricity only)
+    kModePair = 2   // one sampled pair: bidirectional search and path walk
 };
 
 // Everything a persistent launch reads.  Per-slot scratch arrays hold
@@ -34,7 +33,7 @@ struct Params {
     // tasks
     long long ntasks;
     const int32_t *sources;    // task -> source (NULL: task id is the source)
-    int32_t single_source;     // BFS mode
+    int32_t pad2;
     int32_t maxlen;            // pair inspection
     // outputs
     double *bc;
@@ -117,14 +116,6 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long lon
 hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s);
-hipError_t launch_cc_init(int32_t *label, int32_t n, hipStream_t s);
-hipError_t launch_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed,
-                          hipStream_t s);
-hipError_t launch_cc_compress(int32_t *label, int32_t n, hipStream_t s);
-hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipStream_t s);
-hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
-                               hipStream_t s);
-
 // Degree-descending relabelling of a single graph (nk_relabel.hip).
 struct Relabeled {
     const int32_t *rowptr;  // CSR in internal ids (the input when not relabelled)

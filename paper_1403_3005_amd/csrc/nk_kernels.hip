@@ -152,7 +152,7 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     const int tid = threadIdx.x;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
-        if (tid < cnt) sm.val.u[tid] = (MODE == kModeBFS) ? 1ULL : s.sigma[s.lv[tb + tid]];
+        if (tid < cnt) sm.val.u[tid] = s.sigma[s.lv[tb + tid]];
         const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
@@ -172,7 +172,7 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
             for (int j = 0; j < kChunk; ++j) {
                 if (act[j]) {
                     c.dag++;
-                    if (MODE != kModeBFS && old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                    if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
                     if ((MODE == kModeSSSP || MODE == kModePair) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
                 }
                 wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
@@ -236,7 +236,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 const bool act = kk[j] >= 0 && bit_test(bm, v[j]);
-                sv[j] = act ? ((MODE == kModeBFS) ? 1ULL : s.sigma[v[j]]) : 0ULL;
+                sv[j] = act ? s.sigma[v[j]] : 0ULL;
             }
             int32_t kcur = kk[0];
             unsigned long long acc = 0ULL;
@@ -246,21 +246,21 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
                 if (kk[j] != kcur) {
                     if (acc) {
                         const unsigned long long o = atomicAdd(&sm.val.u[kcur], acc);
-                        if (MODE != kModeBFS && o + acc < o) atomicOr(&p.st->err, kErrOverflow);
+                        if (o + acc < o) atomicOr(&p.st->err, kErrOverflow);
                     }
                     kcur = kk[j];
                     acc = 0ULL;
                 }
                 if (sv[j]) {
                     const unsigned long long nacc = acc + sv[j];
-                    if (MODE != kModeBFS && nacc < acc) atomicOr(&p.st->err, kErrOverflow);
+                    if (nacc < acc) atomicOr(&p.st->err, kErrOverflow);
                     acc = nacc;
                     c.dag++;
                 }
             }
             if (acc) {
                 const unsigned long long o = atomicAdd(&sm.val.u[kcur], acc);
-                if (MODE != kModeBFS && o + acc < o) atomicOr(&p.st->err, kErrOverflow);
+                if (o + acc < o) atomicOr(&p.st->err, kErrOverflow);
             }
         }
         __syncthreads();
@@ -914,8 +914,6 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 }
                 src = p.perm ? p.perm[a] : a;
                 target = p.perm ? p.perm[b] : b;
-            } else if (MODE == kModeBFS) {
-                src = p.single_source;
             } else {
                 src = p.sources ? p.sources[task] : (int32_t)task;
             }
@@ -924,7 +922,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             if (tid == 0) atomicOr(&p.st->err, kErrArg);
             continue;
         }
-        if (MODE == kModePair) {
+        if constexpr (MODE == kModePair) {
             // an isolated endpoint leaves the pair unreachable
             if (g.rp[target + 1] == g.rp[target] || g.rp[src + 1] == g.rp[src]) {
                 if (tid == 0 && p.p_len) p.p_len[task] = -1;
@@ -936,7 +934,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             if (tid == 0) c.tasks++;
             phase_end<BLOCK>(sm, kPhTd);
             continue;
-        }
+        } else {
 
         const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, p.G > 0 ? nullptr : p.iso, src, target, c);
         const int32_t nreached = s.lvl[Ld + 1];
@@ -955,26 +953,13 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 p.d_out[row + o] = s.d[v];
                 p.sigma_out[row + o] = s.sigma[v];
             }
-        } else if (MODE == kModeBFS) {
-            // eccentricity of src and the lowest (original) id at that distance
-            const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
-            int32_t mn = 0x7fffffff;
-            for (int32_t i = lo + tid; i < hi; i += BLOCK) {
-                const int32_t v = s.lv[i];
-                mn = min(mn, p.inv ? p.inv[v] : v);
-            }
-            mn = wave_min(mn);
-            if (lane_id() == 0) atomicMin(&p.st->info[1], mn);
-            if (tid == 0) {
-                p.st->info[0] = Ld;
-                p.st->info[2] = nreached;
-            }
         }
         __syncthreads();
         phase_start<BLOCK>(sm);
         for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.lv[i]] = 0ULL;
         __syncthreads();
         phase_end<BLOCK>(sm, kPhReset);
+        }  // non-pair modes
     }
 
     // counters: wave sums, one atomic per wave and counter
@@ -1024,7 +1009,7 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
         case kModeBC: return ref_mode<kModeBC>(block, bitmap_in_lds);
         case kModeSSSP: return ref_mode<kModeSSSP>(block, bitmap_in_lds);
         case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
-        default: return ref_mode<kModeBFS>(block, bitmap_in_lds);
+        default: return ref_mode<kModeBC>(block, bitmap_in_lds);
     }
 }
 
@@ -1129,52 +1114,6 @@ __global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long 
     if (lane_id() == 0) atomicMax(key, best);
 }
 
-// Connected components by minimum-label hooking with pointer jumping.
-__global__ void k_cc_init(int32_t *label, int32_t n) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) label[v] = (int32_t)v;
-}
-
-__global__ void k_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    int ch = 0;
-    for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-        const int32_t lu = label[u];
-        for (int32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
-            const int32_t v = colidx[e];
-            const int32_t lv = label[v];
-            if (lu < lv) {
-                atomicMin(&label[lv], lu);
-                ch = 1;
-            }
-        }
-    }
-    if (ch) atomicOr(changed, 1);
-}
-
-__global__ void k_cc_compress(int32_t *label, int32_t n) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-        int32_t l = label[v];
-        while (label[l] != l) l = label[l];
-        label[v] = l;
-    }
-}
-
-__global__ void k_cc_sizes(const int32_t *label, int32_t n, int32_t *size) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) atomicAdd(&size[label[v]], 1);
-}
-
-__global__ void k_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    const int32_t root0 = label[x0];
-    int32_t best = 0;
-    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-        if (label[v] == (int32_t)v && (int32_t)v != root0) best = max(best, size[v]);
-    if (best) atomicMax(out, best);
-}
-
 static inline unsigned grid_for(long long count, int block) {
     long long g = (count + block - 1) / block;
     if (g < 1) g = 1;
@@ -1226,28 +1165,6 @@ hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale,
 }
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s) {
     hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, n, key);
-    return hipGetLastError();
-}
-hipError_t launch_cc_init(int32_t *label, int32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n);
-    return hipGetLastError();
-}
-hipError_t launch_cc_hook(const int32_t *rowptr, const int32_t *colidx, int32_t n, int32_t *label, int32_t *changed,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_hook, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, colidx, n, label, changed);
-    return hipGetLastError();
-}
-hipError_t launch_cc_compress(int32_t *label, int32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_compress, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n);
-    return hipGetLastError();
-}
-hipError_t launch_cc_sizes(const int32_t *label, int32_t n, int32_t *size, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_sizes, dim3(grid_for(n, 256)), dim3(256), 0, s, label, n, size);
-    return hipGetLastError();
-}
-hipError_t launch_cc_other_max(const int32_t *label, const int32_t *size, int32_t n, int32_t x0, int32_t *out,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_other_max, dim3(grid_for(n, 256)), dim3(256), 0, s, label, size, n, x0, out);
     return hipGetLastError();
 }
 
