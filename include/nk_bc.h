@@ -251,7 +251,9 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
  *           task set-up, top-down levels, bottom-up levels, level marking,
  *           pull levels, push levels, path-count reset, everything else
  *   out[24..29] cycles inside bottom-up levels (staging and scans, arc loop,
- *           finalize) and pull levels (same three); out[30..31] reserved
+ *           finalize) and pull levels (same three); pair sampling reports
+ *           in out[24..27] the bidirectional search, the meeting-vertex
+ *           choice, the two walks and the clearing; out[30..31] reserved
  */
 nk_status nk_last_stats(int64_t *out);
 

@@ -258,7 +258,12 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     if (st != NK_OK) return st;
     nk_tuning t = tuning_get();
     int block = t.block;
-    if (block != 256 && block != 512 && block != 1024) block = auto_block(n_max);
+    if (block != 256 && block != 512 && block != 1024) {
+        block = auto_block(n_max);
+        // a pair sample's search levels are small; 512 threads keep its
+        // kernel free of register spills
+        if (mode == kModePair && block > 512) block = 512;
+    }
     const long long words = ((long long)n_max + 31) / 32;
     const size_t bm_bytes = (size_t)words * 4;
     bool lds = false;

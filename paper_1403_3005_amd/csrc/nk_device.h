@@ -37,6 +37,8 @@ struct DevStatus {
 enum PhaseIdx { kPhInit = 0, kPhTd, kPhBu, kPhMark, kPhPull, kPhPush, kPhReset, kPhOther, kNumPhases };
 // sub-phases of the bottom-up and pull levels (staging + scans, arc loop, finalize)
 enum SubIdx { kSbBuStage = 0, kSbBuArcs, kSbBuFin, kSbPlStage, kSbPlArcs, kSbPlFin, kNumSub };
+// pair mode reuses the first four slots: search, meeting-vertex choice, walks, clearing
+enum PairSubIdx { kSbPairSearch = 0, kSbPairSelect, kSbPairWalk, kSbPairClear };
 
 enum StatIdx {
     kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached, kStBwPush,

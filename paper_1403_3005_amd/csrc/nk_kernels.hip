@@ -529,50 +529,6 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 
 // --------------------------------------------------------------- path walk --
 
-// One wave walks from `from` to the root of one side of the bidirectional
-// search: at w (step t) it draws r = bounded(draw(seed, stream, j, t),
-// sigma[w]) and takes the first neighbour p in adjacency order that the
-// side reached one level closer to its root and whose running sigma sum
-// exceeds r (64 neighbours at a time: inclusive u64 scan, then a ballot).
-// emit(i, p) is called by lane 0 for step i = 1, 2, ... with the vertex
-// reached, the root included.  Returns false if no predecessor was found
-// (only possible after a reported overflow).
-template <typename Emit>
-__device__ bool walk_side(const Params &p, const uint32_t *bm, const unsigned long long *sigma, const int32_t *d,
-                          const GView &g, int32_t from, unsigned long long stream, long long j, Emit emit) {
-    const int lane = lane_id();
-    int32_t x = from;
-    unsigned long long t = 0;
-    while (d[x] > 0) {
-        const int32_t dx = d[x];
-        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, t), sigma[x]);
-        const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
-        unsigned long long carry = 0ULL;
-        int32_t pick = -1;
-        for (int32_t base = a0; base < a1; base += kWave) {
-            const int32_t e = base + lane;
-            int32_t pp = -1;
-            unsigned long long sp = 0ULL;
-            if (e < a1) {
-                pp = g.ci[e];
-                if (bit_test(bm, pp) && d[pp] == dx - 1) sp = sigma[pp];
-            }
-            const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
-            const unsigned long long mask = __ballot(e < a1 && carry + incl > r);
-            if (mask) {
-                pick = __shfl(pp, __ffsll((long long)mask) - 1, kWave);
-                break;
-            }
-            carry += __shfl(incl, kWave - 1, kWave);
-        }
-        if (pick < 0) return false;
-        ++t;
-        if (lane == 0) emit((int32_t)t, pick);
-        x = pick;
-    }
-    return true;
-}
-
 // Block-scope state of one bidirectional search (side 0 grows from u,
 // side 1 from v).
 struct BiState {
@@ -583,6 +539,7 @@ struct BiState {
     int32_t z;                       // chosen meeting vertex
     int32_t result;                  // 0 searching, 1 met, -1 unreachable, -3 overflow
     int32_t pad;
+    int32_t pickw, pickv;            // block walk: first crossing wave, chosen vertex
     unsigned long long part_lo[16], part_hi[16];
     unsigned long long total, r0;
 };
@@ -614,6 +571,74 @@ __device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long 
         lo = nl;
     }
     __syncthreads();
+}
+
+// Walk from `from` to the root `rootv` of one search side, all threads of
+// the block together (the same choice as the oracle's walk: at w, step t,
+// r = bounded(draw(seed, stream, j, t), sigma[w]) and the first neighbour
+// in adjacency order one level closer to the root whose running sigma sum
+// exceeds r).  Each iteration covers BLOCK arcs of w: a wave scan per 64
+// arcs, the wave totals in LDS, and the first wave whose running sum
+// crosses r names the vertex.  A vertex one level from the root has the
+// root as its only predecessor.  Thread 0 calls emit(i, vertex) for step
+// i = 1, 2, ..., the root included.  Returns false if no predecessor is
+// found (only after a reported overflow).
+template <int BLOCK, typename Emit>
+__device__ bool walk_block(const Params &p, BiState &bs, const uint32_t *bm, const unsigned long long *sigma,
+                           const int32_t *d, const GView &g, int32_t from, int32_t rootv, unsigned long long stream,
+                           long long j, Emit emit) {
+    constexpr int NW = BLOCK / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), wid = wave_id();
+    int32_t x = from;
+    for (unsigned long long tt = 0;; ++tt) {
+        const int32_t dx = d[x];
+        if (dx <= 0) return true;
+        if (dx == 1) {
+            if (tid == 0) emit((int32_t)tt + 1, rootv);
+            return true;
+        }
+        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), sigma[x]);
+        const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
+        unsigned long long carry = 0ULL;
+        int32_t pick = -1;
+        for (int32_t base = a0; base < a1; base += BLOCK) {
+            const int32_t e = base + tid;
+            int32_t pp = -1;
+            unsigned long long sp = 0ULL;
+            if (e < a1) {
+                pp = g.ci[e];
+                if (bit_test(bm, pp) && d[pp] == dx - 1) sp = sigma[pp];
+            }
+            const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
+            if (lane == kWave - 1) bs.part_lo[wid] = incl;
+            if (tid == 0) bs.pickw = NW;
+            __syncthreads();
+            unsigned long long before = carry, total = carry;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const unsigned long long ws = bs.part_lo[w];
+                if (w < wid) before += ws;
+                total += ws;
+            }
+            const unsigned long long mask = __ballot(e < a1 && before + incl > r);
+            if (lane == 0 && mask) atomicMin(&bs.pickw, wid);
+            __syncthreads();
+            const int pw = bs.pickw;
+            if (pw < NW) {
+                if (wid == pw) {
+                    const int32_t chosen = __shfl(pp, __ffsll((long long)mask) - 1, kWave);
+                    if (lane == 0) bs.pickv = chosen;
+                }
+                __syncthreads();
+                pick = bs.pickv;
+                break;
+            }
+            carry = total;
+        }
+        if (pick < 0) return false;
+        if (tid == 0) emit((int32_t)tt + 1, pick);
+        x = pick;
+    }
 }
 
 // One pair sample by balanced bidirectional search, the procedure of the
@@ -657,6 +682,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         bs.pad = 0;   // set when any weight or partial sum wraps
     }
     __syncthreads();
+    sub_start<BLOCK>(sm);
 
     // ---- search
     while (bs.result == 0) {
@@ -710,6 +736,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         __syncthreads();
     }
     if (tid == 0) c.reached += (unsigned long long)(bs.hi[0] + bs.hi[1]);
+    sub_mark<BLOCK>(sm, kSbPairSearch);
 
     // ---- meeting vertex
     if (bs.result == 1) {
@@ -784,36 +811,36 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         __syncthreads();
     }
 
-    // ---- walks (wave 0)
-    if (wave_id() == 0) {
-        const int lane = lane_id();
-        if (bs.result == -1) {
-            if (lane == 0 && p.p_len) p.p_len[task] = -1;
-        } else if (bs.result == -3) {
-            if (lane == 0 && p.p_len) p.p_len[task] = -3;
-        } else {
-            const int32_t z = bs.z;
-            const int32_t kb = sb.d[z], ha = sa.d[z];
-            const int32_t nb = kb >= 1 ? kb - 1 : 0;
-            const int32_t zc = (kb >= 1 && ha >= 1) ? 1 : 0;
-            const int32_t len = nb + zc + (ha >= 1 ? ha - 1 : 0);
-            auto put = [&](int32_t pos, int32_t vtx) {
-                if (p.counts) atomicAdd(&p.counts[vtx], 1u);
-                if (p.p_path && pos < p.maxlen) p.p_path[task * p.maxlen + pos] = p.inv ? p.inv[vtx] : vtx;
-            };
-            // side B: steps 1 .. kb-1 are interior, listed from v's side
-            bool ok = walk_side(p, bmb, sb.sigma, sb.d, g, z, 5, j, [&](int32_t i, int32_t vtx) {
-                if (i < kb) put(kb - 1 - i, vtx);
-            });
-            if (lane == 0 && zc) put(nb, z);
-            ok = ok && walk_side(p, bma, sa.sigma, sa.d, g, z, 3, j, [&](int32_t i, int32_t vtx) {
+    sub_mark<BLOCK>(sm, kSbPairSelect);
+    // ---- walks (all threads; thread 0 records)
+    if (bs.result == -1) {
+        if (tid == 0 && p.p_len) p.p_len[task] = -1;
+    } else if (bs.result == -3) {
+        if (tid == 0 && p.p_len) p.p_len[task] = -3;
+    } else {
+        const int32_t z = bs.z;
+        const int32_t kb = sb.d[z], ha = sa.d[z];
+        const int32_t nb = kb >= 1 ? kb - 1 : 0;
+        const int32_t zc = (kb >= 1 && ha >= 1) ? 1 : 0;
+        const int32_t len = nb + zc + (ha >= 1 ? ha - 1 : 0);
+        auto put = [&](int32_t pos, int32_t vtx) {
+            if (p.counts) atomicAdd(&p.counts[vtx], 1u);
+            if (p.p_path && pos < p.maxlen) p.p_path[task * p.maxlen + pos] = p.inv ? p.inv[vtx] : vtx;
+        };
+        // side B: steps 1 .. kb-1 are interior, listed from v's side
+        bool ok = walk_block<BLOCK>(p, bs, bmb, sb.sigma, sb.d, g, z, v, 5, j, [&](int32_t i, int32_t vtx) {
+            if (i < kb) put(kb - 1 - i, vtx);
+        });
+        if (tid == 0 && zc) put(nb, z);
+        if (ok)
+            ok = walk_block<BLOCK>(p, bs, bma, sa.sigma, sa.d, g, z, u, 3, j, [&](int32_t i, int32_t vtx) {
                 if (i < ha) put(nb + zc + i - 1, vtx);
             });
-            if (!ok && lane == 0) atomicOr(&p.st->err, kErrInternal);
-            if (lane == 0 && p.p_len) p.p_len[task] = !ok ? -3 : (len > p.maxlen ? -2 : len);
-        }
+        if (!ok && tid == 0) atomicOr(&p.st->err, kErrInternal);
+        if (tid == 0 && p.p_len) p.p_len[task] = !ok ? -3 : (len > p.maxlen ? -2 : len);
     }
     __syncthreads();
+    sub_mark<BLOCK>(sm, kSbPairWalk);
 
     // ---- clear what this sample touched
     for (int k = 0; k < 2; ++k) {
@@ -826,6 +853,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         }
     }
     __syncthreads();
+    sub_mark<BLOCK>(sm, kSbPairClear);
 }
 
 // ------------------------------------------------------------ the kernel --
