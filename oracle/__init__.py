@@ -5,8 +5,8 @@ benchmark may import this package.  The GPU library and its Python binding
 never import it, and nothing here imports them.
 
 ``brandes.c`` holds plain sequential Brandes (exact, source set, the
-linear-scaling source-set estimator, edge betweenness, pair sampling) and is
-loaded through ctypes; ``bruteforce.py`` holds exact
+linear-scaling source-set estimator, edge betweenness, closeness, pair
+sampling) and is loaded through ctypes; ``bruteforce.py`` holds exact
 rational all-simple-paths enumeration for graphs of at most a dozen
 vertices.  Status codes: 0 ok, -1 invalid argument, -2 invalid graph,
 -3 sigma overflow, -4 out of memory.
@@ -61,6 +61,8 @@ def _load():
         "or_bc_exact": (c.c_int, g + [f64p, c.c_int32]),
         "or_bc_sources_linear": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_edge_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, f64p, c.c_int32]),
+        "or_closeness": (c.c_int, g + [f64p]),
+        "or_closeness_approx": (c.c_int, g + [i32p, c.c_int32, f64p, i64p]),
         "or_work_counts": (c.c_int, g + [i32p, c.c_int32, i64p]),
         "or_mix64": (c.c_uint64, [c.c_uint64]),
         "or_draw": (c.c_uint64, [c.c_uint64] * 4),
@@ -174,6 +176,32 @@ def edge_bc(rowptr, colidx, sources=None, scale: float = 1.0, nthreads: int = 1)
                                       _ptr(src, ctypes.c_int32), k, float(scale), _ptr(ebc, ctypes.c_double),
                                       _ptr(bc, ctypes.c_double), nthreads), "edge_bc")
     return ebc[:m], bc[:n]
+
+
+def closeness(rowptr, colidx) -> np.ndarray:
+    """Exact closeness, generalised to disconnected graphs:
+    (r-1)/(n-1) * (r-1)/farness, 0 for isolated vertices."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_closeness(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                _ptr(out, ctypes.c_double)), "closeness")
+    return out[:n]
+
+
+def closeness_approx(rowptr, colidx, sources):
+    """(closeness estimate, integer distance sums) of Eppstein and Wang's
+    sampling over `sources`: (n-1) / (n/k * sum of d(s, v))."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    out = np.zeros(max(n, 1), dtype=np.float64)
+    sums = np.zeros(max(n, 1), dtype=np.int64)
+    _check(_load().or_closeness_approx(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                       _ptr(src, ctypes.c_int32), k, _ptr(out, ctypes.c_double),
+                                       _ptr(sums, ctypes.c_int64)), "closeness_approx")
+    return out[:n], sums[:n]
 
 
 def work_counts(rowptr, colidx, sources):

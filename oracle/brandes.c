@@ -16,6 +16,7 @@
  *     Schultes (the reference cited for that sampling);
  *   - edge betweenness (section "Edge Centrality, Sparsification and Link
  *     Prediction");
+ *   - closeness, exact and sampled (Table 1, "closeness", "ap. closeness");
  *   - pair sampling (Riondato and Kornaropoulos, cited for the epsilon
  *     guarantee in "Heuristics and Approximation Algorithms").
  *
@@ -467,6 +468,96 @@ int or_work_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
         work_reset(&w, nS);
     }
     work_free(&w);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Closeness (Table 1, "closeness": a shortest-path search from each node;
+ * "ap. closeness": Eppstein and Wang's sampling, cited there).
+ *
+ * Plain BFS distances from s; returns the number of vertices reached
+ * (s included) and their distance sum. */
+static int32_t bfs_farness(const graph_t *g, int32_t s, int32_t *d, int32_t *queue, int64_t *far) {
+    int32_t head = 0, tail = 0;
+    int64_t sum = 0;
+    d[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+        int32_t v = queue[head++];
+        sum += d[v];
+        for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+            int32_t w = g->colidx[e];
+            if (d[w] < 0) { d[w] = d[v] + 1; queue[tail++] = w; }
+        }
+    }
+    for (int32_t i = 0; i < tail; ++i) d[queue[i]] = -1;
+    *far = sum;
+    return tail;
+}
+
+/*
+ * Exact closeness of every vertex, generalised to disconnected graphs:
+ * with r the number of vertices reachable from v (v included) and F the sum
+ * of their distances from v,
+ *     C(v) = (r - 1) / (n - 1) * (r - 1) / F,   and C(v) = 0 when r = 1,
+ * which is (n - 1) / F on a connected graph.
+ */
+int or_closeness(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, double *out) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (n == 0) return OR_OK;
+    graph_t g = {n, rowptr, colidx};
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!d || !q) { free(d); free(q); return OR_E_NO_MEMORY; }
+    for (int32_t i = 0; i < n; ++i) d[i] = -1;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t far;
+        int32_t r = bfs_farness(&g, v, d, q, &far);
+        out[v] = (r <= 1 || n <= 1) ? 0.0 : ((double)(r - 1) / (double)(n - 1)) * ((double)(r - 1) / (double)far);
+    }
+    free(d); free(q);
+    return OR_OK;
+}
+
+/*
+ * Eppstein-Wang sampled closeness: with the sources S (k of them),
+ *     F(v) = n / k * sum over s in S of d(s, v)   (unreachable pairs add 0),
+ *     C(v) = (n - 1) / F(v),  0 when no source reaches v (F = 0).
+ * The distance sums are kept as exact integers; sums[v] (optional, k-sum of
+ * distances) is returned for inspection.
+ */
+int or_closeness_approx(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                        const int32_t *src, int32_t k, double *out, int64_t *sums) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n == 0) return OR_OK;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *acc = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    if (!d || !q || !acc) { free(d); free(q); free(acc); return OR_E_NO_MEMORY; }
+    for (int32_t i = 0; i < n; ++i) d[i] = -1;
+    for (int32_t i = 0; i < k; ++i) {
+        int32_t s = src[i], head = 0, tail = 0;
+        d[s] = 0;
+        q[tail++] = s;
+        while (head < tail) {
+            int32_t v = q[head++];
+            acc[v] += d[v];
+            for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+                int32_t w = colidx[e];
+                if (d[w] < 0) { d[w] = d[v] + 1; q[tail++] = w; }
+            }
+        }
+        for (int32_t t = 0; t < tail; ++t) d[q[t]] = -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        double F = k > 0 ? (double)n / (double)k * (double)acc[v] : 0.0;
+        out[v] = F > 0.0 ? (double)(n - 1) / F : 0.0;
+        if (sums) sums[v] = acc[v];
+    }
+    free(d); free(q); free(acc);
     return OR_OK;
 }
 
