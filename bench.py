@@ -137,6 +137,30 @@ def other_workload(args) -> dict:
             print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
             rec["cpu_baseline"] = cpu_baseline(g, src, g.m_undirected,
                                                kind="linear" if args.workload == "rmat20_linear" else "edge")
+    elif args.workload == "rmat20_closeness":
+        print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
+        g, src = gg.workload_rmat20(2)
+        rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
+        k = len(src)
+        out = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sec = _timed(lambda: nk.nk_closeness_sampled(rp, ci, sv, out=out), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        rec.update(metric="GTEPS, Eppstein-Wang sampled closeness", unit="GTEPS", dtype="int64+f64",
+                   value=round(k * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": "rmat20_closeness_sources4096", "n": g.n, "arcs": g.m, "sources": k,
+                           "kernel_ms": st["kernel_us"] / 1e3, "block": st["block"],
+                           "workgroups": st["workgroups"], "levels_bu": st["levels_bu"]})
+        if not args.no_cpu_baseline:
+            print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            oracle.closeness_approx(g.rowptr, g.colidx, src[:16])
+            per = max((time.perf_counter() - t0) / 16, 1e-4)
+            kc = int(max(16, min(k, 15.0 / per)))
+            t0 = time.perf_counter()
+            oracle.closeness_approx(g.rowptr, g.colidx, src[:kc])
+            dt = time.perf_counter() - t0
+            rec["cpu_baseline"] = {"value": round(kc * g.m_undirected / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                                   "kind": "oracle", "sample": f"first {kc} of the {k} sources, {dt:.1f} s"}
     elif args.workload == "er2000":
         g = gg.workload_er2000(1)
         rp, ci = up(g.rowptr), up(g.colidx)
@@ -278,7 +302,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--workload", default="rmat20",
                     choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear",
-                             "rmat20_edge"],
+                             "rmat20_edge", "rmat20_closeness"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -147,6 +147,28 @@ nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, in
                      int32_t k, double scale, double *ebc, double *bc, void *stream);
 
 /*
+ * Closeness (Table 1, "closeness": one shortest-path search from each
+ * node), generalised to disconnected graphs: with r the number of vertices
+ * reachable from v (v included) and F the sum of their distances,
+ *     out[v] = (r - 1) / (n - 1) * (r - 1) / F,  0 for an isolated vertex,
+ * which is (n - 1) / F on a connected graph.
+ *   out  FP64[n] DEVICE, overwritten.
+ */
+nk_status nk_closeness(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, double *out,
+                       void *stream);
+
+/*
+ * Sampled closeness of Eppstein and Wang (Table 1, "ap. closeness"): the
+ * farness of v is estimated as F(v) = n / k * sum over the k sources of
+ * d(s, v) (an unreachable pair adds 0; the sums are exact integers), and
+ *     out[v] = (n - 1) / F(v),  0 where no source reaches v.
+ *   sources  int32[k] DEVICE array (repeats count once per occurrence);
+ *   out      FP64[n] DEVICE, overwritten; k = 0 writes zeros.
+ */
+nk_status nk_closeness_sampled(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double *out, void *stream);
+
+/*
  * Forward phase only, for inspection: distance and shortest-path count from
  * each of k sources (the breadth-first search with path counting that
  * Brandes' algorithm runs per source).

@@ -32,7 +32,7 @@ NK_E_INTERNAL = -8
 
 EXPORTS = [
     "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
-    "nk_bc_sources_linear", "nk_edge_bc",
+    "nk_bc_sources_linear", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
@@ -71,6 +71,8 @@ def load():
         "nk_bc_sources": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_bc_sources_linear": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_edge_bc": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp, vp]),
+        "nk_closeness": (c.c_int32, g + [vp, vp]),
+        "nk_closeness_sampled": (c.c_int32, g + [vp, c.c_int32, vp, vp]),
         "nk_sssp_counts": (c.c_int32, g + [vp, c.c_int32, vp, vp, vp]),
         "nk_vd_bound": (c.c_int32, g + [i32p, vp]),
         "nk_rk_sample_size": (c.c_int64, [c.c_double, c.c_double, c.c_int32]),
@@ -195,6 +197,29 @@ def nk_edge_bc(rowptr, colidx, sources=None, scale: float = 1.0, stream=None):
     bp = _dev(bc, torch.float64, "bc") if n > 0 else ctypes.c_void_p(0)
     _check(load().nk_edge_bc(rp, ci, n, m, sp, k, float(scale), ep, bp, _stream(stream)))
     return ebc, bc
+
+
+def nk_closeness(rowptr, colidx, out=None, stream=None):
+    """Exact closeness (generalised to disconnected graphs), FP64[n]."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    _check(load().nk_closeness(rp, ci, n, m, _dev(out, torch.float64, "out") if n > 0 else ctypes.c_void_p(0),
+                               _stream(stream)))
+    return out
+
+
+def nk_closeness_sampled(rowptr, colidx, sources, out=None, stream=None):
+    """Eppstein-Wang sampled closeness over `sources`, FP64[n]."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    k = sources.numel()
+    sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
+    _check(load().nk_closeness_sampled(rp, ci, n, m, sp, k,
+                                       _dev(out, torch.float64, "out") if n > 0 else ctypes.c_void_p(0),
+                                       _stream(stream)))
+    return out
 
 
 def nk_sssp_counts(rowptr, colidx, sources, stream=None):

@@ -653,6 +653,93 @@ nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, in
     return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, vb, stream, 0, ebc);
 }
 
+// Shared body of nk_closeness (sources NULL: every vertex, exact form into
+// out by source) and nk_closeness_sampled (Eppstein-Wang form over sources).
+static nk_status closeness_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                                const int32_t *sources, int32_t k, double *out, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n == 0) return NK_OK;
+    if (!out) return fail(NK_E_INVALID_ARG, "out is NULL");
+    const bool sampled = sources != nullptr || k != n;
+    if (k < 0 || (sampled && k > 0 && !sources)) return fail(NK_E_INVALID_ARG, "bad sources");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    uint32_t *iso;
+    unsigned long long *acc = nullptr;
+    const long long words = ((long long)n + 31) / 32;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    if ((st = scr.get(words, &iso)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    NK_HIP(launch_fill_f64(out, 0.0, n, s));
+    LaunchPlan plan = {};
+    float ms = 0.0f;
+    if (k > 0) {
+        Relabeled g;
+        if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
+        const int32_t *src = sources;
+        if (g.perm && sources) {
+            int32_t *mapped;
+            if ((st = scr.get(k, &mapped)) != NK_OK) return st;
+            NK_HIP(launch_map_sources(sources, k, g.perm, n, mapped, s));
+            src = mapped;
+        }
+        if (sampled) {
+            if ((st = scr.get(n, &acc)) != NK_OK) return st;
+            NK_HIP(launch_fill_u64(acc, 0ULL, n, s));
+        }
+        if ((st = plan_launch(kModeClose, n, k, 0, &plan)) != NK_OK) return st;
+        Params p;
+        memset(&p, 0, sizeof(p));
+        p.rowptr = g.rowptr;
+        p.colidx = g.colidx;
+        p.n = n;
+        p.m = (int32_t)m;
+        p.ntasks = k;
+        p.sources = src;
+        p.inv = g.inv;
+        p.iso = iso;
+        p.st = dst;
+        p.close_out = sampled ? nullptr : out;
+        p.close_acc = acc;
+        hipEvent_t ev0, ev1;
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+        if (sampled) NK_HIP(launch_close_finish(acc, g.perm, n, k, out, s));
+        st = finish(dst, h, s);
+        NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    } else {
+        st = finish(dst, h, s);
+    }
+    stats_record(*h, plan.grid, plan.block, plan.lds, ms);
+    return st;
+}
+
+nk_status nk_closeness(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, double *out,
+                       void *stream) {
+    return closeness_impl(rowptr, colidx, n, m, nullptr, n, out, stream);
+}
+
+nk_status nk_closeness_sampled(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double *out, void *stream) {
+    if (k > 0 && !sources) {
+        clear_error();
+        return fail(NK_E_INVALID_ARG, "sources is NULL");
+    }
+    if (k == 0) {
+        // no sources: every estimate is 0 (keeps the exact form out of reach)
+        return closeness_impl(rowptr, colidx, n, m, nullptr, 0, out, stream);
+    }
+    return closeness_impl(rowptr, colidx, n, m, sources, k, out, stream);
+}
+
 nk_status nk_sssp_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
                          const int32_t *sources, int32_t k, int32_t *d, uint64_t *sigma, void *stream) {
     clear_error();

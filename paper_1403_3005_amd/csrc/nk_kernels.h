@@ -13,7 +13,8 @@ namespace nk {
 enum Mode : int {
     kModeBC = 0,    // forward + dependency sweep, scores into bc
     kModeSSSP = 1,  // forward only, d and sigma written out per task
-    kModePair = 2   // one sampled pair: bidirectional search and path walk
+    kModePair = 2,  // one sampled pair: bidirectional search and path walk
+    kModeClose = 3  // forward with unit path counts; distance sums for closeness
 };
 
 // Everything a persistent launch reads.  Per-slot scratch arrays hold
@@ -81,6 +82,10 @@ struct Params {
     int32_t *ld2;
     int32_t *lvl2;
     uint32_t *bmg2;
+    // closeness mode: per-source closeness by original id (exact form), or
+    // per-vertex integer distance sums over the sources (sampled form)
+    double *close_out;
+    unsigned long long *close_acc;
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.
@@ -116,6 +121,9 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long lon
 hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s);
+// Sampled closeness: out[o] = (n-1) / (n/k * acc[perm[o]]) (0 where acc = 0).
+hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,
+                               hipStream_t s);
 // Degree-descending relabelling of a single graph (nk_relabel.hip).
 struct Relabeled {
     const int32_t *rowptr;  // CSR in internal ids (the input when not relabelled)

@@ -152,7 +152,8 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     const int tid = threadIdx.x;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
-        if (tid < cnt) sm.val.u[tid] = s.sigma[s.lv[tb + tid]];
+        // closeness needs distances only: unit counts keep them from wrapping
+        if (tid < cnt) sm.val.u[tid] = (MODE == kModeClose) ? 1ULL : s.sigma[s.lv[tb + tid]];
         const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
@@ -236,7 +237,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 const bool act = kk[j] >= 0 && bit_test(bm, v[j]);
-                sv[j] = act ? s.sigma[v[j]] : 0ULL;
+                sv[j] = act ? ((MODE == kModeClose) ? 1ULL : s.sigma[v[j]]) : 0ULL;
             }
             int32_t kcur = kk[0];
             unsigned long long acc = 0ULL;
@@ -971,7 +972,23 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             c.tasks++;
         }
 
-        if (MODE == kModeBC) {
+        if (MODE == kModeClose) {
+            if (p.close_out && tid == 0) {
+                // distance sum from the level sizes; generalised closeness
+                long long far = 0;
+                for (int32_t l = 1; l <= Ld; ++l) far += (long long)l * (s.lvl[l + 1] - s.lvl[l]);
+                const int32_t o = p.inv ? p.inv[src] : src;
+                p.close_out[o] = (nreached <= 1 || g.n <= 1)
+                                     ? 0.0
+                                     : ((double)(nreached - 1) / (double)(g.n - 1)) *
+                                           ((double)(nreached - 1) / (double)far);
+            }
+            if (p.close_acc) {
+                for (int32_t l = 1; l <= Ld; ++l)
+                    for (int32_t i = s.lvl[l] + tid; i < s.lvl[l + 1]; i += BLOCK)
+                        atomicAdd(p.close_acc + s.lv[i], (unsigned long long)l);
+            }
+        } else if (MODE == kModeBC) {
             backward<BLOCK>(p, sm, bm, s, g, Ld, p.bc + g.vbase, c);
         } else if (MODE == kModeSSSP) {
             const long long row = task * (long long)g.n;
@@ -1037,6 +1054,7 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
         case kModeBC: return ref_mode<kModeBC>(block, bitmap_in_lds);
         case kModeSSSP: return ref_mode<kModeSSSP>(block, bitmap_in_lds);
         case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
+        case kModeClose: return ref_mode<kModeClose>(block, bitmap_in_lds);
         default: return ref_mode<kModeBC>(block, bitmap_in_lds);
     }
 }
@@ -1142,11 +1160,27 @@ __global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long 
     if (lane_id() == 0) atomicMax(key, best);
 }
 
+__global__ void k_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k,
+                               double *out) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += stride) {
+        const unsigned long long a = acc[perm ? perm[o] : o];
+        const double F = (double)n / (double)k * (double)a;
+        out[o] = F > 0.0 ? (double)(n - 1) / F : 0.0;
+    }
+}
+
 static inline unsigned grid_for(long long count, int block) {
     long long g = (count + block - 1) / block;
     if (g < 1) g = 1;
     if (g > 65536) g = 65536;
     return (unsigned)g;
+}
+
+hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_close_finish, dim3(grid_for(n, 256)), dim3(256), 0, s, acc, perm, n, k, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_status_init(DevStatus *st, hipStream_t s) {
