@@ -299,6 +299,27 @@ def test_vd_bound_matches_oracle(make):
     assert nk.nk_vd_bound(rp, ci) == oracle.vd_bound(g.rowptr, g.colidx)
 
 
+def _deferred_bottom_up_graph():
+    """A graph whose breadth-first sweep from the hub takes a bottom-up
+    step in which an unreached vertex of degree 301 finds its only frontier
+    neighbour after its first 256 arcs (the wave-per-vertex pass), plus a
+    second component of 350 vertices."""
+    edges = [(0, 10000 + i) for i in range(1000)]            # hub 0, level 1 at ids 10000..10999
+    edges += [(5000, 2000 + i) for i in range(300)]          # vertex 5000: 300 leaves with low ids ...
+    edges.append((5000, 10999))                              # ... then its frontier neighbour
+    edges += [(20000 + i, 20001 + i) for i in range(349)]    # a path of 350 vertices elsewhere
+    u, v = zip(*edges)
+    return gg.from_edges(20400, np.array(u), np.array(v), "deferred-bottom-up")
+
+
+def test_vd_bound_deferred_bottom_up():
+    g = _deferred_bottom_up_graph()
+    rp, ci = upload(g)
+    info = nk.nk_vd_bound(rp, ci)
+    assert info == oracle.vd_bound(g.rowptr, g.colidx)
+    assert info["c2"] == 350 and info["e1"] == 3
+
+
 @pytest.mark.parametrize("make,r,seed", [
     (lambda: gg.grid(8, 9), 3000, 5), (lambda: gg.erdos_renyi(600, 1500, 81), 2000, 6),
     (lambda: gg.barabasi_albert(2000, 3, 82), 1500, 7), (lambda: gg.rmat(11, 16, 83), 1000, 8),
