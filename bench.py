@@ -161,6 +161,25 @@ def other_workload(args) -> dict:
             dt = time.perf_counter() - t0
             rec["cpu_baseline"] = {"value": round(kc * g.m_undirected / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
                                    "kind": "oracle", "sample": f"first {kc} of the {k} sources, {dt:.1f} s"}
+    elif args.workload == "er200k":
+        # the shape that holds most of the batched workload's work: ER, n = 2e5, mean degree 8
+        g = gg.erdos_renyi(200_000, 800_000, 7)
+        src = np.arange(4096, dtype=np.int32)
+        rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
+        bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sec = _timed(lambda: nk.nk_bc_sources(rp, ci, sv, g.n / 4096, bc=bc), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        alg = 68 * st["reached"] + 16 * st["arcs_reached"] + 24 * st["dag_arcs"]
+        kern_s = st["kernel_us"] * 1e-6
+        rec.update(metric="GTEPS, source-sampled Brandes", unit="GTEPS", dtype="f64",
+                   value=round(4096 * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": "er200k_sources4096", "graph": "Erdos-Renyi G(2e5, 8e5), seed 7",
+                           "n": g.n, "arcs": g.m, "sources": 4096, "kernel_ms": kern_s * 1e3,
+                           "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"]},
+                   roofline={"bound": "hbm", "achieved": round(alg / kern_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / PEAK_HBM_GBS, 4),
+                             "traffic": counter_traffic("er200k_sources4096"), "kernel": KERNEL,
+                             "algorithmic_bytes_per_launch": alg})
     elif args.workload == "er2000":
         g = gg.workload_er2000(1)
         rp, ci = up(g.rowptr), up(g.colidx)
@@ -302,7 +321,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=96)
     ap.add_argument("--workload", default="rmat20",
                     choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear",
-                             "rmat20_edge", "rmat20_closeness"],
+                             "rmat20_edge", "rmat20_closeness", "er200k"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
     if args.gpus != 1:
