@@ -307,6 +307,56 @@ def serving_run(qps: float, count: int) -> dict:
             "pool": "R-MAT scales 14-17 (ef 16) + BA n in {1e4, 3e4, 1e5, 3e5} (m0 4)"}
 
 
+def serving_sweep(warm: int, measured: int) -> dict:
+    """The serving configuration: a resident pool of 64 graphs (32 R-MAT of
+    scales 14-20 with edge factor 16, 32 Barabasi-Albert with n log-uniform
+    in [1e4, 1e6]); requests uniform over the pool and over k in {64, 256,
+    1024} and pair sampling at eps in {0.05, 0.02} (delta 0.1).  First the
+    saturation throughput (every request submitted at once), then Poisson
+    arrivals at 0.25, 0.5, 0.75 and 0.9 of it, each after `warm` warm-up
+    requests.  Latency is submit to scores in host memory."""
+    import torch
+
+    import graphgen as gg
+    import paper_1403_3005_amd as nk
+    from paper_1403_3005_amd.serving import latency_summary, replay
+
+    print("bench: serving sweep: building the 64-graph pool", file=sys.stderr, flush=True)
+    pool = []
+    for i, g in enumerate(gg.serving_pool(64, 5)):
+        pool.append(g)
+        if (i + 1) % 8 == 0:
+            print(f"bench: {i + 1} graphs built", file=sys.stderr, flush=True)
+    sizes = [g.n for g in pool]
+    dev = torch.device("cuda:0")
+    out = {"pool": "32 R-MAT (scales 14-20, ef 16) + 32 BA (n in [1e4, 1e6], m0 4)", "graphs": len(pool),
+           "pool_vertices": int(sum(sizes)), "pool_arcs": int(sum(g.m for g in pool)), "points": []}
+    with nk.NkServer(96 << 30, slots=4) as server:
+        ids = [server.add_graph(torch.from_numpy(g.rowptr).to(dev), torch.from_numpy(g.colidx).to(dev)) for g in pool]
+        replay(server, ids, gg.request_stream(warm, 1e9, sizes, seed=55))
+        server.reset_stats()
+        sat_reqs = gg.request_stream(measured, 1e9, sizes, seed=56)
+        print(f"bench: saturation run, {measured} requests", file=sys.stderr, flush=True)
+        res, wall = replay(server, ids, sat_reqs)
+        sat = measured / wall
+        lat = latency_summary(res)
+        out["saturation_rps"] = round(sat, 2)
+        out["saturation_gteps"] = round(server.stats()["gteps"], 3)
+        out["points"].append({"fraction": "all at once", "qps": None, "p50_ms": round(lat["p50_ms"], 2),
+                              "p99_ms": round(lat["p99_ms"], 2), "achieved_rps": round(sat, 2)})
+        for i, f in enumerate((0.25, 0.5, 0.75, 0.9)):
+            qps = f * sat
+            reqs = gg.request_stream(warm + measured, qps, sizes, seed=57 + i)
+            print(f"bench: {f:.2f} of saturation ({qps:.1f} QPS), {warm + measured} requests", file=sys.stderr,
+                  flush=True)
+            res, wall = replay(server, ids, reqs)
+            lat = latency_summary(res[warm:])
+            out["points"].append({"fraction": f, "qps": round(qps, 2), "p50_ms": round(lat["p50_ms"], 2),
+                                  "p99_ms": round(lat["p99_ms"], 2), "mean_ms": round(lat["mean_ms"], 2),
+                                  "achieved_rps": round(len(reqs) / wall, 2)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,10 +368,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--serving-qps", type=float, default=8.0)
-    ap.add_argument("--serving-requests", type=int, default=96)
+    ap.add_argument("--serving-requests", type=int, default=96,
+                    help="requests of the default serving line; measured requests per point of --workload serving")
+    ap.add_argument("--serving-warm", type=int, default=50, help="warm-up requests per point of --workload serving")
     ap.add_argument("--workload", default="rmat20",
                     choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear",
-                             "rmat20_edge", "rmat20_closeness", "er200k"],
+                             "rmat20_edge", "rmat20_closeness", "er200k", "serving"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -348,6 +400,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 4}), flush=True)
+        return
+    if args.workload == "serving":
+        rec = {"metric": "p50 / p99 request latency of the betweenness server (ms)", "n_gpus": 1,
+               "higher_is_better": False, "data": "synthetic", "dtype": "f64"}
+        rec.update(serving_sweep(args.serving_warm, args.serving_requests))
+        print(json.dumps(rec), flush=True)
         return
     if args.workload != "rmat20":
         print(json.dumps(other_workload(args)), flush=True)

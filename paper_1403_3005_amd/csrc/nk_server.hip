@@ -111,7 +111,15 @@ static size_t request_footprint(const ServerGraph &g, long long k, int grid, boo
     b += round256((size_t)g.n * 8);     // accumulator / counts
     b += round256((size_t)std::max<long long>(k, 1) * 4) * 2;
     b += round256(sizeof(DevStatus));
-    (void)pair;
+    if (pair) {
+        // second side of the bidirectional search and both visited bitmaps
+        const long long words = (((long long)g.n + 31) / 32 + 63) / 64 * 64;
+        b += round256(cells * 8);           // sigma2
+        b += round256(cells * 4) * 5;       // d2, lv2, la2, ld2, lvl2
+        b += round256((long long)grid * words * 4) * 2;
+    } else {
+        b += round256((size_t)((g.n + 31) / 32) * 4);   // isolated-vertex bitmap
+    }
     return b;
 }
 
