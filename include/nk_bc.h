@@ -296,7 +296,13 @@ nk_status nk_last_stats(int64_t *out);
  *              about 16 n + 4 m bytes, fits one workgroup's LDS);
  *   bw_ratio   in the dependency sweep, handle level l by pushing from level
  *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
- *              of level l (0 = always pull; default 0.1).
+ *              of level l (0 = always pull; default 0.1);
+ *   scratch_mib  cap, in MiB, on the per-call scratch of the persistent
+ *              kernel's workgroup slots (about 44 bytes per vertex per slot,
+ *              72 in pair sampling); 0 = 85% of the device memory that is
+ *              free or idle in the library's pool.  The grid shrinks to fit;
+ *              if a single slot does not fit the call fails with
+ *              NK_E_NO_MEMORY.
  * nk_set_tuning applies to later calls from every thread.
  */
 typedef struct {
@@ -305,7 +311,8 @@ typedef struct {
     int32_t wg_per_cu;
     int32_t flags;
     float bw_ratio;
-    int32_t reserved[3];
+    int32_t scratch_mib;
+    int32_t reserved[2];
 } nk_tuning;
 
 nk_status nk_set_tuning(const nk_tuning *t);

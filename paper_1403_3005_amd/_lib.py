@@ -48,7 +48,8 @@ class NkError(RuntimeError):
 
 class NkTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("bu_ratio", ctypes.c_float), ("wg_per_cu", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("bw_ratio", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+                ("flags", ctypes.c_int32), ("bw_ratio", ctypes.c_float), ("scratch_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 def load():
@@ -305,8 +306,9 @@ def nk_last_stats() -> dict:
     return {k: int(v) for k, v in zip(STAT_KEYS, out)}
 
 
-def nk_set_tuning(block: int = 0, bu_ratio: float = 16.0, wg_per_cu: int = 0, flags: int = 0, bw_ratio: float = 0.1):
-    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio)
+def nk_set_tuning(block: int = 0, bu_ratio: float = 16.0, wg_per_cu: int = 0, flags: int = 0, bw_ratio: float = 0.1,
+                  scratch_mib: int = 0):
+    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio, scratch_mib)
     _check(load().nk_set_tuning(ctypes.byref(t)))
 
 
@@ -314,12 +316,12 @@ def nk_get_tuning() -> dict:
     t = NkTuning()
     _check(load().nk_get_tuning(ctypes.byref(t)))
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
-            "bw_ratio": t.bw_ratio}
+            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib}
 
 
 def _tuning_dict(t) -> dict:
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
-            "bw_ratio": t.bw_ratio}
+            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib}
 
 
 def nk_autotune(rowptr, colidx, sources, cache_path: str | None = None, stream=None) -> dict:

@@ -155,6 +155,16 @@ void pool_clear() {
     (void)hipSetDevice(cur);
 }
 
+size_t pool_bytes_idle() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    size_t s = 0;
+    for (auto &b : g_pool)
+        if (!b.busy && b.device == dev) s += b.bytes;
+    return s;
+}
+
 size_t pool_bytes_in_use() {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     size_t s = 0;
@@ -166,7 +176,7 @@ size_t pool_bytes_in_use() {
 // ------------------------------------------------------------------ tuning --
 
 static std::mutex g_tune_mu;
-static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, {0, 0, 0}};
+static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, 0, {0, 0}};
 
 nk_tuning tuning_get() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -285,6 +295,29 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     if (ntasks < grid) grid = ntasks;
     if (max_slots > 0 && grid > max_slots) grid = max_slots;
     if (grid < 1) grid = 1;
+    // Cap the grid so the slots' scratch fits: per vertex 8 (path counts)
+    // + 8 (push accumulator) + 7 x 4 (level sums, d, lists, candidates), the
+    // pair search's second side 8 + 5 x 4 more, plus global bitmaps.
+    {
+        const long long stride = (((long long)n_max + 2) + 63) / 64 * 64;
+        const long long wordsr = (words + 63) / 64 * 64;
+        size_t per_slot = (size_t)stride * 44;
+        if (mode == kModePair) per_slot += (size_t)stride * 28 + (size_t)wordsr * 8;
+        else if (!lds) per_slot += (size_t)wordsr * 4;
+        size_t avail;
+        if (t.scratch_mib > 0) {
+            avail = (size_t)t.scratch_mib << 20;
+        } else {
+            size_t fr = 0, tot = 0;
+            NK_HIP(hipMemGetInfo(&fr, &tot));
+            avail = (size_t)((double)(fr + pool_bytes_idle()) * 0.85);
+        }
+        const long long fit = (long long)(avail / per_slot);
+        if (fit < 1)
+            return fail(NK_E_NO_MEMORY, "one workgroup slot needs %zu bytes of scratch; %zu available", per_slot,
+                        avail);
+        if (grid > fit) grid = fit;
+    }
     plan->mode = mode;
     plan->block = block;
     plan->lds = lds;
@@ -463,7 +496,7 @@ nk_status nk_set_tuning(const nk_tuning *t) {
     if (!t) return fail(NK_E_INVALID_ARG, "tuning is NULL");
     if (t->block != 0 && t->block != 256 && t->block != 512 && t->block != 1024)
         return fail(NK_E_INVALID_ARG, "block must be 0, 256, 512 or 1024");
-    if (!(t->bu_ratio >= 0.0f) || !(t->bw_ratio >= 0.0f) || t->wg_per_cu < 0)
+    if (!(t->bu_ratio >= 0.0f) || !(t->bw_ratio >= 0.0f) || t->wg_per_cu < 0 || t->scratch_mib < 0)
         return fail(NK_E_INVALID_ARG, "bad tuning values");
     tuning_set(*t);
     return NK_OK;

@@ -51,6 +51,7 @@ private:
 };
 void pool_clear();
 size_t pool_bytes_in_use();
+size_t pool_bytes_idle();   // idle pooled bytes on the current device
 
 nk_tuning tuning_get();
 void tuning_set(const nk_tuning &t);

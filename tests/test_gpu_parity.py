@@ -171,6 +171,30 @@ def test_launch_variants(block, bu_ratio, flags, bw_ratio):
         assert np.array_equal(s[i].cpu().numpy().view(np.uint64), os_)
 
 
+def test_scratch_cap_shrinks_the_grid():
+    """A scratch cap of 8 MiB leaves room for 11 slots of a 16k-vertex graph
+    (44 bytes per vertex per slot); results stay exact.  A cap below one
+    slot is NK_E_NO_MEMORY.  Pair sampling honours the cap too."""
+    g = gg.rmat(14, 16, 44)
+    rp, ci = upload(g)
+    src = gg.sample_sources(g.n, 100, 45)
+    nk.nk_set_tuning(flags=4, scratch_mib=8)
+    got = nk.nk_bc_sources(rp, ci, ivec(src), 1.0).cpu().numpy()
+    stride = (g.n + 2 + 63) // 64 * 64
+    assert nk.nk_last_stats()["workgroups"] == (8 << 20) // (stride * 44)
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src), "capped")
+    cnt = nk.nk_pair_counts(rp, ci, 300, 46).cpu().numpy().view(np.uint32)
+    assert nk.nk_last_stats()["workgroups"] <= (8 << 20) // (stride * 72)
+    assert np.array_equal(cnt, oracle.pair_counts(g.rowptr, g.colidx, 300, 46))
+    nk.nk_set_tuning(flags=4, scratch_mib=0)
+    big = gg.rmat(15, 16, 47)
+    rp2, ci2 = upload(big)
+    nk.nk_set_tuning(flags=4, scratch_mib=1)
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_sources(rp2, ci2, ivec([0, 1]), 1.0)
+    assert e.value.code == nk.NK_E_NO_MEMORY
+
+
 @pytest.mark.parametrize("flags", PATHS)
 def test_work_counters_match_oracle(flags):
     # top-down only (the all-in-LDS kernel always is): forward arcs = arcs of reached vertices
