@@ -295,15 +295,15 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     if (ntasks < grid) grid = ntasks;
     if (max_slots > 0 && grid > max_slots) grid = max_slots;
     if (grid < 1) grid = 1;
-    // Cap the grid so the slots' scratch fits: per vertex 8 (path counts)
-    // + 8 (push accumulator) + 7 x 4 (level sums, d, lists, candidates), the
-    // pair search's second side 8 + 5 x 4 more, plus global bitmaps.
+    // Cap the grid so the slots' scratch fits.
     {
         const long long stride = (((long long)n_max + 2) + 63) / 64 * 64;
         const long long wordsr = (words + 63) / 64 * 64;
-        size_t per_slot = (size_t)stride * 44;
-        if (mode == kModePair) per_slot += (size_t)stride * 28 + (size_t)wordsr * 8;
-        else if (!lds) per_slot += (size_t)wordsr * 4;
+        // pair sampling: 32-byte records, 8 (weights) and 6 x 4 (two sides'
+        // lists) + 4 (meeting list); otherwise 8 + 8 + 7 x 4 and a global
+        // bitmap when it does not sit in LDS
+        size_t per_slot = (size_t)stride * (mode == kModePair ? 68 : 44);
+        if (mode != kModePair && !lds) per_slot += (size_t)wordsr * 4;
         size_t avail;
         if (t.scratch_mib > 0) {
             avail = (size_t)t.scratch_mib << 20;
@@ -370,40 +370,41 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     const long long slots = plan.grid;
     const long long cells = slots * plan.stride;
     nk_status st;
-    if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
+    const bool pair = plan.mode == kModePair;
+    p.sigma = nullptr;
+    p.ldeg = nullptr;
+    p.d = nullptr;
+    p.lvl = nullptr;
+    p.bmg = nullptr;
+    p.pair_rec = nullptr;
+    p.lv2 = p.la2 = p.ld2 = nullptr;
     if ((st = scr.get(cells, &p.dacc)) != NK_OK) return st;
-    if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
-    if ((st = scr.get(cells, &p.d)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.ld)) != NK_OK) return st;
-    if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.cand)) != NK_OK) return st;
-    p.bmg = nullptr;
-    if (!plan.lds)
-        if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
-    if (plan.mode == kModePair) {
-        // second side of the bidirectional pair search; both bitmaps start
-        // empty and each sample clears what it touched
-        if ((st = scr.get(cells, &p.sigma2)) != NK_OK) return st;
-        if ((st = scr.get(cells, &p.d2)) != NK_OK) return st;
+    if (pair) {
+        // 32-byte records of both search sides, the target side's lists
+        if ((st = scr.get((size_t)cells * 32, &p.pair_rec)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.lv2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.la2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ld2)) != NK_OK) return st;
-        if ((st = scr.get(cells, &p.lvl2)) != NK_OK) return st;
-        if ((st = scr.get(slots * plan.bm_words, &p.bmg2)) != NK_OK) return st;
-        NK_HIP(launch_fill_u64(p.sigma2, 0ULL, cells, s));
-        NK_HIP(launch_fill_u32(p.bmg, 0u, slots * plan.bm_words, s));
-        NK_HIP(launch_fill_u32(p.bmg2, 0u, slots * plan.bm_words, s));
+        NK_HIP(launch_pair_rec_init(p.pair_rec, cells, s));
+    } else {
+        if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.d)) != NK_OK) return st;
+        if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
+        if (!plan.lds)
+            if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
+        NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
+        // the push accumulator of the dependency sweep must start at zero
+        if (plan.mode == kModeBC) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
     }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
     p.bu_ratio = tuning_get().bu_ratio;
     p.bw_ratio = tuning_get().bw_ratio;
-    NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
-    // the push accumulator of the dependency sweep must start at zero (pair
-    // mode uses the array only as a weight buffer it writes before reading)
-    if (plan.mode == kModeBC) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
     if (ev0) NK_HIP(hipEventRecord(ev0, s));
     plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
     NK_HIP(hipGetLastError());

@@ -73,15 +73,13 @@ struct Params {
     int32_t linear;
     int32_t pad1;
     double *ebc;
-    // pair mode: the second side (grown from the pair's target) of the
-    // bidirectional search; both visited bitmaps live in global memory
-    unsigned long long *sigma2;
-    int32_t *d2;
+    // pair mode: 32-byte per-vertex records of both search sides (path
+    // counts and distances from u and from v; `stride` records per slot)
+    // and the level lists of the side grown from the target
+    void *pair_rec;
     int32_t *lv2;
     int32_t *la2;
     int32_t *ld2;
-    int32_t *lvl2;
-    uint32_t *bmg2;
     // closeness mode: per-source closeness by original id (exact form), or
     // per-vertex integer distance sums over the sources (sampled form)
     double *close_out;
@@ -122,6 +120,8 @@ hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s);
 // Sampled closeness: out[o] = (n-1) / (n/k * acc[perm[o]]) (0 where acc = 0).
+// Pair mode: every record unreached (path counts 0, distances -1).
+hipError_t launch_pair_rec_init(void *rec, long long count, hipStream_t s);
 hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,
                                hipStream_t s);
 // Degree-descending relabelling of a single graph (nk_relabel.hip).

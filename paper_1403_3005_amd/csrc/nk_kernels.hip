@@ -574,7 +574,58 @@ __device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long 
     __syncthreads();
 }
 
-// Walk from `from` to the root `rootv` of one search side, all threads of
+// Pair mode keeps both search sides' state of a vertex in one 32-byte
+// record, so the visited test, the path-count update, the meeting test and
+// the walk's predecessor test each touch one cache line.  d = -1 is
+// unreached; a sample resets the records it touched.
+struct PairRec {
+    unsigned long long sig[2];   // path counts from u (side 0) and from v (side 1)
+    int32_t d[2];                // distances from u and from v
+    int32_t pad[2];
+};
+
+// Top-down growth of side X by one level (list[f0, f1) at distance dep)
+// into list[f1, ...): every arc y -> z with z not reached by X before this
+// level adds sigma_X(y) to sigma_X(z); the first adder appends z.
+template <int BLOCK>
+__device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, const Scr &s, const GView &g,
+                           int32_t f0, int32_t f1, int32_t dep, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t tb = f0; tb < f1; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, f1 - tb);
+        if (tid < cnt) sm.val.u[tid] = R[s.lv[tb + tid]].sig[X];
+        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+        __syncthreads();
+        if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            int32_t kk[kChunk], w[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+            bool act[kChunk];
+            unsigned long long add[kChunk], old[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                // unreached, or reached on this very level by another adder
+                const int32_t dz = kk[j] >= 0 ? R[w[j]].d[X] : 0;
+                act[j] = kk[j] >= 0 && (dz < 0 || dz == dep + 1);
+                add[j] = act[j] ? sm.val.u[kk[j]] : 0ULL;
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) old[j] = act[j] ? atomicAdd(&R[w[j]].sig[X], add[j]) : 1ULL;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                if (act[j]) {
+                    c.dag++;
+                    if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                    if (old[j] == 0ULL) R[w[j]].d[X] = dep + 1;
+                }
+                wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Walk from `from` to the root `rootv` of search side X, all threads of
 // the block together (the same choice as the oracle's walk: at w, step t,
 // r = bounded(draw(seed, stream, j, t), sigma[w]) and the first neighbour
 // in adjacency order one level closer to the root whose running sigma sum
@@ -585,20 +636,19 @@ __device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long 
 // i = 1, 2, ..., the root included.  Returns false if no predecessor is
 // found (only after a reported overflow).
 template <int BLOCK, typename Emit>
-__device__ bool walk_block(const Params &p, BiState &bs, const uint32_t *bm, const unsigned long long *sigma,
-                           const int32_t *d, const GView &g, int32_t from, int32_t rootv, unsigned long long stream,
-                           long long j, Emit emit) {
+__device__ bool walk_block(const Params &p, BiState &bs, const PairRec *R, int X, const GView &g, int32_t from,
+                           int32_t rootv, unsigned long long stream, long long j, Emit emit) {
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = lane_id(), wid = wave_id();
     int32_t x = from;
     for (unsigned long long tt = 0;; ++tt) {
-        const int32_t dx = d[x];
+        const int32_t dx = R[x].d[X];
         if (dx <= 0) return true;
         if (dx == 1) {
             if (tid == 0) emit((int32_t)tt + 1, rootv);
             return true;
         }
-        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), sigma[x]);
+        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), R[x].sig[X]);
         const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         unsigned long long carry = 0ULL;
         int32_t pick = -1;
@@ -608,7 +658,7 @@ __device__ bool walk_block(const Params &p, BiState &bs, const uint32_t *bm, con
             unsigned long long sp = 0ULL;
             if (e < a1) {
                 pp = g.ci[e];
-                if (bit_test(bm, pp) && d[pp] == dx - 1) sp = sigma[pp];
+                if (R[pp].d[X] == dx - 1) sp = R[pp].sig[X];
             }
             const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
             if (lane == kWave - 1) bs.part_lo[wid] = incl;
@@ -650,28 +700,24 @@ __device__ bool walk_block(const Params &p, BiState &bs, const uint32_t *bm, con
 // probability sigma_A(z) sigma_B(z) / sigma_uv -- the first z in
 // increasing original id whose running weight exceeds the draw, found by a
 // binary search on the id threshold with one block reduction per step --
-// then wave 0 walks z -> v on side B (draw stream 5) and z -> u on side A
-// (stream 3).  Interior vertices are counted and, for inspection, written
-// from v's side towards u.  Touched entries are cleared at the end, so the
-// next sample starts from zeroed path counts and empty bitmaps.
+// then the block walks z -> v on side B (draw stream 5) and z -> u on side
+// A (stream 3).  Interior vertices are counted and, for inspection, written
+// from v's side towards u.  The records of every listed vertex are reset at
+// the end, so the next sample starts from unreached records.
 template <int BLOCK>
-__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Scr &sa, const Scr &sb,
-                             uint32_t *bma, uint32_t *bmb, const GView &g, int32_t u, int32_t v, long long j,
-                             long long task, Counters &c) {
+__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, PairRec *R, const Scr &sa,
+                             const Scr &sb, const GView &g, int32_t u, int32_t v, long long j, long long task,
+                             Counters &c) {
     const int tid = threadIdx.x;
     if (tid < 2) {
         const Scr &x = tid == 0 ? sa : sb;
-        uint32_t *bm = tid == 0 ? bma : bmb;
         const int32_t r = tid == 0 ? u : v;
         const int32_t a0 = g.rp[r], dg = g.rp[r + 1] - a0;
-        x.sigma[r] = 1ULL;
-        x.d[r] = 0;
-        bit_set(bm, r);
+        R[r].sig[tid] = 1ULL;
+        R[r].d[tid] = 0;
         x.lv[0] = r;
         x.la[0] = a0;
         x.ld[0] = dg;
-        x.lvl[0] = 0;
-        x.lvl[1] = 1;
         bs.lo[tid] = 0;
         bs.hi[tid] = 1;
         bs.depth[tid] = 0;
@@ -689,8 +735,6 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
     while (bs.result == 0) {
         const int X = bs.cost[0] <= bs.cost[1] ? 0 : 1;
         const Scr &sx = X == 0 ? sa : sb;
-        uint32_t *bmx = X == 0 ? bma : bmb;
-        const uint32_t *bmy = X == 0 ? bmb : bma;
         const int32_t lo = bs.lo[X], hi = bs.hi[X], dep = bs.depth[X];
         __syncthreads();
         if (tid == 0) {
@@ -699,7 +743,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             c.td++;
         }
         __syncthreads();
-        td_level<BLOCK, kModePair>(p, sm, bmx, sx, g, lo, hi, dep, c);
+        pair_level<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, c);
         __syncthreads();
         const int32_t nnew = sm.count < g.n - hi ? sm.count : g.n - hi;
         long long dsum = 0;
@@ -710,12 +754,11 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             bool meet = false;
             if (in) {
                 w = sx.lv[i];
-                bit_set(bmx, w);
                 const int32_t a0 = g.rp[w], dg = g.rp[w + 1] - a0;
                 sx.la[i] = a0;
                 sx.ld[i] = dg;
                 dsum += dg;
-                meet = bit_test(bmy, w);
+                meet = R[w].d[1 - X] >= 0;
             }
             // meeting vertices: new on side X and already reached by the other side
             wave_append(meet, w, sa.cand, &bs.nm, g.n, &p.st->err);
@@ -728,7 +771,6 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             bs.hi[X] = hi + nnew;
             bs.depth[X] = dep + 1;
             bs.cost[X] = bs.newcost;
-            sx.lvl[dep + 2] = hi + nnew;
             if (nnew == 0)
                 bs.result = -1;
             else if (bs.nm > 0)
@@ -748,7 +790,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         int32_t idlo = 0x7fffffff, idhi = -1;
         for (int32_t i = tid; i < nm; i += BLOCK) {
             const int32_t z = sa.cand[i];
-            const unsigned long long a = sa.sigma[z], b = sb.sigma[z];
+            const unsigned long long a = R[z].sig[0], b = R[z].sig[1];
             const unsigned long long w = a * b;
             if (__umul64hi(a, b) != 0ULL) wrap = true;
             wt[i] = w;
@@ -811,7 +853,6 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         }
         __syncthreads();
     }
-
     sub_mark<BLOCK>(sm, kSbPairSelect);
     // ---- walks (all threads; thread 0 records)
     if (bs.result == -1) {
@@ -820,7 +861,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         if (tid == 0 && p.p_len) p.p_len[task] = -3;
     } else {
         const int32_t z = bs.z;
-        const int32_t kb = sb.d[z], ha = sa.d[z];
+        const int32_t kb = R[z].d[1], ha = R[z].d[0];
         const int32_t nb = kb >= 1 ? kb - 1 : 0;
         const int32_t zc = (kb >= 1 && ha >= 1) ? 1 : 0;
         const int32_t len = nb + zc + (ha >= 1 ? ha - 1 : 0);
@@ -829,12 +870,12 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             if (p.p_path && pos < p.maxlen) p.p_path[task * p.maxlen + pos] = p.inv ? p.inv[vtx] : vtx;
         };
         // side B: steps 1 .. kb-1 are interior, listed from v's side
-        bool ok = walk_block<BLOCK>(p, bs, bmb, sb.sigma, sb.d, g, z, v, 5, j, [&](int32_t i, int32_t vtx) {
+        bool ok = walk_block<BLOCK>(p, bs, R, 1, g, z, v, 5, j, [&](int32_t i, int32_t vtx) {
             if (i < kb) put(kb - 1 - i, vtx);
         });
         if (tid == 0 && zc) put(nb, z);
         if (ok)
-            ok = walk_block<BLOCK>(p, bs, bma, sa.sigma, sa.d, g, z, u, 3, j, [&](int32_t i, int32_t vtx) {
+            ok = walk_block<BLOCK>(p, bs, R, 0, g, z, u, 3, j, [&](int32_t i, int32_t vtx) {
                 if (i < ha) put(nb + zc + i - 1, vtx);
             });
         if (!ok && tid == 0) atomicOr(&p.st->err, kErrInternal);
@@ -843,14 +884,15 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
     __syncthreads();
     sub_mark<BLOCK>(sm, kSbPairWalk);
 
-    // ---- clear what this sample touched
+    // ---- reset the records of every listed vertex (both sides)
     for (int k = 0; k < 2; ++k) {
         const Scr &x = k == 0 ? sa : sb;
-        uint32_t *bm = k == 0 ? bma : bmb;
         for (int32_t i = tid; i < bs.hi[k]; i += BLOCK) {
-            const int32_t w = x.lv[i];
-            x.sigma[w] = 0ULL;
-            bm[w >> 5] = 0u;
+            PairRec &rc = R[x.lv[i]];
+            rc.sig[0] = 0ULL;
+            rc.sig[1] = 0ULL;
+            rc.d[0] = -1;
+            rc.d[1] = -1;
         }
     }
     __syncthreads();
@@ -871,28 +913,28 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     __syncthreads();
 
     const long long slot = blockIdx.x;
+    const long long off = slot * p.stride;
     Scr s;
-    s.sigma = p.sigma + slot * p.stride;
-    s.dacc = p.dacc + slot * p.stride;
-    s.ldeg = p.ldeg + slot * p.stride;
-    s.d = p.d + slot * p.stride;
-    s.lv = p.lv + slot * p.stride;
-    s.la = p.la + slot * p.stride;
-    s.ld = p.ld + slot * p.stride;
-    s.lvl = p.lvl + slot * p.stride;
-    s.cand = p.cand + slot * p.stride;
-    uint32_t *bm = BMLDS ? lds_bm : p.bmg + slot * p.bm_words;
-    // pair mode: the target's side of the bidirectional search
+    // pair mode keeps its path counts and distances in records instead
+    s.sigma = MODE == kModePair ? nullptr : p.sigma + off;
+    s.dacc = p.dacc + off;
+    s.ldeg = MODE == kModePair ? nullptr : p.ldeg + off;
+    s.d = MODE == kModePair ? nullptr : p.d + off;
+    s.lv = p.lv + off;
+    s.la = p.la + off;
+    s.ld = p.ld + off;
+    s.lvl = MODE == kModePair ? nullptr : p.lvl + off;
+    s.cand = p.cand + off;
+    uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
+    // pair mode: per-vertex records of both search sides, and the target
+    // side's level lists
     Scr s2 = s;
-    uint32_t *bm2 = nullptr;
+    PairRec *rec = nullptr;
     if (MODE == kModePair) {
-        s2.sigma = p.sigma2 + slot * p.stride;
-        s2.d = p.d2 + slot * p.stride;
+        rec = reinterpret_cast<PairRec *>(p.pair_rec) + slot * p.stride;
         s2.lv = p.lv2 + slot * p.stride;
         s2.la = p.la2 + slot * p.stride;
         s2.ld = p.ld2 + slot * p.stride;
-        s2.lvl = p.lvl2 + slot * p.stride;
-        bm2 = p.bmg2 + slot * p.bm_words;
     }
 
     Counters c = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -959,7 +1001,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 continue;
             }
             phase_start<BLOCK>(sm);
-            bidir_sample<BLOCK>(p, sm, bs, s, s2, bm, bm2, g, src, target, j, task, c);
+            bidir_sample<BLOCK>(p, sm, bs, rec, s, s2, g, src, target, j, task, c);
             if (tid == 0) c.tasks++;
             phase_end<BLOCK>(sm, kPhTd);
             continue;
@@ -1160,6 +1202,18 @@ __global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long 
     if (lane_id() == 0) atomicMax(key, best);
 }
 
+__global__ void k_pair_rec_init(PairRec *rec, long long count) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        rec[i].sig[0] = 0ULL;
+        rec[i].sig[1] = 0ULL;
+        rec[i].d[0] = -1;
+        rec[i].d[1] = -1;
+        rec[i].pad[0] = 0;
+        rec[i].pad[1] = 0;
+    }
+}
+
 __global__ void k_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k,
                                double *out) {
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -1175,6 +1229,12 @@ static inline unsigned grid_for(long long count, int block) {
     if (g < 1) g = 1;
     if (g > 65536) g = 65536;
     return (unsigned)g;
+}
+
+hipError_t launch_pair_rec_init(void *rec, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_rec_init, dim3(grid_for(count, 256)), dim3(256), 0, s, reinterpret_cast<PairRec *>(rec),
+                       count);
+    return hipGetLastError();
 }
 
 hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,

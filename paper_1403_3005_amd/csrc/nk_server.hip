@@ -106,18 +106,17 @@ static size_t request_footprint(const ServerGraph &g, long long k, int grid, boo
     const long long stride = (((long long)g.n + 2) + 63) / 64 * 64;
     const long long cells = (long long)grid * stride;
     size_t b = 0;
-    b += round256(cells * 8) * 2;       // sigma, dacc
-    b += round256(cells * 4) * 7;       // ldeg, d, lv, la, ld, lvl, cand
+    b += round256(cells * 8);           // weights / push accumulator
+    b += round256(cells * 4) * 4;       // lv, la, ld, cand
     b += round256((size_t)g.n * 8);     // accumulator / counts
     b += round256((size_t)std::max<long long>(k, 1) * 4) * 2;
     b += round256(sizeof(DevStatus));
     if (pair) {
-        // second side of the bidirectional search and both visited bitmaps
-        const long long words = (((long long)g.n + 31) / 32 + 63) / 64 * 64;
-        b += round256(cells * 8);           // sigma2
-        b += round256(cells * 4) * 5;       // d2, lv2, la2, ld2, lvl2
-        b += round256((long long)grid * words * 4) * 2;
+        b += round256(cells * 32);          // records of both search sides
+        b += round256(cells * 4) * 3;       // the target side's lists
     } else {
+        b += round256(cells * 8);           // sigma
+        b += round256(cells * 4) * 4;       // ldeg, d, lvl, candidates' spare
         b += round256((size_t)((g.n + 31) / 32) * 4);   // isolated-vertex bitmap
     }
     return b;

@@ -174,7 +174,8 @@ def test_launch_variants(block, bu_ratio, flags, bw_ratio):
 def test_scratch_cap_shrinks_the_grid():
     """A scratch cap of 8 MiB leaves room for 11 slots of a 16k-vertex graph
     (44 bytes per vertex per slot); results stay exact.  A cap below one
-    slot is NK_E_NO_MEMORY.  Pair sampling honours the cap too."""
+    slot is NK_E_NO_MEMORY.  Pair sampling (68 bytes per vertex per slot)
+    honours the cap too."""
     g = gg.rmat(14, 16, 44)
     rp, ci = upload(g)
     src = gg.sample_sources(g.n, 100, 45)
@@ -184,7 +185,7 @@ def test_scratch_cap_shrinks_the_grid():
     assert nk.nk_last_stats()["workgroups"] == (8 << 20) // (stride * 44)
     assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src), "capped")
     cnt = nk.nk_pair_counts(rp, ci, 300, 46).cpu().numpy().view(np.uint32)
-    assert nk.nk_last_stats()["workgroups"] <= (8 << 20) // (stride * 72)
+    assert nk.nk_last_stats()["workgroups"] <= (8 << 20) // (stride * 68)
     assert np.array_equal(cnt, oracle.pair_counts(g.rowptr, g.colidx, 300, 46))
     nk.nk_set_tuning(flags=4, scratch_mib=0)
     big = gg.rmat(15, 16, 47)
