@@ -166,6 +166,27 @@ __device__ __forceinline__ void wave_append(bool pred, int32_t value, int32_t *o
     }
 }
 
+// As wave_append, and returns the lane's position in `out` (or -1 when
+// pred is false or the position is past cap).
+__device__ __forceinline__ int32_t wave_append_pos(bool pred, int32_t value, int32_t *out, int32_t *counter,
+                                                   int32_t cap, int32_t *err) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ULL) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int32_t)__popcll(mask));
+    base = __shfl(base, leader, kWave);
+    if (!pred) return -1;
+    const int32_t pos = base + (int32_t)__popcll(mask & ((1ULL << lane) - 1ULL));
+    if (pos < cap) {
+        out[pos] = value;
+        return pos;
+    }
+    atomicOr(err, kErrInternal);
+    return -1;
+}
+
 // Largest k in [0, cnt) with pre[k] <= i (pre[0] = 0 <= i).
 __device__ __forceinline__ int32_t tile_search(const int32_t *pre, int32_t cnt, int32_t i) {
     int32_t lo = 0, hi = cnt - 1;

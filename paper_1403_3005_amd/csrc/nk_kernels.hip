@@ -586,11 +586,15 @@ struct PairRec {
 
 // Top-down growth of side X by one level (list[f0, f1) at distance dep)
 // into list[f1, ...): every arc y -> z with z not reached by X before this
-// level adds sigma_X(y) to sigma_X(z); the first adder appends z.
+// level adds sigma_X(y) to sigma_X(z).  The first adder appends z with its
+// first arc and degree, adds the degree to *newcost, and, when the other
+// side has reached z, appends z to the meeting list (meet, *nm).
 template <int BLOCK>
 __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, const Scr &s, const GView &g,
-                           int32_t f0, int32_t f1, int32_t dep, Counters &c) {
+                           int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
+                           unsigned long long *newcost, Counters &c) {
     const int tid = threadIdx.x;
+    unsigned long long dsum = 0;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
         if (tid < cnt) sm.val.u[tid] = R[s.lv[tb + tid]].sig[X];
@@ -613,16 +617,33 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, 
             for (int j = 0; j < kChunk; ++j) old[j] = act[j] ? atomicAdd(&R[w[j]].sig[X], add[j]) : 1ULL;
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
+                const bool fresh = act[j] && old[j] == 0ULL;
+                int32_t a0 = 0, dg = 0;
+                bool met = false;
                 if (act[j]) {
                     c.dag++;
                     if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
-                    if (old[j] == 0ULL) R[w[j]].d[X] = dep + 1;
                 }
-                wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
+                if (fresh) {
+                    R[w[j]].d[X] = dep + 1;
+                    a0 = g.rp[w[j]];
+                    dg = g.rp[w[j] + 1] - a0;
+                    met = R[w[j]].d[1 - X] >= 0;
+                    dsum += (unsigned long long)dg;
+                }
+                const int32_t pos = wave_append_pos(fresh, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
+                if (pos >= 0) {
+                    s.la[f1 + pos] = a0;
+                    s.ld[f1 + pos] = dg;
+                }
+                // meeting vertices: new on side X and already reached by the other side
+                wave_append(met, w[j], meet, nm, g.n, &p.st->err);
             }
         }
         __syncthreads();
     }
+    dsum = wave_sum<unsigned long long>(dsum);
+    if (lane_id() == 0 && dsum) atomicAdd(newcost, dsum);
 }
 
 // Walk from `from` to the root `rootv` of search side X, all threads of
@@ -743,29 +764,10 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
             c.td++;
         }
         __syncthreads();
-        pair_level<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, c);
+        pair_level<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm,
+                          reinterpret_cast<unsigned long long *>(&bs.newcost), c);
         __syncthreads();
         const int32_t nnew = sm.count < g.n - hi ? sm.count : g.n - hi;
-        long long dsum = 0;
-        for (int32_t i0 = hi; i0 < hi + nnew; i0 += BLOCK) {
-            const int32_t i = i0 + tid;
-            const bool in = i < hi + nnew;
-            int32_t w = 0;
-            bool meet = false;
-            if (in) {
-                w = sx.lv[i];
-                const int32_t a0 = g.rp[w], dg = g.rp[w + 1] - a0;
-                sx.la[i] = a0;
-                sx.ld[i] = dg;
-                dsum += dg;
-                meet = R[w].d[1 - X] >= 0;
-            }
-            // meeting vertices: new on side X and already reached by the other side
-            wave_append(meet, w, sa.cand, &bs.nm, g.n, &p.st->err);
-        }
-        dsum = wave_sum<long long>(dsum);
-        if (lane_id() == 0 && dsum) atomicAdd((unsigned long long *)&bs.newcost, (unsigned long long)dsum);
-        __syncthreads();
         if (tid == 0) {
             bs.lo[X] = hi;
             bs.hi[X] = hi + nnew;
