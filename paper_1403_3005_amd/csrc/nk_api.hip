@@ -73,6 +73,7 @@ struct PoolBlock {
     size_t bytes;
     int device;
     bool busy;
+    int tag;    // meaning of the contents kept across calls (0 = none)
 };
 static std::mutex g_pool_mu;
 static std::vector<PoolBlock> g_pool;
@@ -91,6 +92,7 @@ nk_status Scratch::get(size_t bytes, void **out) {
         }
         if (best >= 0) {
             g_pool[best].busy = true;
+            g_pool[best].tag = 0;
             held_.push_back(g_pool[best].ptr);
             *out = g_pool[best].ptr;
             return NK_OK;
@@ -122,11 +124,52 @@ nk_status Scratch::get(size_t bytes, void **out) {
     }
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
-        g_pool.push_back(PoolBlock{p, bytes, dev, true});
+        g_pool.push_back(PoolBlock{p, bytes, dev, true, 0});
     }
     held_.push_back(p);
     *out = p;
     return NK_OK;
+}
+
+nk_status Scratch::get_tagged(size_t bytes, int tag, void **out, bool *clean, size_t *block_bytes) {
+    int dev = 0;
+    NK_HIP(hipGetDevice(&dev));
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    *clean = false;
+    *block_bytes = need;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        int best = -1;
+        for (size_t i = 0; i < g_pool.size(); ++i) {
+            const PoolBlock &b = g_pool[i];
+            if (b.busy || b.device != dev || b.tag != tag || b.bytes < need || b.bytes > 2 * need + (64u << 20))
+                continue;
+            if (best < 0 || b.bytes < g_pool[best].bytes) best = (int)i;
+        }
+        if (best >= 0) {
+            g_pool[best].busy = true;
+            g_pool[best].tag = 0;   // dirty until marked again
+            held_.push_back(g_pool[best].ptr);
+            *out = g_pool[best].ptr;
+            *clean = true;
+            *block_bytes = g_pool[best].bytes;
+            return NK_OK;
+        }
+    }
+    nk_status st = get(bytes, out);
+    if (st != NK_OK) return st;
+    // a reused untagged block may be larger than asked for; the caller
+    // prepares all of it, so that a later mark() covers the whole block
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (const auto &b : g_pool)
+        if (b.ptr == *out) *block_bytes = b.bytes;
+    return NK_OK;
+}
+
+void Scratch::mark(void *p, int tag) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto &b : g_pool)
+        if (b.ptr == p) b.tag = tag;
 }
 
 void Scratch::release_all() {
@@ -326,6 +369,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     plan->stride = (((long long)n_max + 2) + 63) / 64 * 64;
     plan->bm_words = (words + 63) / 64 * 64;
     plan->kernel = kr;
+    plan->pair_rec = nullptr;
     return NK_OK;
 }
 
@@ -384,12 +428,17 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     if ((st = scr.get(cells, &p.ld)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.cand)) != NK_OK) return st;
     if (pair) {
-        // 32-byte records of both search sides, the target side's lists
-        if ((st = scr.get((size_t)cells * 32, &p.pair_rec)) != NK_OK) return st;
+        // 32-byte records of both search sides (every sample resets the
+        // records it touched, so a block left by a successful pair launch is
+        // still all-unreached and needs no fill), the target side's lists
+        bool clean = false;
+        size_t rec_bytes = 0;
+        if ((st = scr.get_tagged((size_t)cells * 32, kTagPairRecords, &p.pair_rec, &clean, &rec_bytes)) != NK_OK)
+            return st;
         if ((st = scr.get(cells, &p.lv2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.la2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ld2)) != NK_OK) return st;
-        NK_HIP(launch_pair_rec_init(p.pair_rec, cells, s));
+        if (!clean) NK_HIP(launch_pair_rec_init(p.pair_rec, (long long)(rec_bytes / 32), s));
     } else {
         if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
@@ -886,6 +935,7 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     p.st = dst;
     if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
     if (counts && g.perm) NK_HIP(launch_gather_u32(cnt, g.perm, n, counts, s));
+    plan.pair_rec = p.pair_rec;
     *plan_out = plan;
     return NK_OK;
 }
@@ -916,6 +966,7 @@ nk_status nk_pair_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n
                            ev0, ev1)) != NK_OK)
             return st;
         st = finish(dst, h, s);
+        if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     } else {
         st = finish(dst, h, s);
@@ -966,6 +1017,7 @@ nk_status nk_bc_pair_sample(const int32_t *rowptr, const int32_t *colidx, int32_
     const double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
     NK_HIP(launch_counts_to_bc(cnt, bc, scale, n, s));
     st = finish(dst, h, s);
+    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
     if (r > 0) NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     stats_record(*h, plan.grid, plan.block, plan.lds, ms);
     return st;
@@ -995,6 +1047,7 @@ nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t 
                        dst, scr, s, &plan, nullptr, nullptr)) != NK_OK)
         return st;
     st = finish(dst, h, s);
+    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
     stats_record(*h, plan.grid, plan.block, plan.lds, 0.0f);
     return st;
 }

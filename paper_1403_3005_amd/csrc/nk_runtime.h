@@ -32,6 +32,9 @@ nk_status dev_info(DevInfo *out);
 
 // Pooled device scratch.  Blocks return to the pool when the holder is
 // destroyed; the pool keeps them for later calls until nk_shutdown.
+// Scratch block tags (contents that stay meaningful across calls).
+constexpr int kTagPairRecords = 1;   // pair-mode records, all unreached
+
 class Scratch {
 public:
     Scratch() = default;
@@ -45,6 +48,14 @@ public:
         return get((size_t)(count > 0 ? count : 1) * sizeof(T), (void **)out);
     }
     void release_all();
+    // A block that keeps a meaning across calls: `tag` != 0 asks for a free
+    // block last marked with that tag (*clean = true if one was found; its
+    // contents are as the marking call left them).  *block_bytes is the
+    // whole block's size, which may exceed `bytes`: a caller that marks the
+    // block must have prepared all of it.  Any block handed out loses its
+    // tag until mark() sets it again.
+    nk_status get_tagged(size_t bytes, int tag, void **out, bool *clean, size_t *block_bytes);
+    void mark(void *p, int tag);
 
 private:
     std::vector<void *> held_;
@@ -71,6 +82,7 @@ struct LaunchPlan {
     long long stride;
     long long bm_words;
     KernelRef kernel;
+    void *pair_rec;   // pair mode: the record block the launch used (set by the caller after the launch)
 };
 
 // Picks block size, bitmap placement and grid for graphs of at most n_max

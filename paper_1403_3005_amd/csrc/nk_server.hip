@@ -68,7 +68,7 @@ struct Slot {
     double *staging = nullptr;  // pinned host, n_max doubles
     size_t staging_n = 0;
     Scratch *scr = nullptr;
-    LaunchPlan plan;
+    LaunchPlan plan = {};
 };
 
 }  // namespace nk
@@ -206,6 +206,7 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
             p.iso = g.iso;
             p.st = sl.dst;
             if ((st = launch_persistent(sl.plan, p, scr, s, nullptr, nullptr)) != NK_OK) return bail(st);
+            sl.plan.pair_rec = p.pair_rec;
         }
         (void)launch_gather_u32(cnt, g.perm, n, cnt_orig, s);
         const double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
@@ -227,6 +228,9 @@ static void finish_request(nk_server *sv, Slot &sl) {
         else if (err & kErrInternal) rq->status = NK_E_INTERNAL;
     }
     if (rq->status == NK_OK && rq->out) memcpy(rq->out, sl.staging, sizeof(double) * g.n);
+    // a successful pair launch leaves its records all unreached
+    if (rq->status == NK_OK && sl.plan.pair_rec) sl.scr->mark(sl.plan.pair_rec, kTagPairRecords);
+    sl.plan.pair_rec = nullptr;
     rq->t_done = now_s();
     delete sl.scr;
     sl.scr = nullptr;

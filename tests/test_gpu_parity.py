@@ -358,6 +358,23 @@ def test_pair_counts_bit_exact(make, r, seed):
     assert np.array_equal(got, ref)
 
 
+def test_pair_record_block_reused_across_sizes():
+    """Pair launches reuse the previous launch's record block without a
+    fill when it is left all unreached.  Betweenness calls in between leave
+    dirty pool blocks of other sizes behind; every pair result, on graphs
+    growing and shrinking, stays bit-exact."""
+    nk.nk_shutdown()
+    graphs = [gg.rmat(10, 8, 91), gg.rmat(12, 8, 92), gg.rmat(13, 8, 93), gg.rmat(11, 8, 94), gg.rmat(13, 16, 95)]
+    big = gg.rmat(14, 16, 96)
+    brp, bci = upload(big)
+    for i, g in enumerate(graphs):
+        nk.nk_bc_sources(brp, bci, ivec(gg.sample_sources(big.n, 300 + 100 * i, 97)), 1.0)
+        rp, ci = upload(g)
+        for seed in (98, 99):
+            got = nk.nk_pair_counts(rp, ci, 700, seed + i).cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, oracle.pair_counts(g.rowptr, g.colidx, 700, seed + i)), (g.name, seed)
+
+
 def test_sample_paths_bit_exact():
     g = gg.barabasi_albert(3000, 2, 91)
     rp, ci = upload(g)
