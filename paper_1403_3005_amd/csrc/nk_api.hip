@@ -472,16 +472,12 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     Scratch scr;
     DevStatus *dst;
     unsigned long long *key;
-    int32_t *d, *f0, *f1, *f2, *label, *size, *flag;
-    long long *cnt;
+    int32_t *label, *size, *flag;
+    BfsWork w;
     nk_status st;
     if ((st = scr.get(1, &dst)) != NK_OK) return st;
     if ((st = scr.get(1, &key)) != NK_OK) return st;
-    if ((st = scr.get(n, &d)) != NK_OK) return st;
-    if ((st = scr.get(n, &f0)) != NK_OK) return st;
-    if ((st = scr.get(n, &f1)) != NK_OK) return st;
-    if ((st = scr.get(n, &f2)) != NK_OK) return st;
-    if ((st = scr.get(4, &cnt)) != NK_OK) return st;
+    if ((st = bfs_work_get(scr, n, s, &w)) != NK_OK) return st;
     if ((st = scr.get(n, &label)) != NK_OK) return st;
     if ((st = scr.get(n, &size)) != NK_OK) return st;
     if ((st = scr.get(2, &flag)) != NK_OK) return st;
@@ -498,14 +494,14 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     const int32_t x0 = (int32_t)(0xffffffffULL - (k & 0xffffffffULL));
     // first sweep from x0: e1, the lowest far vertex a, and |C(x0)|
     int32_t r1[3], r2[3];
-    if ((st = grid_bfs(rowptr, colidx, n, m, x0, d, f0, f1, f2, cnt, s, r1)) != NK_OK) return st;
+    if ((st = grid_bfs(rowptr, colidx, n, m, x0, w, s, r1)) != NK_OK) return st;
     const int32_t e1 = r1[0], a = r1[1], c0 = r1[2];
     // largest component among the vertices the first sweep did not reach
     int32_t c2 = 0;
     if (c0 < n)
-        if ((st = largest_unreached_component(rowptr, colidx, n, d, label, size, flag, s, &c2)) != NK_OK) return st;
+        if ((st = largest_unreached_component(rowptr, colidx, n, w.d, label, size, flag, s, &c2)) != NK_OK) return st;
     // second sweep from a
-    if ((st = grid_bfs(rowptr, colidx, n, m, a, d, f0, f1, f2, cnt, s, r2)) != NK_OK) return st;
+    if ((st = grid_bfs(rowptr, colidx, n, m, a, w, s, r2)) != NK_OK) return st;
     const int32_t e2 = r2[0];
     int32_t ub = 2 * e1 + 1;
     if (ub > c0) ub = c0;

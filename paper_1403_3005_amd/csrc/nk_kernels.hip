@@ -1201,7 +1201,14 @@ __global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long 
         const unsigned long long y = __shfl_xor(best, off, kWave);
         best = y > best ? y : best;
     }
-    if (lane_id() == 0) atomicMax(key, best);
+    // one global atomic per workgroup (same-address atomics serialise)
+    __shared__ unsigned long long part[1024 / kWave];
+    if (lane_id() == 0) part[wave_id()] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) best = part[w] > best ? part[w] : best;
+        atomicMax(key, best);
+    }
 }
 
 __global__ void k_pair_rec_init(PairRec *rec, long long count) {
@@ -1288,7 +1295,8 @@ hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale,
     return hipGetLastError();
 }
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s) {
-    hipLaunchKernelGGL(k_argmax_degree, dim3(grid_for(n, 256)), dim3(256), 0, s, rowptr, n, key);
+    const unsigned g = grid_for(n, 256);
+    hipLaunchKernelGGL(k_argmax_degree, dim3(g < 1024 ? g : 1024), dim3(256), 0, s, rowptr, n, key);
     return hipGetLastError();
 }
 

@@ -89,13 +89,21 @@ struct LaunchPlan {
 // vertices and `ntasks` tasks.  max_slots > 0 caps the grid.
 nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan);
 
-// Grid-wide direction-optimising breadth-first search from src
-// (nk_bfs.hip): d[n] receives the distances (-1 unreached); f0, f1, f2 are
-// buffers of n entries (frontiers, deferred vertices) and cnt four 8-byte
-// words of device scratch.  out = {eccentricity of src, lowest id at that
-// distance, vertices reached}.  Synchronises s.
-nk_status grid_bfs(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t src, int32_t *d,
-                   int32_t *f0, int32_t *f1, int32_t *f2, long long *cnt, hipStream_t s, int32_t out[3]);
+// Grid-wide direction-optimising breadth-first search (nk_bfs.hip).
+struct BfsWork {
+    int32_t *d;        // n distances from the source (-1 unreached)
+    int32_t *f0, *f1;  // frontier lists, n entries each
+    int32_t *f2;       // n + 1: deferred vertices, or a frontier's degrees
+    int32_t *off;      // n + 1 arc offsets of a top-down frontier
+    long long *cnt;    // 9 words: two level counter sets and one spare
+    void *tmp;         // prefix-sum temporary storage
+    size_t tmp_bytes;
+};
+nk_status bfs_work_get(Scratch &scr, int32_t n, hipStream_t s, BfsWork *w);
+// Distances from src into w.d; out = {eccentricity of src, lowest id at
+// that distance, vertices reached}.  Synchronises s.
+nk_status grid_bfs(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t src,
+                   const BfsWork &w, hipStream_t s, int32_t out[3]);
 // Size of the largest connected component among the vertices with
 // skip[v] < 0 (label, size: n ints of scratch; flag: one int).
 nk_status largest_unreached_component(const int32_t *rowptr, const int32_t *colidx, int32_t n, const int32_t *skip,

@@ -324,6 +324,27 @@ def test_vd_bound_matches_oracle(make):
     assert nk.nk_vd_bound(rp, ci) == oracle.vd_bound(g.rowptr, g.colidx)
 
 
+def _broom_graph():
+    """A hub with 12,000 leaves, every 40th leaf tied into a sparse random
+    graph of 50,000 vertices and 150,000 edges: the sweep from the hub takes
+    top-down levels whose arcs span several tiles of 2048, the first one all
+    from a single vertex."""
+    er = gg.erdos_renyi(50000, 150000, 74)
+    a, b = er.edges()
+    leaves = np.arange(1, 12001)
+    u = np.concatenate([np.zeros(12000, dtype=np.int64), leaves[::40], a + 12001])
+    v = np.concatenate([leaves, 12001 + (leaves[::40] * 7919) % 50000, b + 12001])
+    return gg.from_edges(62001, u, v, "broom")
+
+
+def test_vd_bound_balanced_top_down():
+    g = _broom_graph()
+    rp, ci = upload(g)
+    info = nk.nk_vd_bound(rp, ci)
+    assert info == oracle.vd_bound(g.rowptr, g.colidx)
+    assert info["x0"] == 0
+
+
 def _deferred_bottom_up_graph():
     """A graph whose breadth-first sweep from the hub takes a bottom-up
     step in which an unreached vertex of degree 301 finds its only frontier
