@@ -313,9 +313,9 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     int block = t.block;
     if (block != 256 && block != 512 && block != 1024) {
         block = auto_block(n_max);
-        // a pair sample's search levels are small; 512 threads keep its
-        // kernel free of register spills
-        if (mode == kModePair && block > 512) block = 512;
+        // a pair sample's search levels are small: more concurrent samples
+        // of 256 threads hide more memory latency than fewer wide ones
+        if (mode == kModePair) block = 256;
     }
     const long long words = ((long long)n_max + 31) / 32;
     const size_t bm_bytes = (size_t)words * 4;
@@ -354,12 +354,18 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
             size_t fr = 0, tot = 0;
             NK_HIP(hipMemGetInfo(&fr, &tot));
             avail = (size_t)((double)(fr + pool_bytes_idle()) * 0.85);
+            // pair samples touch their slots' records at random: beyond
+            // about half the device's memory, more slots add address-
+            // translation misses faster than they hide latency
+            if (mode == kModePair && avail > tot / 2) avail = tot / 2;
         }
         const long long fit = (long long)(avail / per_slot);
         if (fit < 1)
             return fail(NK_E_NO_MEMORY, "one workgroup slot needs %zu bytes of scratch; %zu available", per_slot,
                         avail);
-        if (grid > fit) grid = fit;
+        // a memory-capped grid keeps the same number of workgroups on
+        // every compute unit
+        if (grid > fit) grid = fit > di.cus ? fit / di.cus * di.cus : fit;
     }
     plan->mode = mode;
     plan->block = block;
