@@ -56,13 +56,15 @@ def counter_traffic(workload: str):
 
 def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = "plain"):
     """The oracle (plain Brandes, the paper's per-thread-array parallel
-    pattern; or its linear-scaling / edge form) on a bounded prefix of the
-    same source list."""
+    pattern; or its linear-scaling / bisection / edge form) on a bounded
+    prefix of the same source list."""
     import oracle
 
     def run(sources, threads):
         if kind == "linear":
             oracle.bc_sources_linear(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
+        elif kind == "bisect":
+            oracle.bc_sources_bisect(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         elif kind == "edge":
             oracle.edge_bc(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         else:
@@ -112,7 +114,7 @@ def other_workload(args) -> dict:
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     rec = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
-    if args.workload in ("rmat20_linear", "rmat20_edge"):
+    if args.workload in ("rmat20_linear", "rmat20_bisect", "rmat20_edge"):
         print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
         g, src = gg.workload_rmat20(2)
         rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
@@ -122,6 +124,10 @@ def other_workload(args) -> dict:
             scale = 2.0 * g.n / k
             sec = _timed(lambda: nk.nk_bc_sources_linear(rp, ci, sv, scale, bc=bc), args.steps, args.warmup)
             metric = "GTEPS, linear-scaling (Geisberger-Sanders-Schultes) source-sampled betweenness"
+        elif args.workload == "rmat20_bisect":
+            scale = 2.0 * g.n / k
+            sec = _timed(lambda: nk.nk_bc_sources_bisect(rp, ci, sv, scale, bc=bc), args.steps, args.warmup)
+            metric = "GTEPS, bisection (Geisberger-Sanders-Schultes) source-sampled betweenness"
         else:
             scale = g.n / k
             sec = _timed(lambda: nk.nk_edge_bc(rp, ci, sv, scale), args.steps, args.warmup)
@@ -136,7 +142,8 @@ def other_workload(args) -> dict:
         if not args.no_cpu_baseline:
             print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
             rec["cpu_baseline"] = cpu_baseline(g, src, g.m_undirected,
-                                               kind="linear" if args.workload == "rmat20_linear" else "edge")
+                                               kind={"rmat20_linear": "linear", "rmat20_bisect": "bisect"}.get(
+                                                   args.workload, "edge"))
     elif args.workload == "rmat20_closeness":
         print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
         g, src = gg.workload_rmat20(2)
@@ -372,7 +379,7 @@ def main():
                     help="requests of the default serving line; measured requests per point of --workload serving")
     ap.add_argument("--serving-warm", type=int, default=50, help="warm-up requests per point of --workload serving")
     ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear",
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect",
                              "rmat20_edge", "rmat20_closeness", "er200k", "serving"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()

@@ -128,6 +128,21 @@ nk_status nk_bc_sources_linear(const int32_t *rowptr, const int32_t *colidx, int
                                const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
 
 /*
+ * Bisection estimator of the same paper by Geisberger, Sanders and
+ * Schultes: a pair (s, t) with s in the source list counts
+ * sigma_st(v) / sigma_st for the vertices v on the far half of its
+ * shortest paths (2 d(s, v) > d(s, t)), half of it for a vertex exactly in
+ * the middle, nothing on the near half.  As for linear scaling the weights
+ * of a path seen from its two ends add to 1: over every vertex as a source
+ * this is half of exact betweenness, and scale = 2 n / k estimates the
+ * exact scores.  A source whose search reaches depth L does about
+ * 1 + L/4 times the dependency-sweep work of nk_bc_sources.
+ *   sources, bc, errors as for nk_bc_sources_linear.
+ */
+nk_status nk_bc_sources_bisect(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
+
+/*
  * Edge betweenness (section "Edge Centrality, Sparsification and Link
  * Prediction"): for the undirected edge {u, v}, the sum over ordered pairs
  * (s, t), s in the source list, of the share of shortest s-t paths that

@@ -60,6 +60,7 @@ def _load():
         "or_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_bc_exact": (c.c_int, g + [f64p, c.c_int32]),
         "or_bc_sources_linear": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
+        "or_bc_sources_bisect": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_edge_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, f64p, c.c_int32]),
         "or_closeness": (c.c_int, g + [f64p]),
         "or_closeness_approx": (c.c_int, g + [i32p, c.c_int32, f64p, i64p]),
@@ -158,6 +159,21 @@ def bc_sources_linear(rowptr, colidx, sources, scale: float = 1.0, nthreads: int
     _check(_load().or_bc_sources_linear(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
                                         _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double),
                                         nthreads), "bc_sources_linear")
+    return bc[:n]
+
+
+def bc_sources_bisect(rowptr, colidx, sources, scale: float = 1.0, nthreads: int = 1) -> np.ndarray:
+    """Bisection (Geisberger-Sanders-Schultes) dependencies summed over
+    `sources`, times `scale` (2 n / k gives the estimate of exact scores)."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    bc = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_bc_sources_bisect(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                        _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double),
+                                        nthreads), "bc_sources_bisect")
     return bc[:n]
 
 

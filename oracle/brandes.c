@@ -12,8 +12,9 @@
  *   - exact: sum of dependencies over all sources (Table 1, "betweenness");
  *   - source set: sum over a given source list times a scale factor
  *     (Table 1, "ap. betweenness", sampling shortest-path trees);
- *   - the linear-scaling source-set estimator of Geisberger, Sanders and
- *     Schultes (the reference cited for that sampling);
+ *   - the linear-scaling and bisection source-set estimators of
+ *     Geisberger, Sanders and Schultes (the reference cited for that
+ *     sampling);
  *   - edge betweenness (section "Edge Centrality, Sparsification and Link
  *     Prediction");
  *   - closeness, exact and sampled (Table 1, "closeness", "ap. closeness");
@@ -204,6 +205,51 @@ static int one_source_linear(const graph_t *g, int32_t s, work_t *w, double *bc)
 }
 
 /*
+ * One source of the bisection estimator of the same Geisberger, Sanders and
+ * Schultes paper: the pair (s, t) adds sigma_st(v) / sigma_st to v when v
+ * lies on the far half of its shortest paths (2 d(s,v) > d(s,t)), half of
+ * that when v is exactly in the middle (2 d(s,v) = d(s,t)), and nothing on
+ * the near half.  Let D_T(v) be Brandes' dependency of v counting only the
+ * targets at depth <= T.  Then v at depth l receives
+ *     (D_{2l-1}(v) + D_{2l}(v)) / 2,
+ * where D_T = D_L for T >= L, the depth of the deepest vertex.  Each D_T is
+ * the plain accumulation in reverse visit order over the vertices at depth
+ * <= T; every T = 1..L is computed over the whole tree and added to the
+ * vertices whose depths select it.
+ */
+static int one_source_bisect(const graph_t *g, int32_t s, work_t *w, double *bc) {
+    int32_t nS = 0;
+    int status = forward(g, s, w->d, w->sigma, w->S, &nS, w->queue);
+    if (status == OR_OK && nS > 1) {
+        const int32_t L = w->d[w->S[nS - 1]];
+        for (int32_t T = 1; T <= L; ++T) {
+            for (int32_t i = 0; i < nS; ++i) w->delta[w->S[i]] = 0.0;
+            for (int32_t i = nS - 1; i >= 0; --i) {
+                int32_t x = w->S[i];
+                if (w->d[x] > T) continue;
+                for (int32_t e = g->rowptr[x]; e < g->rowptr[x + 1]; ++e) {
+                    int32_t v = g->colidx[e];
+                    if (w->d[v] == w->d[x] - 1)
+                        w->delta[v] += (double)w->sigma[v] / (double)w->sigma[x] * (1.0 + w->delta[x]);
+                }
+            }
+            for (int32_t i = 0; i < nS; ++i) {
+                int32_t x = w->S[i];
+                if (x == s) continue;
+                const int32_t l = w->d[x];
+                const int32_t t1 = 2 * l - 1 < L ? 2 * l - 1 : L, t2 = 2 * l < L ? 2 * l : L;
+                double wt = 0.0;
+                if (T == t1) wt += 0.5;
+                if (T == t2) wt += 0.5;
+                if (wt != 0.0) bc[x] += wt * w->delta[x];
+            }
+        }
+    }
+    work_reset(w, nS);
+    return status;
+}
+
+/*
  * One source of Brandes' algorithm with edge dependencies (edge
  * betweenness, named in the section "Edge Centrality, Sparsification and
  * Link Prediction"): the shortest-path DAG arc v -> w carries
@@ -251,7 +297,7 @@ int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     return st;
 }
 
-enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2 };
+enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2, KIND_BISECT = 3 };
 
 typedef struct {
     const graph_t *g;
@@ -272,6 +318,8 @@ static void *run_job(void *arg) {
             int st;
             if (j->kind == KIND_LINEAR)
                 st = one_source_linear(j->g, j->src[i], &w, j->bc);
+            else if (j->kind == KIND_BISECT)
+                st = one_source_bisect(j->g, j->src[i], &w, j->bc);
             else if (j->kind == KIND_EDGE)
                 st = one_source_edge(j->g, j->src[i], &w, j->bc, j->ebc);
             else
@@ -380,6 +428,25 @@ int or_bc_sources_linear(int32_t n, int64_t m, const int32_t *rowptr, const int3
     if (n > 0 && !bc) return OR_E_INVALID_ARG;
     graph_t g = {n, rowptr, colidx};
     st = run_sources(&g, m, src, k, KIND_LINEAR, bc, NULL, nthreads);
+    if (st == OR_OK && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return st;
+}
+
+/*
+ * Bisection estimator over the sources src[0..k): the sum of
+ * one_source_bisect dependencies times `scale`.  Summed over every vertex
+ * as a source it is half of exact betweenness, so the unbiased estimate
+ * from k sampled sources uses scale = 2 n / k.
+ */
+int or_bc_sources_bisect(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                         const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n > 0 && !bc) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    st = run_sources(&g, m, src, k, KIND_BISECT, bc, NULL, nthreads);
     if (st == OR_OK && scale != 1.0)
         for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
     return st;

@@ -85,6 +85,30 @@ def linear_dependencies(rowptr, colidx, sources):
     return out
 
 
+def bisection_dependencies(rowptr, colidx, sources):
+    """Sum over s in `sources` and every t != s of sigma_st(v) / sigma_st
+    weighted 1 when v is on the far half of the path (2 d(s, v) > d(s, t)),
+    1/2 in its exact middle and 0 on the near half, as exact Fractions: the
+    bisection estimator of Geisberger, Sanders and Schultes written out from
+    its definition, path by path."""
+    n = len(rowptr) - 1
+    paths = all_pairs_paths(rowptr, colidx)
+    out = [Fraction(0)] * n
+    for s in sources:
+        for t in range(n):
+            ps = paths.get((s, t))
+            if not ps:
+                continue
+            dst = len(ps[0]) - 1
+            for p in ps:
+                for pos, v in enumerate(p[1:-1], start=1):
+                    if 2 * pos > dst:
+                        out[v] += Fraction(1, len(ps))
+                    elif 2 * pos == dst:
+                        out[v] += Fraction(1, 2 * len(ps))
+    return out
+
+
 def edge_betweenness(rowptr, colidx):
     """dict {(u, v): Fraction} with u < v: over ordered pairs (s, t), the
     share of shortest s-t paths that use the edge {u, v}."""

@@ -454,7 +454,7 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
             if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
         NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
         // the push accumulator of the dependency sweep must start at zero
-        if (plan.mode == kModeBC) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
+        if (plan.mode == kModeBC || plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
     }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
@@ -588,12 +588,15 @@ static nk_status prepare_graph(const int32_t *rowptr, const int32_t *colidx, int
     return relabel_graph(rowptr, colidx, n, m, dst, scr, s, g);
 }
 
+// Estimators of the source-sampled sweep.
+enum Estimator : int { kEstPlain = 0, kEstLinear = 1, kEstBisect = 2 };
+
 // Shared body of nk_bc_exact / nk_bc_sources / nk_bc_sources_linear /
-// nk_edge_bc.  linear selects the linear-scaling estimator; ebc != NULL
-// also computes edge scores (global kernel, graph under its own ids).
+// nk_bc_sources_bisect / nk_edge_bc.  est selects the estimator; ebc !=
+// NULL also computes edge scores (global kernel, graph under its own ids).
 static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
                                  const int32_t *sources, long long k, double scale, double *bc, void *stream,
-                                 int linear = 0, double *ebc = nullptr) {
+                                 int est = kEstPlain, double *ebc = nullptr) {
     clear_error();
     stats_clear();
     nk_status st = check_graph_args(rowptr, colidx, n, m);
@@ -618,7 +621,8 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     LaunchPlan plan = {};
     float ms = 0.0f;
     int where = 0;
-    if (k > 0 && !ebc && plan_lds(lds_graph_bytes(n, m), n, k, &plan)) {
+    // (the all-in-LDS kernel has no bisection sweeps)
+    if (k > 0 && !ebc && est != kEstBisect && plan_lds(lds_graph_bytes(n, m), n, k, &plan)) {
         // the whole graph fits one workgroup's LDS: no relabelling, no scratch
         Params p;
         memset(&p, 0, sizeof(p));
@@ -630,7 +634,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.sources = sources;
         p.bc = bc;
         p.st = dst;
-        p.linear = linear;
+        p.linear = est == kEstLinear;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         NK_HIP(hipEventRecord(ev0, s));
@@ -660,7 +664,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
             if ((st = scr.get(n, &acc)) != NK_OK) return st;
             NK_HIP(launch_fill_f64(acc, 0.0, n, s));
         }
-        if ((st = plan_launch(kModeBC, n, k, 0, &plan)) != NK_OK) return st;
+        if ((st = plan_launch(est == kEstBisect ? kModeBisect : kModeBC, n, k, 0, &plan)) != NK_OK) return st;
         Params p;
         memset(&p, 0, sizeof(p));
         p.rowptr = g.rowptr;
@@ -672,7 +676,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.bc = acc;
         p.iso = iso;
         p.st = dst;
-        p.linear = linear;
+        p.linear = est == kEstLinear;
         p.ebc = ebc;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
@@ -712,7 +716,16 @@ nk_status nk_bc_sources_linear(const int32_t *rowptr, const int32_t *colidx, int
         clear_error();
         return fail(NK_E_INVALID_ARG, "sources is NULL");
     }
-    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, 1);
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, kEstLinear);
+}
+
+nk_status nk_bc_sources_bisect(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                               const int32_t *sources, int32_t k, double scale, double *bc, void *stream) {
+    if (k > 0 && !sources && k != n) {
+        clear_error();
+        return fail(NK_E_INVALID_ARG, "sources is NULL");
+    }
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, kEstBisect);
 }
 
 nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,

@@ -14,7 +14,8 @@ enum Mode : int {
     kModeBC = 0,    // forward + dependency sweep, scores into bc
     kModeSSSP = 1,  // forward only, d and sigma written out per task
     kModePair = 2,  // one sampled pair: bidirectional search and path walk
-    kModeClose = 3  // forward with unit path counts; distance sums for closeness
+    kModeClose = 3,  // forward with unit path counts; distance sums for closeness
+    kModeBisect = 4  // betweenness with the bisection estimator (keeps distances)
 };
 
 // Everything a persistent launch reads.  Per-slot scratch arrays hold

@@ -174,7 +174,7 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
                 if (act[j]) {
                     c.dag++;
                     if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
-                    if ((MODE == kModeSSSP || MODE == kModePair) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
+                    if ((MODE == kModeSSSP || MODE == kModeBisect) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
                 }
                 wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
             }
@@ -273,7 +273,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
             if (sum != 0ULL) {
                 w = sm.v[tid];
                 s.sigma[w] = sum;
-                if (MODE == kModeSSSP || MODE == kModePair) s.d[w] = lvl + 1;
+                if (MODE == kModeSSSP || MODE == kModeBisect) s.d[w] = lvl + 1;
                 fresh = true;
             }
         }
@@ -301,11 +301,10 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 }
 
 // Forward phase from `src`.  Returns the deepest non-empty level Ld; the
-// list holds levels 0..Ld at s.lvl[l] .. s.lvl[l+1].  In pair mode the
-// search stops after the level that reaches `target`.
+// list holds levels 0..Ld at s.lvl[l] .. s.lvl[l+1].
 template <int BLOCK, int MODE>
 __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
-                           const uint32_t *iso, int32_t src, int32_t target, Counters &c) {
+                           const uint32_t *iso, int32_t src, Counters &c) {
     const int tid = threadIdx.x;
     const int32_t nw = (g.n + 31) >> 5;
     phase_start<BLOCK>(sm);
@@ -319,7 +318,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
     if (tid == 0) {
         bm[src >> 5] |= 1u << (src & 31);
         s.sigma[src] = 1ULL;
-        if (MODE == kModeSSSP || MODE == kModePair) s.d[src] = 0;
+        if (MODE == kModeSSSP || MODE == kModeBisect) s.d[src] = 0;
         const int32_t a0 = g.rp[src];
         const int32_t dsrc = g.rp[src + 1] - a0;
         s.lv[0] = src;
@@ -333,14 +332,12 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
         c.arcs_reached += (unsigned long long)dsrc;
         sm.lvl_lo[0] = 0;
         sm.lvl_lo[1] = 1;
-        sm.flag = 0;
     }
     __syncthreads();
     phase_end<BLOCK>(sm, kPhInit);
     int32_t lvl = 0;
     for (;;) {
         const int32_t f0 = sm.lvl_lo[0], f1 = sm.lvl_lo[1];
-        if (MODE == kModePair && sm.flag) break;
         const bool bu = (p.bu_ratio > 0.0f) && ((double)sm.mu < (double)p.bu_ratio * (double)sm.mf);
         __syncthreads();
         if (tid == 0) {
@@ -386,7 +383,6 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
             sm.mu -= sm.acc_mf;
             sm.mf = sm.acc_mf;
             c.arcs_reached += (unsigned long long)sm.acc_mf;
-            if (MODE == kModePair) sm.flag = bit_test(bm, target) ? 1 : 0;
         }
         __syncthreads();
         phase_end<BLOCK>(sm, kPhMark);
@@ -402,7 +398,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
 // (= level l+1) neighbours.
 template <int BLOCK>
 __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
-                        double *bcg, double wfac, double *ebc, bool add_bc, Counters &c) {
+                        double *bcg, double wfac, double owt, double *ebc, bool add_bc, Counters &c) {
     const int tid = threadIdx.x;
     sub_start<BLOCK>(sm);
     for (int32_t tb = lo; tb < hi; tb += BLOCK) {
@@ -451,7 +447,7 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
             const double sg = (double)s.sigma[v];
             const double delta = sg * sm.val.f[tid] * wfac;
             s.sigma[v] = as_u64((1.0 + delta) / sg);
-            if (add_bc && delta != 0.0) atomicAdd(bcg + v, delta);
+            if (add_bc && delta != 0.0 && owt != 0.0) atomicAdd(bcg + v, delta * owt);
         }
         __syncthreads();
         sub_mark<BLOCK>(sm, kSbPlFin);
@@ -463,7 +459,7 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // level l (list[lo, hi)) takes delta_v = sigma_v * dacc[v] and clears dacc.
 template <int BLOCK>
 __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
-                        int32_t lo1, int32_t hi1, double *bcg, double wfac, Counters &c) {
+                        int32_t lo1, int32_t hi1, double *bcg, double wfac, double owt, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t tb = lo1; tb < hi1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, hi1 - tb);
@@ -486,16 +482,84 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
         const double delta = sg * s.dacc[v] * wfac;
         s.dacc[v] = 0.0;
         s.sigma[v] = as_u64((1.0 + delta) / sg);
-        if (delta != 0.0) atomicAdd(bcg + v, delta);
+        if (delta != 0.0 && owt != 0.0) atomicAdd(bcg + v, delta * owt);
     }
     __syncthreads();
 }
 
+// Bisection estimator, one cutoff depth T (2 <= T < Ld): delta^T counts
+// only targets at depth <= T.  A vertex on level l takes half of
+// delta^(2l-1) and half of delta^(2l), so this sweep serves level
+// ceil(T/2) only and runs from level T-1 up to it.  The targets' inverse
+// path counts and then (1 + delta^T) / sigma sit in dacc; a neighbour
+// belongs to the level below exactly when its distance says so (other
+// vertices' dacc entries are zero).  The sweep clears what it wrote.
 template <int BLOCK>
+__device__ void bis_sweep(Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t T, double *bcg, Counters &c) {
+    const int tid = threadIdx.x;
+    const int32_t lmin = (T + 1) / 2;
+    for (int32_t i = s.lvl[T] + tid; i < s.lvl[T + 1]; i += BLOCK) {
+        const int32_t w = s.lv[i];
+        s.dacc[w] = 1.0 / (double)s.sigma[w];
+    }
+    __syncthreads();
+    for (int32_t l = T - 1; l >= lmin; --l) {
+        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
+        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, hi - tb);
+            if (tid < cnt) sm.val.f[tid] = 0.0;
+            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+            __syncthreads();
+            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                int32_t kk[kChunk], w[kChunk];
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                double cf[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) cf[j] = (kk[j] >= 0 && s.d[w[j]] == l + 1) ? s.dacc[w[j]] : 0.0;
+                int32_t kcur = kk[0];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    if (kk[j] < 0) continue;
+                    if (kk[j] != kcur) {
+                        if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                        kcur = kk[j];
+                        acc = 0.0;
+                    }
+                    acc += cf[j];
+                }
+                if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                const int32_t v = sm.v[tid];
+                const double sg = (double)s.sigma[v];
+                const double delta = sg * sm.val.f[tid];
+                if (l > lmin)
+                    s.dacc[v] = (1.0 + delta) / sg;
+                else if (delta != 0.0)
+                    atomicAdd(bcg + v, 0.5 * delta);
+            }
+            __syncthreads();
+        }
+    }
+    for (int32_t i = s.lvl[lmin + 1] + tid; i < s.lvl[T + 1]; i += BLOCK) s.dacc[s.lv[i]] = 0.0;
+    __syncthreads();
+}
+
+template <int BLOCK, bool BIS>
 __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
                          int32_t Ld, double *bcg, Counters &c) {
     const int tid = threadIdx.x;
     if (Ld == 0) return;
+    // bisection: the truncated sweeps need the path counts, which the full
+    // sweep below overwrites with coefficients, so they run first
+    if constexpr (BIS) {
+        phase_start<BLOCK>(sm);
+        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, s, g, T, bcg, c);
+        phase_end<BLOCK>(sm, kPhPull);
+    }
     {
         const int32_t lo = s.lvl[Ld], hi = s.lvl[Ld + 1];
         for (int32_t i = lo + tid; i < hi; i += BLOCK) {
@@ -513,14 +577,17 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         // linear scaling: the pair weights d(s,v)/d(s,t) factor as l/(l+1)
         // per DAG step from level l+1 to level l
         const double wfac = p.linear ? (double)l / (double)(l + 1) : 1.0;
+        // bisection: level l takes the full dependency once for each of the
+        // depths 2l-1, 2l that reach the deepest level Ld
+        const double owt = BIS ? 0.5 * ((2 * l - 1 >= Ld ? 1.0 : 0.0) + (2 * l >= Ld ? 1.0 : 0.0)) : 1.0;
         // scan whichever side of the level pair has fewer arcs
         const bool push = !p.ebc && (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
         phase_start<BLOCK>(sm);
         if (push) {
             if (tid == 0) c.bw_push++;
-            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, c);
+            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, owt, c);
         } else {
-            bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, wfac, p.ebc, l >= 1, c);
+            bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, wfac, owt, p.ebc, l >= 1, c);
         }
         if (push) phase_end<BLOCK>(sm, kPhPush); else phase_end<BLOCK>(sm, kPhPull);
         for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
@@ -1009,7 +1076,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             continue;
         } else {
 
-        const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, p.G > 0 ? nullptr : p.iso, src, target, c);
+        const int32_t Ld = forward<BLOCK, MODE>(p, sm, bm, s, g, p.G > 0 ? nullptr : p.iso, src, c);
         const int32_t nreached = s.lvl[Ld + 1];
         if (tid == 0) {
             c.reached += (unsigned long long)nreached;
@@ -1032,8 +1099,8 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                     for (int32_t i = s.lvl[l] + tid; i < s.lvl[l + 1]; i += BLOCK)
                         atomicAdd(p.close_acc + s.lv[i], (unsigned long long)l);
             }
-        } else if (MODE == kModeBC) {
-            backward<BLOCK>(p, sm, bm, s, g, Ld, p.bc + g.vbase, c);
+        } else if (MODE == kModeBC || MODE == kModeBisect) {
+            backward<BLOCK, MODE == kModeBisect>(p, sm, bm, s, g, Ld, p.bc + g.vbase, c);
         } else if (MODE == kModeSSSP) {
             const long long row = task * (long long)g.n;
             for (int32_t i = tid; i < nreached; i += BLOCK) {
@@ -1099,6 +1166,7 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
         case kModeSSSP: return ref_mode<kModeSSSP>(block, bitmap_in_lds);
         case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
         case kModeClose: return ref_mode<kModeClose>(block, bitmap_in_lds);
+        case kModeBisect: return ref_mode<kModeBisect>(block, bitmap_in_lds);
         default: return ref_mode<kModeBC>(block, bitmap_in_lds);
     }
 }

@@ -1,5 +1,5 @@
-"""GPU parity of the linear-scaling estimator and of edge betweenness
-against the oracle, through the C ABI."""
+"""GPU parity of the linear-scaling and bisection estimators and of edge
+betweenness against the oracle, through the C ABI."""
 import numpy as np
 import pytest
 import torch
@@ -74,6 +74,66 @@ def test_linear_rmat14_sampled_relabelled():
     got = nk.nk_bc_sources_linear(rp, ci, ivec(src), 2.0 * g.n / 256).cpu().numpy()
     assert_scores_close(got, oracle.bc_sources_linear(g.rowptr, g.colidx, src, 2.0 * g.n / 256, nthreads=8),
                         "rmat14 linear")
+
+
+@pytest.mark.parametrize("make", GRAPHS)
+def test_bisect_exact_sources(make):
+    """All sources and a sampled set (the bisection sweeps run on the
+    global kernel only)."""
+    g = make()
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_bisect(rp, ci, None, 2.0).cpu().numpy()
+    ref = oracle.bc_sources_bisect(g.rowptr, g.colidx, np.arange(g.n), 2.0, nthreads=8)
+    assert_scores_close(got, ref, g.name + " all")
+    k = min(g.n, 97)
+    src = gg.sample_sources(g.n, k, 84)
+    got = nk.nk_bc_sources_bisect(rp, ci, ivec(src), 2.0 * g.n / k).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources_bisect(g.rowptr, g.colidx, src, 2.0 * g.n / k), g.name + " sampled")
+
+
+def test_bisect_all_sources_is_half_of_exact_on_gpu():
+    g = gg.barabasi_albert(3000, 3, 85)
+    rp, ci = upload(g)
+    bis = nk.nk_bc_sources_bisect(rp, ci, None, 2.0).cpu().numpy()
+    assert_scores_close(bis, nk.nk_bc_exact(rp, ci).cpu().numpy(), "2 x bisection vs exact")
+
+
+@pytest.mark.parametrize("block", [256, 1024])
+@pytest.mark.parametrize("bu_ratio", [0.0, 1e9])
+@pytest.mark.parametrize("bw_ratio", [0.0, 1e9])
+def test_bisect_launch_variants(block, bu_ratio, bw_ratio):
+    """Output weights in both the pull and the push sweep, truncated sweeps
+    after top-down and bottom-up forward levels."""
+    nk.nk_set_tuning(block=block, bu_ratio=bu_ratio, bw_ratio=bw_ratio)
+    g = gg.rmat(11, 8, 86)
+    src = gg.sample_sources(g.n, 64, 87)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_bisect(rp, ci, ivec(src), g.n / 32).cpu().numpy()
+    st = nk.nk_last_stats()
+    if bw_ratio > 1:
+        assert st["levels_bw_push"] > 0
+    assert_scores_close(got, oracle.bc_sources_bisect(g.rowptr, g.colidx, src, g.n / 32), "bisect variant")
+
+
+def test_bisect_rmat14_sampled_relabelled():
+    g = gg.rmat(14, 16, 88)
+    src = gg.sample_sources(g.n, 256, 89)
+    rp, ci = upload(g)
+    got = nk.nk_bc_sources_bisect(rp, ci, ivec(src), 2.0 * g.n / 256).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources_bisect(g.rowptr, g.colidx, src, 2.0 * g.n / 256, nthreads=8),
+                        "rmat14 bisect")
+
+
+def test_bisect_edge_cases_and_errors():
+    g = gg.cycle(12)
+    rp, ci = upload(g)
+    out = nk.nk_bc_sources_bisect(rp, ci, torch.zeros(0, dtype=torch.int32, device="cuda:0"), 1.0)
+    assert not out.any()
+    with pytest.raises(nk.NkError) as e:
+        nk.nk_bc_sources_bisect(rp, ci, ivec([0, 12]), 1.0)
+    assert e.value.code == nk.NK_E_INVALID_ARG
+    got = nk.nk_bc_sources_bisect(rp, ci, ivec([3]), 1.0).cpu().numpy()
+    assert_scores_close(got, oracle.bc_sources_bisect(g.rowptr, g.colidx, [3]), "cycle after errors")
 
 
 @pytest.mark.parametrize("make", GRAPHS)

@@ -1,7 +1,7 @@
-"""Pins of the oracle's linear-scaling estimator (Geisberger, Sanders and
-Schultes) and edge betweenness against brute force, closed forms and
-invariants computed independently of it (scipy shortest paths and
-components)."""
+"""Pins of the oracle's linear-scaling and bisection estimators
+(Geisberger, Sanders and Schultes) and edge betweenness against brute force,
+closed forms and invariants computed independently of it (scipy shortest
+paths and components)."""
 from fractions import Fraction
 
 import numpy as np
@@ -31,6 +31,16 @@ def test_linear_matches_definition_by_enumeration(make):
     for sources in (list(range(g.n)), [0, g.n - 1, g.n // 2], [1, 1]):
         got = oracle.bc_sources_linear(g.rowptr, g.colidx, sources)
         ref = bf.linear_dependencies(g.rowptr, g.colidx, sources)
+        for v in range(g.n):
+            assert abs(Fraction(got[v]) - ref[v]) <= Fraction(1, 10 ** 12) * max(1, abs(ref[v])), (g.name, v)
+
+
+@pytest.mark.parametrize("make", SMALL + [lambda: gg.cycle(8), lambda: gg.path(9)])
+def test_bisect_matches_definition_by_enumeration(make):
+    g = make()
+    for sources in (list(range(g.n)), [0, g.n - 1, g.n // 2], [1, 1]):
+        got = oracle.bc_sources_bisect(g.rowptr, g.colidx, sources)
+        ref = bf.bisection_dependencies(g.rowptr, g.colidx, sources)
         for v in range(g.n):
             assert abs(Fraction(got[v]) - ref[v]) <= Fraction(1, 10 ** 12) * max(1, abs(ref[v])), (g.name, v)
 
@@ -66,6 +76,39 @@ def test_linear_over_all_sources_is_half_of_exact(make):
     assert np.allclose(2.0 * lin, ex, rtol=1e-11, atol=1e-9)
     twice = oracle.bc_sources_linear(g.rowptr, g.colidx, np.arange(g.n), scale=2.0, nthreads=4)
     assert np.allclose(twice, ex, rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("make", MID)
+def test_bisect_over_all_sources_is_half_of_exact(make):
+    """The bisection weight f (1 above one half, 1/2 at one half, 0 below)
+    also satisfies f(x) + f(1 - x) = 1."""
+    g = make()
+    bis = oracle.bc_sources_bisect(g.rowptr, g.colidx, np.arange(g.n), scale=2.0, nthreads=4)
+    assert np.allclose(bis, oracle.bc_exact(g.rowptr, g.colidx), rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 9, 40])
+def test_bisect_single_source_on_a_path(n):
+    """Path 0..n-1 from source 0: v lies on the unique path to every t > v;
+    it counts fully for v < t < 2v and half for t = 2v."""
+    g = gg.path(n)
+    got = oracle.bc_sources_bisect(g.rowptr, g.colidx, [0])
+    want = [0.0] * n
+    for v in range(1, n - 1):
+        want[v] = float(sum(1 for t in range(v + 1, n) if t < 2 * v)) + (0.5 if 2 * v <= n - 1 else 0.0)
+    assert np.array_equal(got, np.array(want))
+
+
+def test_bisect_differs_from_linear_and_plain():
+    """On a graph with paths of several lengths the three source-set sums are
+    pairwise different (a swapped estimator would not pass the GPU parity
+    tests unnoticed)."""
+    g = gg.barabasi_albert(300, 2, 14)
+    src = [0, 7, 99]
+    a = oracle.bc_sources(g.rowptr, g.colidx, src)
+    b = oracle.bc_sources_linear(g.rowptr, g.colidx, src)
+    c = oracle.bc_sources_bisect(g.rowptr, g.colidx, src)
+    assert not np.allclose(a, b) and not np.allclose(b, c) and not np.allclose(a, c)
 
 
 def test_linear_single_source_on_a_path():
