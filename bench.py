@@ -65,6 +65,8 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = 
             oracle.bc_sources_linear(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         elif kind == "bisect":
             oracle.bc_sources_bisect(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
+        elif kind == "directed":
+            oracle.bc_directed(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         elif kind == "edge":
             oracle.edge_bc(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         else:
@@ -144,6 +146,25 @@ def other_workload(args) -> dict:
             rec["cpu_baseline"] = cpu_baseline(g, src, g.m_undirected,
                                                kind={"rmat20_linear": "linear", "rmat20_bisect": "bisect"}.get(
                                                    args.workload, "edge"))
+    elif args.workload == "rmat20_directed":
+        print("bench: generating directed R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
+        g = gg.directed_rmat(20, 16, 2)
+        src = gg.sample_sources(g.n, 4096, 2)
+        rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
+        trp, tci = nk.nk_transpose(rp, ci)
+        k = len(src)
+        bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sec = _timed(lambda: nk.nk_bc_directed(rp, ci, sv, g.n / k, trp, tci, bc=bc), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        # every arc is one directed edge here
+        rec.update(metric="GTEPS, source-sampled directed Brandes betweenness", unit="GTEPS", dtype="f64",
+                   value=round(k * g.m / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": "rmat20_directed_sources4096", "n": g.n, "arcs": g.m, "sources": k,
+                           "kernel_ms": st["kernel_us"] / 1e3, "block": st["block"], "workgroups": st["workgroups"],
+                           "levels_bu": st["levels_bu"], "levels_td": st["levels_td"], "reached": st["reached"]})
+        if not args.no_cpu_baseline:
+            print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+            rec["cpu_baseline"] = cpu_baseline(g, src, g.m, kind="directed")
     elif args.workload == "rmat20_closeness":
         print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
         g, src = gg.workload_rmat20(2)
@@ -379,7 +400,7 @@ def main():
                     help="requests of the default serving line; measured requests per point of --workload serving")
     ap.add_argument("--serving-warm", type=int, default=50, help="warm-up requests per point of --workload serving")
     ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect",
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect", "rmat20_directed",
                              "rmat20_edge", "rmat20_closeness", "er200k", "serving"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()

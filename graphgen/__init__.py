@@ -126,6 +126,49 @@ def from_edges(n: int, u, v, name: str = "") -> Graph:
     return Graph(n, rowptr, colidx[:m].copy(), name)
 
 
+def directed_from_arcs(n: int, u, v, name: str = "") -> Graph:
+    """Directed CSR of out-arcs from an arc list u[i] -> v[i]: rows sorted,
+    duplicates and self-loops dropped, no symmetrisation."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    if u.shape != v.shape:
+        raise ValueError("arc arrays differ in length")
+    if u.size and (u.min() < 0 or v.min() < 0 or u.max() >= n or v.max() >= n):
+        raise ValueError("arc list has a vertex id outside [0, n)")
+    keep = u != v
+    key = np.unique(u[keep] * n + v[keep])
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    if n > 0:
+        np.cumsum(np.bincount(key // n, minlength=n), out=rowptr[1:])
+    return Graph(n, rowptr, (key % n).astype(np.int32), name)
+
+
+def transpose(g: Graph) -> Graph:
+    """In-arc CSR of a directed graph (rows sorted)."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    return directed_from_arcs(g.n, g.colidx, src, g.name + "_T")
+
+
+def directed_rmat(scale: int, edge_factor: int, seed: int, a=0.57, b=0.19, c=0.19) -> Graph:
+    """R-MAT arcs taken as directed (first draw -> second draw), not
+    symmetrised: skewed out- and in-degrees, many vertices reachable from few."""
+    n = 1 << scale
+    ne = edge_factor * n
+    u = np.zeros(ne, dtype=np.int32)
+    v = np.zeros(ne, dtype=np.int32)
+    if _load().gg_rmat(scale, ne, a, b, c, seed, _p(u), _p(v)) != 0:
+        raise ValueError("bad R-MAT parameters")
+    return directed_from_arcs(n, u, v, f"drmat_s{scale}_ef{edge_factor}_s{seed}")
+
+
+def directed_random(n: int, m: int, seed: int) -> Graph:
+    """m arcs with independent uniform endpoints (counter draws on stream
+    90), then deduplicated: a directed G(n, p)-like graph."""
+    u = np.array([(draw(seed, 90, i, 0) * n) >> 64 for i in range(m)], dtype=np.int64)
+    v = np.array([(draw(seed, 90, i, 1) * n) >> 64 for i in range(m)], dtype=np.int64)
+    return directed_from_arcs(n, u, v, f"dgnm_n{n}_m{m}_s{seed}")
+
+
 # ---------------------------------------------------------------- models --
 
 def erdos_renyi(n: int, m: int, seed: int) -> Graph:

@@ -143,6 +143,38 @@ nk_status nk_bc_sources_bisect(const int32_t *rowptr, const int32_t *colidx, int
                                const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
 
 /*
+ * Betweenness of a DIRECTED graph (the paper's graph model allows directed
+ * edges, section "Graph data structure"): shortest paths follow arcs, the
+ * score of v sums sigma_st(v) / sigma_st over ordered pairs (s, t) with a
+ * directed s -> t path, s != v != t, over the listed sources, times scale.
+ *   rowptr, colidx     out-arc CSR (int32[n+1], int32[m] DEVICE; no symmetry
+ *                      required; simple: no self-loops, no duplicate arcs);
+ *   trowptr, tcolidx   the in-arc CSR of the same graph (nk_transpose builds
+ *                      it) or both NULL.  With them, levels with a large
+ *                      frontier run bottom-up over in-arcs; without, every
+ *                      level runs top-down.  A supplied pair is checked for
+ *                      structure and for every vertex's in-degree
+ *                      (NK_E_INVALID_GRAPH otherwise);
+ *   sources, k, scale  as nk_bc_sources (NULL with k = n: every vertex, the
+ *                      exact scores);
+ *   bc                 FP64[n] DEVICE, overwritten.
+ * The dependency sweep always pulls over out-arcs.  The graph keeps its own
+ * ids (no degree relabelling).  Same errors as nk_bc_sources.
+ */
+nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int32_t *trowptr,
+                         const int32_t *tcolidx, int32_t n, int64_t m, const int32_t *sources, int32_t k,
+                         double scale, double *bc, void *stream);
+
+/*
+ * In-arc CSR of a directed graph given by its out-arcs: trowptr int32[n+1]
+ * and tcolidx int32[m] DEVICE, caller-allocated, overwritten; every row
+ * sorted ascending.  The input is validated first (NK_E_INVALID_GRAPH).
+ * Synchronises the stream; scratch of about 16 m bytes.
+ */
+nk_status nk_transpose(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *trowptr,
+                       int32_t *tcolidx, void *stream);
+
+/*
  * Edge betweenness (section "Edge Centrality, Sparsification and Link
  * Prediction"): for the undirected edge {u, v}, the sum over ordered pairs
  * (s, t), s in the source list, of the share of shortest s-t paths that

@@ -61,6 +61,7 @@ def _load():
         "or_bc_exact": (c.c_int, g + [f64p, c.c_int32]),
         "or_bc_sources_linear": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_bc_sources_bisect": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
+        "or_bc_directed": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_edge_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, f64p, c.c_int32]),
         "or_closeness": (c.c_int, g + [f64p]),
         "or_closeness_approx": (c.c_int, g + [i32p, c.c_int32, f64p, i64p]),
@@ -174,6 +175,21 @@ def bc_sources_bisect(rowptr, colidx, sources, scale: float = 1.0, nthreads: int
     _check(_load().or_bc_sources_bisect(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
                                         _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double),
                                         nthreads), "bc_sources_bisect")
+    return bc[:n]
+
+
+def bc_directed(rowptr, colidx, sources=None, scale: float = 1.0, nthreads: int = 1) -> np.ndarray:
+    """Directed betweenness (out-arc CSR, no symmetry needed) summed over
+    `sources` (None: every vertex, the exact scores), times `scale`."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    bc = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_bc_directed(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                  _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double), nthreads),
+           "bc_directed")
     return bc[:n]
 
 

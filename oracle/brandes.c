@@ -15,6 +15,7 @@
  *   - the linear-scaling and bisection source-set estimators of
  *     Geisberger, Sanders and Schultes (the reference cited for that
  *     sampling);
+ *   - directed graphs (out-arc CSR) for the exact and source-set forms;
  *   - edge betweenness (section "Edge Centrality, Sparsification and Link
  *     Prediction");
  *   - closeness, exact and sampled (Table 1, "closeness", "ap. closeness");
@@ -250,6 +251,38 @@ static int one_source_bisect(const graph_t *g, int32_t s, work_t *w, double *bc)
 }
 
 /*
+ * One source of Brandes' algorithm on a directed graph (the paper's graph
+ * model allows directed edges, section "Graph data structure"; the
+ * adjacency arrays hold out-arcs).  The forward phase follows out-arcs as
+ * it is.  Predecessors of x are its in-neighbours, which the out-arc
+ * arrays do not list, so the accumulation is written in the successor
+ * form: in reverse visit order,
+ *     delta[v] = sum over out-arcs v -> w with d[w] = d[v] + 1 of
+ *                sigma[v] / sigma[w] * (1 + delta[w]),
+ * every such w coming later in the visit order and so already final; then
+ * bc[v] += delta[v] for v != s.
+ */
+static int one_source_directed(const graph_t *g, int32_t s, work_t *w, double *bc) {
+    int32_t nS = 0;
+    int status = forward(g, s, w->d, w->sigma, w->S, &nS, w->queue);
+    if (status == OR_OK) {
+        for (int32_t i = nS - 1; i >= 0; --i) {
+            int32_t v = w->S[i];
+            double acc = 0.0;
+            for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+                int32_t x = g->colidx[e];
+                if (w->d[x] == w->d[v] + 1)
+                    acc += (double)w->sigma[v] / (double)w->sigma[x] * (1.0 + w->delta[x]);
+            }
+            w->delta[v] = acc;
+            if (v != s) bc[v] += acc;
+        }
+    }
+    work_reset(w, nS);
+    return status;
+}
+
+/*
  * One source of Brandes' algorithm with edge dependencies (edge
  * betweenness, named in the section "Edge Centrality, Sparsification and
  * Link Prediction"): the shortest-path DAG arc v -> w carries
@@ -297,7 +330,7 @@ int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     return st;
 }
 
-enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2, KIND_BISECT = 3 };
+enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2, KIND_BISECT = 3, KIND_DIRECTED = 4 };
 
 typedef struct {
     const graph_t *g;
@@ -318,6 +351,8 @@ static void *run_job(void *arg) {
             int st;
             if (j->kind == KIND_LINEAR)
                 st = one_source_linear(j->g, j->src[i], &w, j->bc);
+            else if (j->kind == KIND_DIRECTED)
+                st = one_source_directed(j->g, j->src[i], &w, j->bc);
             else if (j->kind == KIND_BISECT)
                 st = one_source_bisect(j->g, j->src[i], &w, j->bc);
             else if (j->kind == KIND_EDGE)
@@ -447,6 +482,24 @@ int or_bc_sources_bisect(int32_t n, int64_t m, const int32_t *rowptr, const int3
     if (n > 0 && !bc) return OR_E_INVALID_ARG;
     graph_t g = {n, rowptr, colidx};
     st = run_sources(&g, m, src, k, KIND_BISECT, bc, NULL, nthreads);
+    if (st == OR_OK && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return st;
+}
+
+/*
+ * Directed betweenness over the sources src[0..k) (every vertex for exact
+ * scores): the sum of one_source_directed dependencies times `scale`.
+ * rowptr/colidx are out-arcs; no symmetry is required.
+ */
+int or_bc_directed(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
+                   const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n > 0 && !bc) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    st = run_sources(&g, m, src, k, KIND_DIRECTED, bc, NULL, nthreads);
     if (st == OR_OK && scale != 1.0)
         for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
     return st;

@@ -458,7 +458,8 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
-    p.bu_ratio = tuning_get().bu_ratio;
+    // a directed run without in-arcs grows every level top-down
+    p.bu_ratio = (p.directed && !p.trowptr) ? 0.0f : tuning_get().bu_ratio;
     p.bw_ratio = tuning_get().bw_ratio;
     if (ev0) NK_HIP(hipEventRecord(ev0, s));
     plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
@@ -591,12 +592,18 @@ static nk_status prepare_graph(const int32_t *rowptr, const int32_t *colidx, int
 // Estimators of the source-sampled sweep.
 enum Estimator : int { kEstPlain = 0, kEstLinear = 1, kEstBisect = 2 };
 
+// A directed run: rowptr/colidx are out-arcs; trp/tci the in-arcs or NULL.
+struct DirectedArgs {
+    const int32_t *trp;
+    const int32_t *tci;
+};
+
 // Shared body of nk_bc_exact / nk_bc_sources / nk_bc_sources_linear /
 // nk_bc_sources_bisect / nk_edge_bc.  est selects the estimator; ebc !=
 // NULL also computes edge scores (global kernel, graph under its own ids).
 static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
                                  const int32_t *sources, long long k, double scale, double *bc, void *stream,
-                                 int est = kEstPlain, double *ebc = nullptr) {
+                                 int est = kEstPlain, double *ebc = nullptr, const DirectedArgs *dir = nullptr) {
     clear_error();
     stats_clear();
     nk_status st = check_graph_args(rowptr, colidx, n, m);
@@ -616,6 +623,12 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
     NK_HIP(launch_status_init(dst, s));
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    if (dir && dir->trp) {
+        // the in-arcs must be the out-arcs' transpose (checked: structure
+        // and every vertex's in-degree)
+        NK_HIP(launch_validate(dir->trp, dir->tci, n, m, 0, dst, s));
+        if ((st = check_transpose(colidx, n, m, dir->trp, dst, scr, s)) != NK_OK) return st;
+    }
     NK_HIP(launch_fill_f64(bc, 0.0, n, s));
     if (ebc) NK_HIP(launch_fill_f64(ebc, 0.0, m, s));
     LaunchPlan plan = {};
@@ -648,10 +661,16 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     } else if (k > 0) {
         where = -1;
         Relabeled g = {rowptr, colidx, nullptr, nullptr};
-        // edge scores are kept per arc of the caller's CSR, so that run keeps its ids
-        if (!ebc)
+        // edge scores are kept per arc of the caller's CSR, so that run keeps
+        // its ids; a directed run keeps them too (one renaming would have to
+        // cover both arc arrays)
+        if (!ebc && !dir)
             if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
-        NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
+        // vertices no search can reach: no arcs (undirected) or no in-arcs
+        // (directed; unknown without the in-arc CSR)
+        if (dir)
+            iso = dir->trp ? iso : nullptr;
+        if (iso) NK_HIP(launch_iso_bitmap(dir ? dir->trp : g.rowptr, n, iso, s));
         const int32_t *src = sources;
         double *acc = bc;
         if (g.perm) {
@@ -678,6 +697,9 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.st = dst;
         p.linear = est == kEstLinear;
         p.ebc = ebc;
+        p.directed = dir != nullptr;
+        p.trowptr = dir ? dir->trp : nullptr;
+        p.tcolidx = dir ? dir->tci : nullptr;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
@@ -717,6 +739,44 @@ nk_status nk_bc_sources_linear(const int32_t *rowptr, const int32_t *colidx, int
         return fail(NK_E_INVALID_ARG, "sources is NULL");
     }
     return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, kEstLinear);
+}
+
+nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int32_t *trowptr,
+                         const int32_t *tcolidx, int32_t n, int64_t m, const int32_t *sources, int32_t k,
+                         double scale, double *bc, void *stream) {
+    clear_error();
+    if (k > 0 && !sources && k != n) return fail(NK_E_INVALID_ARG, "sources is NULL");
+    if ((!trowptr && tcolidx) || (trowptr && !tcolidx && m > 0))
+        return fail(NK_E_INVALID_ARG, "give both in-arc arrays or neither");
+    const DirectedArgs dir = {trowptr, tcolidx};
+    return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, kEstPlain, nullptr, &dir);
+}
+
+nk_status nk_transpose(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *trowptr,
+                       int32_t *tcolidx, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (!trowptr || (m > 0 && !tcolidx)) return fail(NK_E_INVALID_ARG, "output arrays are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        NK_HIP(launch_fill_i32(trowptr, 0, 1, s));
+        NK_HIP(hipStreamSynchronize(s));
+        return NK_OK;
+    }
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    // the arc heads index the output rows: validate before building
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    if ((st = finish(dst, h, s)) != NK_OK) return st;
+    if ((st = transpose_graph(rowptr, colidx, n, m, trowptr, tcolidx, scr, s)) != NK_OK) return st;
+    NK_HIP(hipStreamSynchronize(s));
+    return NK_OK;
 }
 
 nk_status nk_bc_sources_bisect(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,

@@ -72,8 +72,13 @@ struct Params {
     // by d(s, v) / d(s, t) (linear scaling); ebc != NULL also accumulates
     // the per-arc edge terms (single graph, pull sweep down to level 0)
     int32_t linear;
-    int32_t pad1;
+    // directed graph (single graph, BC modes): rowptr/colidx are the out-
+    // arcs; trowptr/tcolidx the in-arcs for bottom-up levels (NULL: top-down
+    // only).  The dependency sweep always pulls over out-arcs.
+    int32_t directed;
     double *ebc;
+    const int32_t *trowptr;
+    const int32_t *tcolidx;
     // pair mode: 32-byte per-vertex records of both search sides (path
     // counts and distances from u and from v; `stride` records per slot)
     // and the level lists of the side grown from the target

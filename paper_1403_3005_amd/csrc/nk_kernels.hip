@@ -56,6 +56,10 @@ struct GView {
     int32_t n;
     int32_t m;
     long long vbase;   // offset of vertex 0 in concatenated outputs
+    // arcs a bottom-up level scans: the in-arcs (the same arrays as rp/ci
+    // for an undirected graph)
+    const int32_t *trp;
+    const int32_t *tci;
 };
 
 struct Scr {
@@ -186,10 +190,15 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 // Bottom-up expansion: every unvisited vertex sums sigma over its marked
 // (= frontier) neighbours.
 template <int BLOCK, int MODE>
-__device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+__device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &go,
                          int32_t f1, int32_t lvl, Counters &c) {
     const int tid = threadIdx.x;
     const int lane = lane_id();
+    // an unreached vertex looks for visited in-neighbours
+    GView g = go;
+    g.rp = go.trp;
+    g.ci = go.tci;
+    const bool sym = go.trp == go.rp;
     const int32_t nw = (g.n + 31) >> 5;
     if (tid == 0) sm.redmin = 0;  // candidate counter
     __syncthreads();
@@ -268,10 +277,18 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         sub_mark<BLOCK>(sm, kSbBuArcs);
         bool fresh = false;
         int32_t w = 0;
+        int32_t wa = 0, wd = 0;   // first out-arc and out-degree of the new vertex
         if (tid < cnt) {
             const unsigned long long sum = sm.val.u[tid];
             if (sum != 0ULL) {
                 w = sm.v[tid];
+                if (sym) {
+                    wa = sm.a0[tid];
+                    wd = dg;
+                } else {
+                    wa = go.rp[w];
+                    wd = go.rp[w + 1] - wa;
+                }
                 s.sigma[w] = sum;
                 if (MODE == kModeSSSP || MODE == kModeBisect) s.d[w] = lvl + 1;
                 fresh = true;
@@ -287,8 +304,8 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
             const int32_t pos = base + rank;
             if (pos < g.n - f1) {
                 s.lv[f1 + pos] = w;
-                s.la[f1 + pos] = sm.a0[tid];
-                s.ld[f1 + pos] = dg;
+                s.la[f1 + pos] = wa;
+                s.ld[f1 + pos] = wd;
             } else {
                 atomicOr(&p.st->err, kErrInternal);
             }
@@ -581,7 +598,8 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         // depths 2l-1, 2l that reach the deepest level Ld
         const double owt = BIS ? 0.5 * ((2 * l - 1 >= Ld ? 1.0 : 0.0) + (2 * l >= Ld ? 1.0 : 0.0)) : 1.0;
         // scan whichever side of the level pair has fewer arcs
-        const bool push = !p.ebc && (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
+        // (a push scans in-arcs, which a directed run may not have)
+        const bool push = !p.ebc && !p.directed && (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
         phase_start<BLOCK>(sm);
         if (push) {
             if (tid == 0) c.bw_push++;
@@ -1036,6 +1054,8 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             g.n = (int32_t)(p.g_vtx[gid + 1] - v0);
             g.m = (int32_t)(p.g_arc[gid + 1] - p.g_arc[gid]);
             g.vbase = v0;
+            g.trp = g.rp;
+            g.tci = g.ci;
             src = (int32_t)(task - p.g_task[lo]);
         } else {
             g.rp = p.rowptr;
@@ -1043,6 +1063,8 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             g.n = p.n;
             g.m = p.m;
             g.vbase = 0;
+            g.trp = p.trowptr ? p.trowptr : p.rowptr;
+            g.tci = p.trowptr ? p.tcolidx : p.colidx;
             if (MODE == kModePair) {
                 j = p.j0 + task;
                 const int32_t a = (int32_t)bounded(draw(p.seed, 1, (unsigned long long)j, 0), (unsigned long long)p.n);

@@ -135,6 +135,14 @@ nk_status check_graph_args(const int32_t *rowptr, const int32_t *colidx, int32_t
 
 // Degree-order relabelling (nk_relabel.hip).  Kernels skip their work when
 // the structural check already failed.
+// Directed graphs (nk_directed.hip): the in-arc CSR of out-arcs (rows
+// sorted by tail), and a check that trowptr's row lengths are the
+// in-degrees of colidx (sets kErrGraph in dst otherwise).
+nk_status transpose_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *trowptr,
+                          int32_t *tcolidx, Scratch &scr, hipStream_t s);
+nk_status check_transpose(const int32_t *colidx, int32_t n, int64_t m, const int32_t *trowptr, DevStatus *dst,
+                          Scratch &scr, hipStream_t s);
+
 nk_status relabel_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const DevStatus *st,
                         Scratch &scr, hipStream_t s, Relabeled *out);
 hipError_t launch_map_sources(const int32_t *src, int32_t k, const int32_t *perm, int32_t n, int32_t *out,
