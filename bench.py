@@ -67,6 +67,8 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = 
             oracle.bc_sources_bisect(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         elif kind == "directed":
             oracle.bc_directed(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
+        elif kind == "weighted":
+            oracle.bc_weighted(g.rowptr, g.colidx, g.weights, sources, 1.0, nthreads=threads)
         elif kind == "edge":
             oracle.edge_bc(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
         else:
@@ -165,6 +167,26 @@ def other_workload(args) -> dict:
         if not args.no_cpu_baseline:
             print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
             rec["cpu_baseline"] = cpu_baseline(g, src, g.m, kind="directed")
+    elif args.workload == "rmat20_weighted":
+        print("bench: generating R-MAT scale 20 (seed 2), weights in [1, 64] and 4096 sources", file=sys.stderr,
+              flush=True)
+        g, src = gg.workload_rmat20(2)
+        g.weights = gg.edge_weights(g, 64, 2)
+        rp, ci, sv, wt = up(g.rowptr), up(g.colidx), up(src), up(g.weights)
+        k = len(src)
+        bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sec = _timed(lambda: nk.nk_bc_weighted(rp, ci, wt, sv, g.n / k, bc=bc), args.steps, args.warmup)
+        st = nk.nk_last_stats()
+        rec.update(metric="GTEPS, source-sampled weighted Brandes betweenness (integer weights 1..64)",
+                   unit="GTEPS", dtype="u64+f64", value=round(k * g.m_undirected / sec / 1e9, 3),
+                   ms_per_step=round(sec * 1e3, 3),
+                   config={"workload": "rmat20_weighted_sources4096", "n": g.n, "arcs": g.m, "sources": k,
+                           "kernel_ms": st["kernel_us"] / 1e3, "block": st["block"], "workgroups": st["workgroups"],
+                           "distance_rounds": st["levels_td"], "dag_layers": st["levels_bu"],
+                           "arcs_relaxed": st["arcs_fwd"], "reached": st["reached"]})
+        if not args.no_cpu_baseline:
+            print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+            rec["cpu_baseline"] = cpu_baseline(g, src, g.m_undirected, kind="weighted")
     elif args.workload == "rmat20_closeness":
         print("bench: generating R-MAT scale 20 (seed 2) and 4096 sources", file=sys.stderr, flush=True)
         g, src = gg.workload_rmat20(2)
@@ -400,7 +422,7 @@ def main():
                     help="requests of the default serving line; measured requests per point of --workload serving")
     ap.add_argument("--serving-warm", type=int, default=50, help="warm-up requests per point of --workload serving")
     ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect", "rmat20_directed",
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect", "rmat20_directed", "rmat20_weighted",
                              "rmat20_edge", "rmat20_closeness", "er200k", "serving"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()

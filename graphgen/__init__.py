@@ -61,6 +61,9 @@ def _load():
     lib.gg_ba.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, i32p, i32p]
     lib.gg_sample_sources.restype = ctypes.c_int
     lib.gg_sample_sources.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, i32p]
+    lib.gg_bounded_draws.restype = ctypes.c_int
+    lib.gg_bounded_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.c_int64, ctypes.c_uint64, i32p]
     lib.gg_csr.restype = ctypes.c_int64
     lib.gg_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p]
     _lib = lib
@@ -167,6 +170,24 @@ def directed_random(n: int, m: int, seed: int) -> Graph:
     u = np.array([(draw(seed, 90, i, 0) * n) >> 64 for i in range(m)], dtype=np.int64)
     v = np.array([(draw(seed, 90, i, 1) * n) >> 64 for i in range(m)], dtype=np.int64)
     return directed_from_arcs(n, u, v, f"dgnm_n{n}_m{m}_s{seed}")
+
+
+def edge_weights(g: Graph, wmax: int, seed: int, symmetric: bool = True) -> np.ndarray:
+    """int32 weight per arc, uniform in [1, wmax] from counter draws (stream
+    91) keyed by the edge {u, v} (both arcs equal: an undirected weighted
+    graph) or, with symmetric=False, by the arc index."""
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    dst = g.colidx.astype(np.int64)
+    key = np.minimum(src, dst) * g.n + np.maximum(src, dst) if symmetric else np.arange(g.m, dtype=np.int64)
+    if g.m == 0:
+        return np.zeros(0, dtype=np.int32)
+    uniq, inv = np.unique(key, return_inverse=True)
+    uniq = np.ascontiguousarray(uniq, dtype=np.int64)
+    w = np.zeros(uniq.shape[0], dtype=np.int32)
+    if _load().gg_bounded_draws(seed, 91, uniq.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), uniq.shape[0],
+                                wmax, _p(w)) != 0:
+        raise ValueError("bad weight range")
+    return (w[inv] + 1).astype(np.int32)
 
 
 # ---------------------------------------------------------------- models --

@@ -36,6 +36,13 @@ static inline uint64_t bounded(uint64_t x, uint64_t N) {
     return (uint64_t)(((unsigned __int128)x * N) >> 64);
 }
 
+/* out[i] = bounded(gg_draw(seed, stream, keys[i], 0), N) for i < count. */
+int gg_bounded_draws(uint64_t seed, uint64_t stream, const int64_t *keys, int64_t count, uint64_t N, int32_t *out) {
+    if (count < 0 || N == 0 || N > 0x7fffffffULL) return -1;
+    for (int64_t i = 0; i < count; ++i) out[i] = (int32_t)bounded(gg_draw(seed, stream, (uint64_t)keys[i], 0), N);
+    return 0;
+}
+
 /* uniform double in the open interval (0, 1) */
 static inline double unit_open(uint64_t x) {
     return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0);

@@ -166,6 +166,25 @@ nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int
                          double scale, double *bc, void *stream);
 
 /*
+ * Betweenness with positive integer arc weights (the paper's graph model
+ * carries edge weights, section "Graph data structure"): shortest paths
+ * minimise the weight sum, sigma counts the minimum-weight paths, and the
+ * score of v sums sigma_st(v) / sigma_st over ordered pairs (s, t), s != v
+ * != t, over the listed sources, times scale.
+ *   rowptr, colidx  out-arc CSR, DEVICE; an undirected weighted graph is
+ *                   given as both arcs of every edge with the same weight
+ *                   (no symmetry is required: a directed weighted graph
+ *                   works as is);
+ *   weights         int32[m] DEVICE, weights[e] >= 1 for arc e
+ *                   (NK_E_INVALID_GRAPH otherwise); distances are 64-bit;
+ *   sources, k, scale, bc  as nk_bc_sources (NULL with k = n: exact).
+ * Integer weights keep "d(s, v) + w = d(s, x)" exact on both sides of a
+ * comparison.  The graph keeps its ids.  Same errors as nk_bc_sources.
+ */
+nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int32_t *weights, int32_t n,
+                         int64_t m, const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
+
+/*
  * In-arc CSR of a directed graph given by its out-arcs: trowptr int32[n+1]
  * and tcolidx int32[m] DEVICE, caller-allocated, overwritten; every row
  * sorted ascending.  The input is validated first (NK_E_INVALID_GRAPH).

@@ -62,6 +62,8 @@ def _load():
         "or_bc_sources_linear": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_bc_sources_bisect": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
         "or_bc_directed": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
+        "or_bc_weighted": (c.c_int, g + [i32p, i32p, c.c_int32, c.c_double, f64p, c.c_int32]),
+        "or_sssp_weighted": (c.c_int, g + [i32p, c.c_int32, c.POINTER(c.c_int64), c.POINTER(c.c_uint64)]),
         "or_edge_bc_sources": (c.c_int, g + [i32p, c.c_int32, c.c_double, f64p, f64p, c.c_int32]),
         "or_closeness": (c.c_int, g + [f64p]),
         "or_closeness_approx": (c.c_int, g + [i32p, c.c_int32, f64p, i64p]),
@@ -191,6 +193,38 @@ def bc_directed(rowptr, colidx, sources=None, scale: float = 1.0, nthreads: int 
                                   _ptr(src, ctypes.c_int32), k, float(scale), _ptr(bc, ctypes.c_double), nthreads),
            "bc_directed")
     return bc[:n]
+
+
+def bc_weighted(rowptr, colidx, weights, sources=None, scale: float = 1.0, nthreads: int = 1) -> np.ndarray:
+    """Betweenness with int32 arc weights >= 1 (out-arc CSR) summed over
+    `sources` (None: every vertex), times `scale`."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    wts = np.ascontiguousarray(weights, dtype=np.int32)
+    if wts.size == 0:
+        wts = np.ones(1, dtype=np.int32)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    if k == 0:
+        src = np.zeros(1, dtype=np.int32)
+    bc = np.zeros(max(n, 1), dtype=np.float64)
+    _check(_load().or_bc_weighted(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                  _ptr(wts, ctypes.c_int32), _ptr(src, ctypes.c_int32), k, float(scale),
+                                  _ptr(bc, ctypes.c_double), nthreads), "bc_weighted")
+    return bc[:n]
+
+
+def sssp_weighted(rowptr, colidx, weights, source: int):
+    """(d int64 with -1 unreachable, sigma uint64) from one source."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    wts = np.ascontiguousarray(weights, dtype=np.int32)
+    if wts.size == 0:
+        wts = np.ones(1, dtype=np.int32)
+    d = np.zeros(max(n, 1), dtype=np.int64)
+    sigma = np.zeros(max(n, 1), dtype=np.uint64)
+    _check(_load().or_sssp_weighted(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
+                                    _ptr(wts, ctypes.c_int32), int(source), _ptr(d, ctypes.c_int64),
+                                    _ptr(sigma, ctypes.c_uint64)), "sssp_weighted")
+    return d[:n], sigma[:n]
 
 
 def edge_bc(rowptr, colidx, sources=None, scale: float = 1.0, nthreads: int = 1):

@@ -16,6 +16,8 @@
  *     Geisberger, Sanders and Schultes (the reference cited for that
  *     sampling);
  *   - directed graphs (out-arc CSR) for the exact and source-set forms;
+ *   - positive integer arc weights (Dijkstra instead of breadth-first
+ *     search) for the exact and source-set forms;
  *   - edge betweenness (section "Edge Centrality, Sparsification and Link
  *     Prediction");
  *   - closeness, exact and sampled (Table 1, "closeness", "ap. closeness");
@@ -330,6 +332,181 @@ int or_sssp_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     return st;
 }
 
+/*
+ * Weighted graphs (positive integer arc weights; the paper's graph model
+ * carries edge weights).  Forward phase: Dijkstra's algorithm with a binary
+ * heap of (distance, vertex) entries, stale entries skipped when popped.
+ * A vertex is settled when popped with its final distance; its path count
+ * is final then, since every predecessor has a smaller distance.  For each
+ * out-arc v -> x of weight w: a shorter d(v) + w replaces d(x) and
+ * sigma(x) = sigma(v); an equal one adds sigma(v).  S is the settle order.
+ * Accumulation in reverse settle order, successor form (as for directed
+ * graphs): delta(v) = sum over out-arcs v -> x with d(v) + w = d(x) of
+ * sigma(v) / sigma(x) * (1 + delta(x)).
+ */
+typedef struct {
+    int64_t d;
+    int32_t v;
+} heap_item_t;
+
+static void heap_push(heap_item_t *h, int64_t *size, int64_t d, int32_t v) {
+    int64_t i = (*size)++;
+    h[i].d = d;
+    h[i].v = v;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= h[i].d) break;
+        heap_item_t t = h[p]; h[p] = h[i]; h[i] = t;
+        i = p;
+    }
+}
+
+static heap_item_t heap_pop(heap_item_t *h, int64_t *size) {
+    heap_item_t top = h[0];
+    h[0] = h[--(*size)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, b = i;
+        if (l < *size && h[l].d < h[b].d) b = l;
+        if (r < *size && h[r].d < h[b].d) b = r;
+        if (b == i) break;
+        heap_item_t t = h[b]; h[b] = h[i]; h[i] = t;
+        i = b;
+    }
+    return top;
+}
+
+/* d (-1 unreached), sigma and settle order S from s; heap holds m + 1 items. */
+static int forward_weighted(const graph_t *g, const int32_t *wt, int32_t s, int64_t *d, uint64_t *sigma,
+                            uint8_t *done, int32_t *S, int32_t *nS, heap_item_t *heap) {
+    int status = OR_OK;
+    int64_t size = 0;
+    int32_t ns = 0;
+    d[s] = 0;
+    sigma[s] = 1;
+    heap_push(heap, &size, 0, s);
+    while (size > 0) {
+        heap_item_t it = heap_pop(heap, &size);
+        int32_t v = it.v;
+        if (done[v] || it.d != d[v]) continue;
+        done[v] = 1;
+        S[ns++] = v;
+        for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+            int32_t x = g->colidx[e];
+            int64_t nd = d[v] + (int64_t)wt[e];
+            if (d[x] < 0 || nd < d[x]) {
+                d[x] = nd;
+                sigma[x] = sigma[v];
+                heap_push(heap, &size, nd, x);
+            } else if (nd == d[x]) {
+                uint64_t sum;
+                if (__builtin_add_overflow(sigma[x], sigma[v], &sum)) status = OR_E_SIGMA_OVERFLOW;
+                sigma[x] = sum;
+            }
+        }
+    }
+    *nS = ns;
+    return status;
+}
+
+typedef struct {
+    int64_t *d;
+    uint64_t *sigma;
+    double *delta;
+    uint8_t *done;
+    int32_t *S;
+    heap_item_t *heap;
+} wwork_t;
+
+static int wwork_alloc(wwork_t *w, int32_t n, int64_t m) {
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    w->d = (int64_t *)malloc(nn * sizeof(int64_t));
+    w->sigma = (uint64_t *)malloc(nn * sizeof(uint64_t));
+    w->delta = (double *)malloc(nn * sizeof(double));
+    w->done = (uint8_t *)malloc(nn);
+    w->S = (int32_t *)malloc(nn * sizeof(int32_t));
+    w->heap = (heap_item_t *)malloc((size_t)(m + 1) * sizeof(heap_item_t));
+    if (!w->d || !w->sigma || !w->delta || !w->done || !w->S || !w->heap) return OR_E_NO_MEMORY;
+    for (int32_t i = 0; i < n; ++i) { w->d[i] = -1; w->sigma[i] = 0; w->delta[i] = 0.0; w->done[i] = 0; }
+    return OR_OK;
+}
+
+static void wwork_free(wwork_t *w) {
+    free(w->d); free(w->sigma); free(w->delta); free(w->done); free(w->S); free(w->heap);
+}
+
+static int one_source_weighted(const graph_t *g, const int32_t *wt, int32_t s, wwork_t *w, double *bc) {
+    int32_t nS = 0;
+    int status = forward_weighted(g, wt, s, w->d, w->sigma, w->done, w->S, &nS, w->heap);
+    if (status == OR_OK) {
+        for (int32_t i = nS - 1; i >= 0; --i) {
+            int32_t v = w->S[i];
+            double acc = 0.0;
+            for (int32_t e = g->rowptr[v]; e < g->rowptr[v + 1]; ++e) {
+                int32_t x = g->colidx[e];
+                if (w->d[x] == w->d[v] + (int64_t)wt[e])
+                    acc += (double)w->sigma[v] / (double)w->sigma[x] * (1.0 + w->delta[x]);
+            }
+            w->delta[v] = acc;
+            if (v != s) bc[v] += acc;
+        }
+    }
+    for (int32_t i = 0; i < nS; ++i) {
+        int32_t v = w->S[i];
+        w->d[v] = -1; w->sigma[v] = 0; w->delta[v] = 0.0; w->done[v] = 0;
+    }
+    return status;
+}
+
+static int weights_ok(int64_t m, const int32_t *wt) {
+    for (int64_t e = 0; e < m; ++e)
+        if (wt[e] < 1) return 0;
+    return 1;
+}
+
+/* Weighted d (-1 unreachable) and sigma of every vertex for one source. */
+int or_sssp_weighted(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, const int32_t *wt,
+                     int32_t s, int64_t *d, uint64_t *sigma) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (m > 0 && (!wt || !weights_ok(m, wt))) return OR_E_INVALID_GRAPH;
+    if (s < 0 || s >= n || !d || !sigma) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    wwork_t w;
+    if ((st = wwork_alloc(&w, n, m)) != OR_OK) { wwork_free(&w); return st; }
+    int32_t nS;
+    st = forward_weighted(&g, wt, s, w.d, w.sigma, w.done, w.S, &nS, w.heap);
+    for (int32_t i = 0; i < n; ++i) { d[i] = w.d[i]; sigma[i] = w.sigma[i]; }
+    wwork_free(&w);
+    return st;
+}
+
+typedef struct {
+    const graph_t *g;
+    const int32_t *wt;
+    const int32_t *src;
+    int32_t lo, hi;
+    int64_t m;
+    double *bc;
+    int status;
+} wjob_t;
+
+static void *run_wjob(void *arg) {
+    wjob_t *j = (wjob_t *)arg;
+    wwork_t w;
+    j->status = wwork_alloc(&w, j->g->n, j->m);
+    if (j->status == OR_OK)
+        for (int32_t i = j->lo; i < j->hi; ++i) {
+            int st = one_source_weighted(j->g, j->wt, j->src[i], &w, j->bc);
+            if (st != OR_OK) { j->status = st; break; }
+        }
+    wwork_free(&w);
+    return NULL;
+}
+
+int or_bc_weighted(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, const int32_t *wt,
+                   const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads);
+
 enum { KIND_PLAIN = 0, KIND_LINEAR = 1, KIND_EDGE = 2, KIND_BISECT = 3, KIND_DIRECTED = 4 };
 
 typedef struct {
@@ -500,6 +677,52 @@ int or_bc_directed(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     if (n > 0 && !bc) return OR_E_INVALID_ARG;
     graph_t g = {n, rowptr, colidx};
     st = run_sources(&g, m, src, k, KIND_DIRECTED, bc, NULL, nthreads);
+    if (st == OR_OK && scale != 1.0)
+        for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
+    return st;
+}
+
+/*
+ * Weighted betweenness over the sources src[0..k) (every vertex for exact
+ * scores) times `scale`: one_source_weighted per source; with nthreads > 1,
+ * contiguous source blocks with private score arrays summed in thread
+ * order, as run_sources does.
+ */
+int or_bc_weighted(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, const int32_t *wt,
+                   const int32_t *src, int32_t k, double scale, double *bc, int32_t nthreads) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (m > 0 && (!wt || !weights_ok(m, wt))) return OR_E_INVALID_GRAPH;
+    if ((st = check_sources(n, src, k)) != OR_OK) return st;
+    if (n > 0 && !bc) return OR_E_INVALID_ARG;
+    for (int32_t i = 0; i < n; ++i) bc[i] = 0.0;
+    if (n == 0 || k == 0) return OR_OK;
+    graph_t g = {n, rowptr, colidx};
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > k) nthreads = k;
+    wjob_t *jobs = (wjob_t *)calloc((size_t)nthreads, sizeof(wjob_t));
+    double *part = (double *)calloc((size_t)nthreads * (size_t)n, sizeof(double));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !part || !th) { free(jobs); free(part); free(th); return OR_E_NO_MEMORY; }
+    for (int32_t t = 0; t < nthreads; ++t) {
+        jobs[t].g = &g;
+        jobs[t].wt = wt;
+        jobs[t].src = src;
+        jobs[t].lo = (int32_t)((int64_t)k * t / nthreads);
+        jobs[t].hi = (int32_t)((int64_t)k * (t + 1) / nthreads);
+        jobs[t].m = m;
+        jobs[t].bc = part + (size_t)t * (size_t)n;
+        if (nthreads == 1) run_wjob(&jobs[t]);
+        else pthread_create(&th[t], NULL, run_wjob, &jobs[t]);
+    }
+    st = OR_OK;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        if (nthreads > 1) pthread_join(th[t], NULL);
+        if (jobs[t].status != OR_OK) st = jobs[t].status;
+    }
+    for (int32_t t = 0; t < nthreads; ++t)
+        for (int32_t i = 0; i < n; ++i) bc[i] += part[(size_t)t * (size_t)n + i];
+    free(jobs); free(part); free(th);
     if (st == OR_OK && scale != 1.0)
         for (int32_t i = 0; i < n; ++i) bc[i] *= scale;
     return st;

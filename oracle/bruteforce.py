@@ -125,3 +125,37 @@ def edge_betweenness(rowptr, colidx):
             for a, b in zip(p[:-1], p[1:]):
                 out[(min(a, b), max(a, b))] += Fraction(1, len(ps))
     return out
+
+
+def brute_force_weighted(rowptr, colidx, weights):
+    """(d, sigma, bc) with arc weights: every simple s-t path is listed, the
+    minimum weight sum is d(s, t), the paths reaching it are the shortest
+    ones; bc[v] over ordered pairs as exact Fractions."""
+    n = len(rowptr) - 1
+    adj = [[(int(colidx[e]), int(weights[e])) for e in range(int(rowptr[v]), int(rowptr[v + 1]))] for v in range(n)]
+    d = [[-1] * n for _ in range(n)]
+    sigma = [[0] * n for _ in range(n)]
+    bc = [Fraction(0)] * n
+    for s in range(n):
+        d[s][s] = 0
+        sigma[s][s] = 1
+        found = {t: [] for t in range(n)}
+        stack = [(s, (s,), 0, {s})]
+        while stack:
+            v, p, wsum, seen = stack.pop()
+            if v != s:
+                found[v].append((wsum, p))
+            for x, w in adj[v]:
+                if x not in seen:
+                    stack.append((x, p + (x,), wsum + w, seen | {x}))
+        for t in range(n):
+            if t == s or not found[t]:
+                continue
+            best = min(ws for ws, _ in found[t])
+            ps = [p for ws, p in found[t] if ws == best]
+            d[s][t] = best
+            sigma[s][t] = len(ps)
+            for p in ps:
+                for v in p[1:-1]:
+                    bc[v] += Fraction(1, len(ps))
+    return d, sigma, bc

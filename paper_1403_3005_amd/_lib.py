@@ -32,7 +32,7 @@ NK_E_INTERNAL = -8
 
 EXPORTS = [
     "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
-    "nk_bc_sources_linear", "nk_bc_sources_bisect", "nk_bc_directed", "nk_transpose", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
+    "nk_bc_sources_linear", "nk_bc_sources_bisect", "nk_bc_directed", "nk_bc_weighted", "nk_transpose", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
@@ -74,6 +74,7 @@ def load():
         "nk_bc_sources_bisect": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_bc_directed": (c.c_int32, [vp, vp, vp, vp, c.c_int32, c.c_int64, vp, c.c_int32, c.c_double, vp, vp]),
         "nk_transpose": (c.c_int32, g + [vp, vp, vp]),
+        "nk_bc_weighted": (c.c_int32, [vp, vp, vp, c.c_int32, c.c_int64, vp, c.c_int32, c.c_double, vp, vp]),
         "nk_edge_bc": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp, vp]),
         "nk_closeness": (c.c_int32, g + [vp, vp]),
         "nk_closeness_sampled": (c.c_int32, g + [vp, c.c_int32, vp, vp]),
@@ -199,6 +200,23 @@ def nk_bc_sources_bisect(rowptr, colidx, sources=None, scale: float = 1.0, bc=No
         sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
     _check(load().nk_bc_sources_bisect(rp, ci, n, m, sp, k, float(scale), _dev(bc, torch.float64, "bc"),
                                        _stream(stream)))
+    return bc
+
+
+def nk_bc_weighted(rowptr, colidx, weights, sources=None, scale: float = 1.0, bc=None, stream=None):
+    """Betweenness with int32 arc weights >= 1 over `sources` (None: every
+    vertex) times `scale`; rowptr/colidx are out-arcs."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if bc is None:
+        bc = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    if sources is None:
+        k, sp = n, ctypes.c_void_p(0)
+    else:
+        k = sources.numel()
+        sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
+    wp = _dev(weights, torch.int32, "weights") if m > 0 else ctypes.c_void_p(0)
+    _check(load().nk_bc_weighted(rp, ci, wp, n, m, sp, k, float(scale), _dev(bc, torch.float64, "bc"),
+                                 _stream(stream)))
     return bc
 
 

@@ -325,7 +325,9 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         hipFuncAttributes attr;
         NK_HIP(hipFuncGetAttributes(&attr, probe.fn));
         // pair mode keeps two visited bitmaps (one per search side) in global memory
-        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1) && mode != kModePair;
+        // (the weighted mode keeps no visited bitmap)
+        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1) && mode != kModePair &&
+              mode != kModeWeighted;
     }
     KernelRef kr = brandes_kernel(mode, block, lds);
     size_t dyn = lds ? bm_bytes : 0;
@@ -345,8 +347,9 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         // pair sampling: 32-byte records, 8 (weights) and 6 x 4 (two sides'
         // lists) + 4 (meeting list); otherwise 8 + 8 + 7 x 4 and a global
         // bitmap when it does not sit in LDS
-        size_t per_slot = (size_t)stride * (mode == kModePair ? 68 : 44);
-        if (mode != kModePair && !lds) per_slot += (size_t)wordsr * 4;
+        // weighted: + u64 distances, round marks and two worklists (20)
+        size_t per_slot = (size_t)stride * (mode == kModePair ? 68 : mode == kModeWeighted ? 64 : 44);
+        if (mode != kModePair && mode != kModeWeighted && !lds) per_slot += (size_t)wordsr * 4;
         size_t avail;
         if (t.scratch_mib > 0) {
             avail = (size_t)t.scratch_mib << 20;
@@ -428,6 +431,9 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     p.bmg = nullptr;
     p.pair_rec = nullptr;
     p.lv2 = p.la2 = p.ld2 = nullptr;
+    p.dist = nullptr;
+    p.mark = nullptr;
+    p.wl0 = p.wl1 = nullptr;
     if ((st = scr.get(cells, &p.dacc)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
@@ -450,8 +456,16 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
         if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.d)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
-        if (!plan.lds)
+        if (plan.mode == kModeWeighted) {
+            if ((st = scr.get(cells, &p.dist)) != NK_OK) return st;
+            if ((st = scr.get(cells, &p.mark)) != NK_OK) return st;
+            if ((st = scr.get(cells, &p.wl0)) != NK_OK) return st;
+            if ((st = scr.get(cells, &p.wl1)) != NK_OK) return st;
+            NK_HIP(launch_fill_u64(p.dist, ~0ULL, cells, s));
+            NK_HIP(launch_fill_i32(p.mark, -1, cells, s));
+        } else if (!plan.lds) {
             if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
+        }
         NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
         // the push accumulator of the dependency sweep must start at zero
         if (plan.mode == kModeBC || plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
@@ -750,6 +764,56 @@ nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int
         return fail(NK_E_INVALID_ARG, "give both in-arc arrays or neither");
     const DirectedArgs dir = {trowptr, tcolidx};
     return bc_sources_impl(rowptr, colidx, n, m, sources, k, scale, bc, stream, kEstPlain, nullptr, &dir);
+}
+
+nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int32_t *weights, int32_t n,
+                         int64_t m, const int32_t *sources, int32_t k, double scale, double *bc, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = check_graph_args(rowptr, colidx, n, m);
+    if (st != NK_OK) return st;
+    if (n == 0) return NK_OK;
+    if (!bc) return fail(NK_E_INVALID_ARG, "bc is NULL");
+    if (m > 0 && !weights) return fail(NK_E_INVALID_ARG, "weights is NULL");
+    if (k < 0) return fail(NK_E_INVALID_ARG, "k is negative");
+    if (k > 0 && !sources && k != n) return fail(NK_E_INVALID_ARG, "sources is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    DevStatus *dst;
+    if ((st = scr.get(1, &dst)) != NK_OK) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    NK_HIP(launch_status_init(dst, s));
+    NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
+    if (m > 0) NK_HIP(launch_validate_weights(weights, m, dst, s));
+    NK_HIP(launch_fill_f64(bc, 0.0, n, s));
+    LaunchPlan plan = {};
+    float ms = 0.0f;
+    if (k > 0) {
+        // the graph keeps its ids: the weights are indexed by arc
+        if ((st = plan_launch(kModeWeighted, n, k, 0, &plan)) != NK_OK) return st;
+        Params p;
+        memset(&p, 0, sizeof(p));
+        p.rowptr = rowptr;
+        p.colidx = colidx;
+        p.n = n;
+        p.m = (int32_t)m;
+        p.ntasks = k;
+        p.sources = sources;
+        p.bc = bc;
+        p.st = dst;
+        p.wts = weights;
+        hipEvent_t ev0, ev1;
+        if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+        if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
+        if (scale != 1.0) NK_HIP(launch_scale_f64(bc, scale, n, s));
+        st = finish(dst, h, s);
+        NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    } else {
+        st = finish(dst, h, s);
+    }
+    stats_record(*h, plan.grid, plan.block, 0, ms);
+    return st;
 }
 
 nk_status nk_transpose(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *trowptr,

@@ -15,7 +15,8 @@ enum Mode : int {
     kModeSSSP = 1,  // forward only, d and sigma written out per task
     kModePair = 2,  // one sampled pair: bidirectional search and path walk
     kModeClose = 3,  // forward with unit path counts; distance sums for closeness
-    kModeBisect = 4  // betweenness with the bisection estimator (keeps distances)
+    kModeBisect = 4,  // betweenness with the bisection estimator (keeps distances)
+    kModeWeighted = 5  // betweenness over positive integer arc weights
 };
 
 // Everything a persistent launch reads.  Per-slot scratch arrays hold
@@ -79,6 +80,14 @@ struct Params {
     double *ebc;
     const int32_t *trowptr;
     const int32_t *tcolidx;
+    // weighted mode (single graph, out-arcs): arc weights >= 1; per-slot
+    // distances (u64, all-ones = unreached between sources), worklist
+    // membership epochs and two worklists
+    const int32_t *wts;
+    unsigned long long *dist;
+    int32_t *mark;
+    int32_t *wl0;
+    int32_t *wl1;
     // pair mode: 32-byte per-vertex records of both search sides (path
     // counts and distances from u and from v; `stride` records per slot)
     // and the level lists of the side grown from the target
@@ -121,6 +130,7 @@ hipError_t launch_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso, hi
 hipError_t launch_fill_f64(double *p, double v, long long count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, long long count, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, long long count, hipStream_t s);
+hipError_t launch_validate_weights(const int32_t *wts, long long m, DevStatus *st, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, hipStream_t s);
 hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);

@@ -63,6 +63,9 @@ struct GView {
 };
 
 struct Scr {
+    unsigned long long *dist;   // weighted mode: distances (all-ones = unreached)
+    int32_t *mark;              // weighted mode: round that last queued the vertex
+    int32_t *wl0, *wl1;         // weighted mode: worklists of the distance rounds
     unsigned long long *sigma;  // path counts; coef bits during the backward phase
     double *dacc;               // push-mode dependency sums (kept at zero between uses)
     int32_t *ldeg;              // degree sum of each level
@@ -613,6 +616,258 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     }
 }
 
+// --------------------------------------------------------------- weighted --
+//
+// Positive integer arc weights.  Per source: (1) distances by label-
+// correcting rounds: each round relaxes the out-arcs of the vertices whose
+// distance dropped in the previous round (64-bit atomicMin), queueing each
+// improved vertex once per round; (2) the shortest-path DAG (arcs with
+// dist_v + w = dist_x): in-degrees, then Kahn layers -- a vertex joins the
+// layer after the one holding its last predecessor, and each layer pushes
+// its path counts to its DAG successors -- so every DAG arc goes from a
+// layer to a later one; (3) the dependency pull over the layers in reverse
+// with the DAG test by distances.
+
+constexpr unsigned long long kInf = ~0ULL;
+
+// Stages list[tb, tb+cnt) (vertex ids) with their out-arc ranges.
+template <int BLOCK>
+__device__ __forceinline__ int32_t stage_ids(Tile<BLOCK> &sm, const int32_t *list, const GView &g, int32_t tb,
+                                             int32_t cnt) {
+    const int tid = threadIdx.x;
+    int32_t dg = 0;
+    if (tid < cnt) {
+        const int32_t v = list[tb + tid];
+        const int32_t a0 = g.rp[v];
+        sm.v[tid] = v;
+        sm.a0[tid] = a0;
+        dg = g.rp[v + 1] - a0;
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+    if (tid < cnt) sm.pre[tid] = ex;
+    if (tid == 0) sm.pre[cnt] = total;
+    return total;
+}
+
+// Distances from src; returns the number of reached vertices, listed in
+// s.cand.  ep: the workgroup's round counter (never repeats in a launch).
+template <int BLOCK>
+__device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
+                               int32_t &ep, unsigned long long *sd, Counters &c) {
+    const int tid = threadIdx.x;
+    __shared__ int32_t s_reach, s_next;
+    if (tid == 0) {
+        s.dist[src] = 0ULL;
+        s.cand[0] = src;
+        s.wl0[0] = src;
+        s_reach = 1;
+    }
+    __syncthreads();
+    int32_t cur = 0, ncur = 1;
+    for (;;) {
+        ++ep;
+        const int32_t *in = cur == 0 ? s.wl0 : s.wl1;
+        int32_t *out = cur == 0 ? s.wl1 : s.wl0;
+        if (tid == 0) {
+            s_next = 0;
+            c.td++;
+        }
+        __syncthreads();
+        for (int32_t tb = 0; tb < ncur; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, ncur - tb);
+            const int32_t total = stage_ids<BLOCK>(sm, in, g, tb, cnt);
+            if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
+            __syncthreads();
+            if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                int32_t kk[kChunk], w[kChunk];
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    bool first = false, queue = false;
+                    if (kk[j] >= 0) {
+                        const int32_t k = kk[j];
+                        const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
+                        const unsigned long long nd = sd[k] + (unsigned long long)p.wts[arc];
+                        if (nd < s.dist[w[j]]) {
+                            const unsigned long long old = atomicMin(&s.dist[w[j]], nd);
+                            if (nd < old) {
+                                first = old == kInf;
+                                queue = atomicExch(&s.mark[w[j]], ep) != ep;
+                            }
+                        }
+                    }
+                    wave_append(first, w[j], s.cand, &s_reach, g.n, &p.st->err);
+                    wave_append(queue, w[j], out, &s_next, g.n, &p.st->err);
+                }
+            }
+            __syncthreads();
+        }
+        const int32_t nn = s_next;
+        __syncthreads();
+        if (nn == 0) break;
+        cur ^= 1;
+        ncur = nn;
+    }
+    return s_reach;
+}
+
+// Shortest-path DAG layers from src over the reached vertices (s.cand[0,
+// nreach)): path counts into s.sigma, layers into s.lv/la/ld with offsets
+// s.lvl; s.d holds DAG in-degrees.  Returns the deepest layer.
+template <int BLOCK>
+__device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
+                            int32_t nreach, unsigned long long *sd, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t i = tid; i < nreach; i += BLOCK) s.d[s.cand[i]] = 0;
+    __syncthreads();
+    // DAG in-degrees
+    for (int32_t tb = 0; tb < nreach; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, nreach - tb);
+        const int32_t total = stage_ids<BLOCK>(sm, s.cand, g, tb, cnt);
+        if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
+        __syncthreads();
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            int32_t kk[kChunk], w[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                if (kk[j] < 0) continue;
+                const int32_t k = kk[j];
+                const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
+                if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
+                    atomicAdd(&s.d[w[j]], 1);
+                    c.dag++;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int32_t a0 = g.rp[src];
+        s.sigma[src] = 1ULL;
+        s.lv[0] = src;
+        s.la[0] = a0;
+        s.ld[0] = g.rp[src + 1] - a0;
+        s.lvl[0] = 0;
+        s.lvl[1] = 1;
+    }
+    __syncthreads();
+    int32_t lo = 0, hi = 1, L = 0;
+    for (;;) {
+        if (tid == 0) {
+            sm.count = 0;
+            c.bu++;
+        }
+        __syncthreads();
+        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, hi - tb);
+            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+            if (tid < cnt) {
+                sd[tid] = s.dist[sm.v[tid]];
+                sm.val.u[tid] = s.sigma[sm.v[tid]];
+            }
+            __syncthreads();
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                int32_t kk[kChunk], w[kChunk];
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    bool ready = false;
+                    if (kk[j] >= 0) {
+                        const int32_t k = kk[j];
+                        const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
+                        if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
+                            const unsigned long long add = sm.val.u[k];
+                            const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
+                            if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
+                            ready = atomicSub(&s.d[w[j]], 1) == 1;
+                        }
+                    }
+                    const int32_t pos = wave_append_pos(ready, w[j], s.lv + hi, &sm.count, g.n - hi, &p.st->err);
+                    if (pos >= 0) {
+                        const int32_t a0 = g.rp[w[j]];
+                        s.la[hi + pos] = a0;
+                        s.ld[hi + pos] = g.rp[w[j] + 1] - a0;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int32_t nnew = sm.count < g.n - hi ? sm.count : g.n - hi;
+        if (tid == 0) s.lvl[L + 2] = hi + nnew;
+        __syncthreads();
+        if (nnew == 0) break;
+        lo = hi;
+        hi += nnew;
+        ++L;
+    }
+    return L;
+}
+
+// Dependencies over the layers in reverse: delta_v = sigma_v * sum over DAG
+// successors x of (1 + delta_x) / sigma_x, kept as coefficients in place
+// of sigma; bc[v] += delta_v for every layer but the source's.
+template <int BLOCK>
+__device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t Ld, double *bcg,
+                           unsigned long long *sd, Counters &c) {
+    const int tid = threadIdx.x;
+    if (Ld == 0) return;
+    for (int32_t i = s.lvl[Ld] + tid; i < s.lvl[Ld + 1]; i += BLOCK) {
+        const int32_t v = s.lv[i];
+        s.sigma[v] = as_u64(1.0 / (double)s.sigma[v]);
+    }
+    __syncthreads();
+    for (int32_t l = Ld - 1; l >= 1; --l) {
+        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
+        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, hi - tb);
+            if (tid < cnt) sm.val.f[tid] = 0.0;
+            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+            if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
+            __syncthreads();
+            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                int32_t kk[kChunk], w[kChunk];
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                double cf[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    cf[j] = 0.0;
+                    if (kk[j] >= 0) {
+                        const int32_t k = kk[j];
+                        const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
+                        if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) cf[j] = as_f64(s.sigma[w[j]]);
+                    }
+                }
+                int32_t kcur = kk[0];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    if (kk[j] < 0) continue;
+                    if (kk[j] != kcur) {
+                        if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                        kcur = kk[j];
+                        acc = 0.0;
+                    }
+                    acc += cf[j];
+                }
+                if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+            }
+            __syncthreads();
+            if (tid < cnt) {
+                const int32_t v = sm.v[tid];
+                const double sg = (double)s.sigma[v];
+                const double delta = sg * sm.val.f[tid];
+                s.sigma[v] = as_u64((1.0 + delta) / sg);
+                if (delta != 0.0) atomicAdd(bcg + v, delta);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // --------------------------------------------------------------- path walk --
 
 // Block-scope state of one bidirectional search (side 0 grows from u,
@@ -1012,6 +1267,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.ld = p.ld + off;
     s.lvl = MODE == kModePair ? nullptr : p.lvl + off;
     s.cand = p.cand + off;
+    s.dist = p.dist ? p.dist + off : nullptr;
+    s.mark = p.mark ? p.mark + off : nullptr;
+    s.wl0 = p.wl0 ? p.wl0 + off : nullptr;
+    s.wl1 = p.wl1 ? p.wl1 + off : nullptr;
     uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists
@@ -1031,6 +1290,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     }
     __syncthreads();
     const long long t_kernel = clock64();
+    int32_t ep = 0;                                   // weighted mode: round counter
+    __shared__ unsigned long long wsd[MODE == kModeWeighted ? BLOCK : 1];   // distances of staged vertices
+    (void)ep;
+    (void)wsd;
     for (;;) {
         if (tid == 0) sm.task = (long long)atomicAdd(&p.st->head, 1ULL);
         __syncthreads();
@@ -1095,6 +1358,29 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             bidir_sample<BLOCK>(p, sm, bs, rec, s, s2, g, src, target, j, task, c);
             if (tid == 0) c.tasks++;
             phase_end<BLOCK>(sm, kPhTd);
+            continue;
+        } else if constexpr (MODE == kModeWeighted) {
+            phase_start<BLOCK>(sm);
+            const int32_t nreach = w_distances<BLOCK>(p, sm, s, g, src, ep, wsd, c);
+            phase_end<BLOCK>(sm, kPhTd);
+            phase_start<BLOCK>(sm);
+            const int32_t Ld = w_layers<BLOCK>(p, sm, s, g, src, nreach, wsd, c);
+            phase_end<BLOCK>(sm, kPhBu);
+            phase_start<BLOCK>(sm);
+            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, wsd, c);
+            phase_end<BLOCK>(sm, kPhPull);
+            phase_start<BLOCK>(sm);
+            for (int32_t i = tid; i < nreach; i += BLOCK) {
+                const int32_t v = s.cand[i];
+                s.sigma[v] = 0ULL;
+                s.dist[v] = kInf;
+            }
+            if (tid == 0) {
+                c.reached += (unsigned long long)nreach;
+                c.tasks++;
+            }
+            __syncthreads();
+            phase_end<BLOCK>(sm, kPhReset);
             continue;
         } else {
 
@@ -1189,6 +1475,7 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
         case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
         case kModeClose: return ref_mode<kModeClose>(block, bitmap_in_lds);
         case kModeBisect: return ref_mode<kModeBisect>(block, bitmap_in_lds);
+        case kModeWeighted: return ref_mode<kModeWeighted>(block, bitmap_in_lds);
         default: return ref_mode<kModeBC>(block, bitmap_in_lds);
     }
 }
@@ -1245,6 +1532,13 @@ __global__ void k_validate_strict(const int32_t *rowptr, const int32_t *colidx, 
         }
     }
     if (bad) atomicOr(&st->err, kErrGraph);
+}
+
+__global__ void k_validate_weights(const int32_t *wts, long long m, DevStatus *st) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) bad |= wts[e] < 1;
+    if (__ballot(bad) != 0ULL && lane_id() == 0) atomicOr(&st->err, kErrGraph);
 }
 
 __global__ void k_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso) {
@@ -1382,6 +1676,10 @@ hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_
 }
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s) {
     hipLaunchKernelGGL(k_counts_to_bc, dim3(grid_for(count, 256)), dim3(256), 0, s, counts, bc, scale, count);
+    return hipGetLastError();
+}
+hipError_t launch_validate_weights(const int32_t *wts, long long m, DevStatus *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, wts, m, st);
     return hipGetLastError();
 }
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s) {
