@@ -108,3 +108,29 @@ def test_batched_c4_sized_graphs():
     got = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
     for i, g in enumerate(graphs):
         assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx, nthreads=8), f"graph {i}")
+
+
+def test_rmat20_directed_sampled_vs_oracle():
+    """The directed benchmark graph (R-MAT-20 draws as arcs, 16.1M arcs) with
+    its device-built in-arc CSR, in the benchmark's launch form: the first 6
+    benchmark sources against the oracle."""
+    g = gg.directed_rmat(20, 16, 2)
+    src = gg.sample_sources(g.n, 4096, 2)
+    rp, ci = upload(g)
+    trp, tci = nk.nk_transpose(rp, ci)
+    nk.nk_set_tuning()
+    few = src[:6]
+    got = nk.nk_bc_directed(rp, ci, ivec(few), g.n / 4096, trp, tci).cpu().numpy()
+    assert_scores_close(got, oracle.bc_directed(g.rowptr, g.colidx, few, g.n / 4096, nthreads=6), "drmat20")
+
+
+def test_rmat20_weighted_sampled_vs_oracle(rmat20):
+    """The weighted benchmark workload (R-MAT-20, edge weights 1..64): the
+    first 6 benchmark sources against the oracle's Dijkstra Brandes."""
+    g, src, rp, ci = rmat20
+    w = gg.edge_weights(g, 64, 2)
+    wt = torch.from_numpy(w).to("cuda:0")
+    nk.nk_set_tuning()
+    few = src[:6]
+    got = nk.nk_bc_weighted(rp, ci, wt, ivec(few), g.n / 4096).cpu().numpy()
+    assert_scores_close(got, oracle.bc_weighted(g.rowptr, g.colidx, w, few, g.n / 4096, nthreads=6), "wrmat20")
