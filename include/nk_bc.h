@@ -335,6 +335,8 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
  *           between the all-in-LDS kernel and the LDS-bitmap kernel
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
  *   out[12] dependency-sweep levels run by push   out[13..15] reserved
+ *   (nk_bc_weighted: out[2] arcs relaxed in the distance rounds, out[5]
+ *   distance rounds, out[6] shortest-path DAG layers, out[4] DAG arcs)
  *   out[16..23] shader-clock cycles per phase, summed over workgroups:
  *           task set-up, top-down levels, bottom-up levels, level marking,
  *           pull levels, push levels, path-count reset, everything else

@@ -15,7 +15,7 @@ enum Mode : int {
     kModeSSSP = 1,  // forward only, d and sigma written out per task
     kModePair = 2,  // one sampled pair: bidirectional search and path walk
     kModeClose = 3,  // forward with unit path counts; distance sums for closeness
-    kModeBisect = 4,  // betweenness with the bisection estimator (keeps distances)
+    kModeBisect = 4,  // betweenness with the bisection estimator
     kModeWeighted = 5  // betweenness over positive integer arc weights
 };
 

@@ -181,7 +181,7 @@ __device__ void td_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
                 if (act[j]) {
                     c.dag++;
                     if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
-                    if ((MODE == kModeSSSP || MODE == kModeBisect) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
+                    if ((MODE == kModeSSSP) && old[j] == 0ULL) s.d[w[j]] = lvl + 1;
                 }
                 wave_append(act[j] && old[j] == 0ULL, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
             }
@@ -293,7 +293,7 @@ __device__ void bu_level(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
                     wd = go.rp[w + 1] - wa;
                 }
                 s.sigma[w] = sum;
-                if (MODE == kModeSSSP || MODE == kModeBisect) s.d[w] = lvl + 1;
+                if (MODE == kModeSSSP) s.d[w] = lvl + 1;
                 fresh = true;
             }
         }
@@ -338,7 +338,7 @@ __device__ int32_t forward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const
     if (tid == 0) {
         bm[src >> 5] |= 1u << (src & 31);
         s.sigma[src] = 1ULL;
-        if (MODE == kModeSSSP || MODE == kModeBisect) s.d[src] = 0;
+        if (MODE == kModeSSSP) s.d[src] = 0;
         const int32_t a0 = g.rp[src];
         const int32_t dsrc = g.rp[src + 1] - a0;
         s.lv[0] = src;
@@ -511,13 +511,18 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // only targets at depth <= T.  A vertex on level l takes half of
 // delta^(2l-1) and half of delta^(2l), so this sweep serves level
 // ceil(T/2) only and runs from level T-1 up to it.  The targets' inverse
-// path counts and then (1 + delta^T) / sigma sit in dacc; a neighbour
-// belongs to the level below exactly when its distance says so (other
-// vertices' dacc entries are zero).  The sweep clears what it wrote.
+// path counts and then (1 + delta^T) / sigma sit in dacc (zero elsewhere).
+// As in the full sweep, the visited bitmap tells the level below: on
+// entry every reached level is marked; levels T.. are cleared first and
+// each processed level after its pass, so an unmarked neighbour of level
+// j is on level j+1.  On exit dacc is clear and every level is marked
+// again.
 template <int BLOCK>
-__device__ void bis_sweep(Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t T, double *bcg, Counters &c) {
+__device__ void bis_sweep(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g, int32_t T, int32_t Ld,
+                          double *bcg, Counters &c) {
     const int tid = threadIdx.x;
     const int32_t lmin = (T + 1) / 2;
+    for (int32_t i = s.lvl[T] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_clear(bm, s.lv[i]);
     for (int32_t i = s.lvl[T] + tid; i < s.lvl[T + 1]; i += BLOCK) {
         const int32_t w = s.lv[i];
         s.dacc[w] = 1.0 / (double)s.sigma[w];
@@ -536,7 +541,7 @@ __device__ void bis_sweep(Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t
                 load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
                 double cf[kChunk];
 #pragma unroll
-                for (int j = 0; j < kChunk; ++j) cf[j] = (kk[j] >= 0 && s.d[w[j]] == l + 1) ? s.dacc[w[j]] : 0.0;
+                for (int j = 0; j < kChunk; ++j) cf[j] = (kk[j] >= 0 && !bit_test(bm, w[j])) ? s.dacc[w[j]] : 0.0;
                 int32_t kcur = kk[0];
                 double acc = 0.0;
 #pragma unroll
@@ -563,8 +568,11 @@ __device__ void bis_sweep(Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t
             }
             __syncthreads();
         }
+        for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
+        __syncthreads();
     }
     for (int32_t i = s.lvl[lmin + 1] + tid; i < s.lvl[T + 1]; i += BLOCK) s.dacc[s.lv[i]] = 0.0;
+    for (int32_t i = s.lvl[lmin] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_set(bm, s.lv[i]);
     __syncthreads();
 }
 
@@ -577,7 +585,7 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     // sweep below overwrites with coefficients, so they run first
     if constexpr (BIS) {
         phase_start<BLOCK>(sm);
-        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, s, g, T, bcg, c);
+        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, bm, s, g, T, Ld, bcg, c);
         phase_end<BLOCK>(sm, kPhPull);
     }
     {
