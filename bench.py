@@ -305,6 +305,19 @@ def other_workload(args) -> dict:
 
         sec = _timed(run_all, args.steps, args.warmup)
         st = nk.nk_last_stats()
+        # the same batch as captured HIP graphs (one plan per launch group),
+        # replayed: the value stays the eager call's; this is reported beside it
+        plans = [nk.NkBatchPlan(*grp) for grp in groups]
+
+        def replay_all():
+            for gi, pl in enumerate(plans):
+                pl.run()
+                if len(plans) > 1:
+                    print(f"bench: replay of group {gi + 1}/{len(plans)} done", file=sys.stderr, flush=True)
+
+        sec_replay = _timed(replay_all, args.steps, 1)
+        for pl in plans:
+            pl.close()
         vtx = np.array([0, sum(g.n for g in graphs)])
         arc = np.array([0, sum(g.m for g in graphs)])
         small = sorted(graphs, key=lambda g: g.n)[:4]
@@ -318,7 +331,9 @@ def other_workload(args) -> dict:
                            "arcs_total": int(arc[-1]), "n_range": [1000, hi], "launches": len(groups),
                            "last_launch_kernel_ms": st["kernel_us"] / 1e3,
                            "kernels": PLACEMENT[st["bitmap_lds"]],
-                           "block": st["block"], "workgroups": st["workgroups"]},
+                           "block": st["block"], "workgroups": st["workgroups"],
+                           "graph_replay_ms_per_step": round(sec_replay * 1e3, 1),
+                           "graph_replay_gteps": round(work / sec_replay / 1e9, 3)},
                    cpu_baseline={"value": round(sum(g.n * g.m_undirected for g in small) / cpu / 1e9, 4),
                                  "unit": "GTEPS", "cores": 1, "kind": "oracle",
                                  "sample": "the 4 smallest graphs of the batch, exact"})

@@ -322,6 +322,32 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
                               void *stream);
 
 /*
+ * The batched run above as a captured HIP graph, for a batch that is run
+ * again and again (same graphs, same output buffer).  nk_batch_plan_create
+ * does all host work once -- argument checks, offset and schedule uploads,
+ * the split between the two kernels, kernel plans and every scratch
+ * buffer (held by the plan until it is destroyed) -- and records the run's
+ * kernels (status reset, batch validation, output clear, the two
+ * persistent launches; no memory-set or copy nodes) into a graph on a
+ * stream of its own.  nk_batch_plan_run replays it on `stream`, then reads
+ * the status (synchronises the stream): the same scores as
+ * nk_bc_exact_batched on the same batch, within the stated tolerance.
+ *   Arguments of create as nk_bc_exact_batched (HOST offset tables are
+ *   copied; rowptr_cat, colidx_cat and bc_cat must stay allocated while
+ *   the plan lives, and every run reads the graphs' current contents and
+ *   overwrites bc_cat).  *out receives the plan (NULL on error).
+ *   Runs of one plan must not overlap; a plan is bound to the device that
+ *   was current at creation (NK_E_INVALID_ARG from another).
+ * nk_batch_plan_destroy waits for the plan's own stream and releases it.
+ */
+typedef struct nk_batch_plan nk_batch_plan;
+nk_status nk_batch_plan_create(int32_t G, const int64_t *vtx_off, const int64_t *arc_off,
+                               const int32_t *rowptr_cat, const int32_t *colidx_cat, double *bc_cat,
+                               nk_batch_plan **out);
+nk_status nk_batch_plan_run(nk_batch_plan *plan, void *stream);
+void nk_batch_plan_destroy(nk_batch_plan *plan);
+
+/*
  * Statistics of the calling thread's last nk_bc_exact / nk_bc_sources /
  * nk_bc_exact_batched / pair-sampling call (HOST out[32]):
  *   out[0] sources (or samples) processed     out[1] vertices reached

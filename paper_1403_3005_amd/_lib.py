@@ -34,7 +34,8 @@ EXPORTS = [
     "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
     "nk_bc_sources_linear", "nk_bc_sources_bisect", "nk_bc_directed", "nk_bc_weighted", "nk_transpose", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
-    "nk_sample_paths", "nk_bc_exact_batched", "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
+    "nk_sample_paths", "nk_bc_exact_batched", "nk_batch_plan_create", "nk_batch_plan_run", "nk_batch_plan_destroy",
+    "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
     "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy", "nk_autotune", "nk_tuning_lookup",
 ]
@@ -85,6 +86,9 @@ def load():
         "nk_pair_counts": (c.c_int32, g + [c.c_int64, c.c_uint64, vp, vp]),
         "nk_sample_paths": (c.c_int32, g + [c.c_uint64, c.c_int64, c.c_int32, c.c_int32, vp, vp, vp, vp]),
         "nk_bc_exact_batched": (c.c_int32, [c.c_int32, i64p, i64p, vp, vp, vp, vp]),
+        "nk_batch_plan_create": (c.c_int32, [c.c_int32, i64p, i64p, vp, vp, vp, c.POINTER(vp)]),
+        "nk_batch_plan_run": (c.c_int32, [vp, vp]),
+        "nk_batch_plan_destroy": (None, [vp]),
         "nk_last_stats": (c.c_int32, [i64p]),
         "nk_set_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
         "nk_get_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
@@ -357,6 +361,46 @@ def nk_bc_exact_batched(vtx_off, arc_off, rowptr_cat, colidx_cat, stream=None):
                                       _dev(bc, torch.float64, "bc_cat") if bc.numel() else ctypes.c_void_p(0),
                                       _stream(stream)))
     return bc
+
+
+class NkBatchPlan:
+    """A batched exact run captured once into a HIP graph and replayed
+    (nk_batch_plan_* in include/nk_bc.h).  Keeps the graph tensors and its
+    output tensor alive; run() overwrites and returns the output."""
+
+    def __init__(self, vtx_off, arc_off, rowptr_cat, colidx_cat):
+        vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+        ao = np.ascontiguousarray(arc_off, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        self.bc = torch.empty(int(vo[-1]), dtype=torch.float64, device=rowptr_cat.device)
+        self._keep = (rowptr_cat, colidx_cat)
+        ci = _dev(colidx_cat, torch.int32, "colidx_cat") if colidx_cat.numel() else ctypes.c_void_p(0)
+        out = _dev(self.bc, torch.float64, "bc_cat") if self.bc.numel() else ctypes.c_void_p(0)
+        self._h = ctypes.c_void_p(0)
+        _check(load().nk_batch_plan_create(vo.shape[0] - 1, vo.ctypes.data_as(i64p), ao.ctypes.data_as(i64p),
+                                           _dev(rowptr_cat, torch.int32, "rowptr_cat"), ci, out,
+                                           ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(load().nk_batch_plan_run(self._h, _stream(stream)))
+        return self.bc
+
+    def close(self):
+        if self._h:
+            load().nk_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",

@@ -418,8 +418,7 @@ bool plan_lds(size_t dyn_bytes, int32_t n_max, long long ntasks, LaunchPlan *pla
     return true;
 }
 
-nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s) {
     const long long slots = plan.grid;
     const long long cells = slots * plan.stride;
     nk_status st;
@@ -461,20 +460,29 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
             if ((st = scr.get(cells, &p.mark)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.wl0)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.wl1)) != NK_OK) return st;
-            NK_HIP(launch_fill_u64(p.dist, ~0ULL, cells, s));
-            NK_HIP(launch_fill_i32(p.mark, -1, cells, s));
         } else if (!plan.lds) {
             if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
         }
-        NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
-        // the push accumulator of the dependency sweep must start at zero
-        if (plan.mode == kModeBC || plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
     }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;
     // a directed run without in-arcs grows every level top-down
     p.bu_ratio = (p.directed && !p.trowptr) ? 0.0f : tuning_get().bu_ratio;
     p.bw_ratio = tuning_get().bw_ratio;
+    return NK_OK;
+}
+
+nk_status persistent_enqueue(const LaunchPlan &plan, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (plan.mode != kModePair) {
+        const long long cells = (long long)plan.grid * plan.stride;
+        if (plan.mode == kModeWeighted) {
+            NK_HIP(launch_fill_u64(p.dist, ~0ULL, cells, s));
+            NK_HIP(launch_fill_i32(p.mark, -1, cells, s));
+        }
+        NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
+        // the push accumulator of the dependency sweep must start at zero
+        if (plan.mode == kModeBC || plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
+    }
     if (ev0) NK_HIP(hipEventRecord(ev0, s));
     plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);
     NK_HIP(hipGetLastError());
@@ -482,10 +490,18 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
     return NK_OK;
 }
 
+nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
+    nk_status st = persistent_alloc(plan, p, scr, s);
+    if (st != NK_OK) return st;
+    return persistent_enqueue(plan, p, s, ev0, ev1);
+}
+
 // --------------------------------------------------------- vertex diameter --
 
-// One breadth-first search from `src` (BFS mode, one workgroup): returns
-// eccentricity, lowest id at that distance and reached count.
+// Vertex-diameter bound: the maximum-degree vertex, a grid-wide sweep from
+// it, the largest component it missed, and a second sweep from the lowest
+// far vertex (info layout as nk_vd_bound).
 nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
                         hipStream_t s) {
     for (int i = 0; i < 8; ++i) info[i] = 0;
@@ -1191,11 +1207,34 @@ nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t 
     return st;
 }
 
-nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *arc_off, const int32_t *rowptr_cat,
-                              const int32_t *colidx_cat, double *bc_cat, void *stream) {
-    clear_error();
-    stats_clear();
+}  // extern "C"
+
+namespace nk {
+
+// Everything a batched exact run launches, planned on the host.
+struct BatchSetup {
+    DevStatus *dst = nullptr;
+    Params p;
+    LaunchPlan plan_s = {}, plan_l = {};
+    long long *t_small = nullptr, *t_large = nullptr;
+    int32_t *o_small = nullptr, *o_large = nullptr;
+    long long k_small = 0, k_large = 0;
+    int32_t g_small = 0, g_large = 0, n_large = 0;
+    long long *d_vtx = nullptr, *d_arc = nullptr;
+    int32_t G = 0;
+    long long nv = 0;
+    const int32_t *rowptr = nullptr, *colidx = nullptr;
+    double *bc = nullptr;
+};
+
+// Argument checks, offset and schedule uploads (synchronous), kernel plans
+// and all scratch.  nv = 0 means nothing to do.
+static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t *arc_off, const int32_t *rowptr_cat,
+                               const int32_t *colidx_cat, double *bc_cat, Scratch &scr, hipStream_t s,
+                               BatchSetup *b) {
     if (G < 0) return fail(NK_E_INVALID_ARG, "G is negative");
+    b->G = G;
+    b->nv = 0;
     if (G == 0) return NK_OK;
     if (!vtx_off || !arc_off) return fail(NK_E_INVALID_ARG, "offset tables are NULL");
     if (vtx_off[0] != 0 || arc_off[0] != 0) return fail(NK_E_INVALID_ARG, "offsets must start at 0");
@@ -1209,21 +1248,12 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
     const long long nv = vtx_off[G], na = arc_off[G];
     if (nv == 0) return NK_OK;
     if (!rowptr_cat || (na > 0 && !colidx_cat) || !bc_cat) return fail(NK_E_INVALID_ARG, "NULL graph or output");
-    hipStream_t s = (hipStream_t)stream;
-    Scratch scr;
-    DevStatus *dst;
     nk_status st;
-    if ((st = scr.get(1, &dst)) != NK_OK) return st;
-    DevStatus *h = host_status();
-    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
-    long long *d_vtx, *d_arc;
-    if ((st = scr.get(G + 1, &d_vtx)) != NK_OK) return st;
-    if ((st = scr.get(G + 1, &d_arc)) != NK_OK) return st;
-    NK_HIP(hipMemcpyAsync(d_vtx, vtx_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
-    NK_HIP(hipMemcpyAsync(d_arc, arc_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
-    NK_HIP(launch_status_init(dst, s));
-    NK_HIP(launch_validate_batched(rowptr_cat, colidx_cat, d_vtx, d_arc, G, dst, s));
-    NK_HIP(launch_fill_f64(bc_cat, 0.0, nv, s));
+    if ((st = scr.get(1, &b->dst)) != NK_OK) return st;
+    if ((st = scr.get(G + 1, &b->d_vtx)) != NK_OK) return st;
+    if ((st = scr.get(G + 1, &b->d_arc)) != NK_OK) return st;
+    NK_HIP(hipMemcpyAsync(b->d_vtx, vtx_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
+    NK_HIP(hipMemcpyAsync(b->d_arc, arc_off, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, s));
 
     // Graphs whose CSR and per-source state fit one workgroup's LDS run on
     // the all-in-LDS kernel, the others on the global-memory kernel.  Each
@@ -1241,21 +1271,21 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
         budget = di.lds_per_block > attr.sharedSizeBytes ? di.lds_per_block - attr.sharedSizeBytes : 0;
     }
     std::vector<int32_t> small, large;
-    int32_t n_large = 0, n_small = 0;
+    int32_t n_small = 0;
     for (int32_t g = 0; g < G; ++g) {
         const long long ng = vtx_off[g + 1] - vtx_off[g], mg = arc_off[g + 1] - arc_off[g];
         if (ng == 0) continue;
-        const size_t b = lds_graph_bytes((int32_t)ng, mg);
-        if (lds_ok && b <= budget) {
+        const size_t by = lds_graph_bytes((int32_t)ng, mg);
+        if (lds_ok && by <= budget) {
             small.push_back(g);
-            dyn_max = std::max(dyn_max, b);
+            dyn_max = std::max(dyn_max, by);
             n_small = std::max<int32_t>(n_small, (int32_t)ng);
         } else {
             large.push_back(g);
-            n_large = std::max<int32_t>(n_large, (int32_t)ng);
+            b->n_large = std::max<int32_t>(b->n_large, (int32_t)ng);
         }
     }
-    auto by_work = [&](int32_t a, int32_t b) { return work[a] > work[b]; };
+    auto by_work = [&](int32_t x, int32_t y) { return work[x] > work[y]; };
     std::stable_sort(small.begin(), small.end(), by_work);
     std::stable_sort(large.begin(), large.end(), by_work);
     auto tables = [&](const std::vector<int32_t> &ids, long long **d_task, int32_t **d_order,
@@ -1273,55 +1303,171 @@ nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *
         *ntasks = pre[K];
         return NK_OK;
     };
-    Params p;
-    memset(&p, 0, sizeof(p));
-    p.rowptr = rowptr_cat;
-    p.colidx = colidx_cat;
-    p.g_vtx = d_vtx;
-    p.g_arc = d_arc;
-    p.bc = bc_cat;
-    p.st = dst;
-    hipEvent_t ev0, ev1;
-    if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
-    LaunchPlan plan_s = {}, plan_l = {};
-    long long *t_small = nullptr, *t_large = nullptr;
-    int32_t *o_small = nullptr, *o_large = nullptr;
-    long long k_small = 0, k_large = 0;
+    memset(&b->p, 0, sizeof(b->p));
+    b->p.rowptr = rowptr_cat;
+    b->p.colidx = colidx_cat;
+    b->p.g_vtx = b->d_vtx;
+    b->p.g_arc = b->d_arc;
+    b->p.bc = bc_cat;
+    b->p.st = b->dst;
+    b->g_small = (int32_t)small.size();
+    b->g_large = (int32_t)large.size();
     if (!small.empty()) {
-        if ((st = tables(small, &t_small, &o_small, &k_small)) != NK_OK) return st;
-        if (!plan_lds(dyn_max, n_small, k_small, &plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
+        if ((st = tables(small, &b->t_small, &b->o_small, &b->k_small)) != NK_OK) return st;
+        if (!plan_lds(dyn_max, n_small, b->k_small, &b->plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
     }
     if (!large.empty()) {
-        if ((st = tables(large, &t_large, &o_large, &k_large)) != NK_OK) return st;
-        if ((st = plan_launch(kModeBC, n_large, k_large, 0, &plan_l)) != NK_OK) return st;
+        if ((st = tables(large, &b->t_large, &b->o_large, &b->k_large)) != NK_OK) return st;
+        if ((st = plan_launch(kModeBC, b->n_large, b->k_large, 0, &b->plan_l)) != NK_OK) return st;
+        if ((st = persistent_alloc(b->plan_l, b->p, scr, s)) != NK_OK) return st;
     }
-    NK_HIP(hipEventRecord(ev0, s));
-    if (!small.empty()) {
+    b->nv = nv;
+    b->rowptr = rowptr_cat;
+    b->colidx = colidx_cat;
+    b->bc = bc_cat;
+    return NK_OK;
+}
+
+// The run itself: kernels only (status reset, batch validation, output
+// clear, the all-in-LDS launch, the global-memory launch), so it can be
+// captured into a HIP graph.
+static nk_status batch_enqueue(const BatchSetup &b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    NK_HIP(launch_status_init(b.dst, s));
+    NK_HIP(launch_validate_batched(b.rowptr, b.colidx, b.d_vtx, b.d_arc, b.G, b.dst, s));
+    NK_HIP(launch_fill_f64(b.bc, 0.0, b.nv, s));
+    if (ev0) NK_HIP(hipEventRecord(ev0, s));
+    Params p = b.p;
+    if (b.g_small > 0) {
         p.n = 0;
-        p.G = (int32_t)small.size();
-        p.g_task = t_small;
-        p.g_order = o_small;
-        p.ntasks = k_small;
-        plan_s.kernel.launch(dim3(plan_s.grid), dim3(plan_s.block), plan_s.dyn_lds, s, p);
+        p.G = b.g_small;
+        p.g_task = b.t_small;
+        p.g_order = b.o_small;
+        p.ntasks = b.k_small;
+        b.plan_s.kernel.launch(dim3(b.plan_s.grid), dim3(b.plan_s.block), b.plan_s.dyn_lds, s, p);
         NK_HIP(hipGetLastError());
     }
-    if (!large.empty()) {
-        if (!small.empty()) NK_HIP(launch_reset_head(dst, s));
-        p.n = n_large;
-        p.G = (int32_t)large.size();
-        p.g_task = t_large;
-        p.g_order = o_large;
-        p.ntasks = k_large;
-        if ((st = launch_persistent(plan_l, p, scr, s, nullptr, nullptr)) != NK_OK) return st;
+    if (b.g_large > 0) {
+        if (b.g_small > 0) NK_HIP(launch_reset_head(b.dst, s));
+        p.n = b.n_large;
+        p.G = b.g_large;
+        p.g_task = b.t_large;
+        p.g_order = b.o_large;
+        p.ntasks = b.k_large;
+        nk_status st = persistent_enqueue(b.plan_l, p, s, nullptr, nullptr);
+        if (st != NK_OK) return st;
     }
-    NK_HIP(hipEventRecord(ev1, s));
-    st = finish(dst, h, s);
+    if (ev1) NK_HIP(hipEventRecord(ev1, s));
+    return NK_OK;
+}
+
+static void batch_stats(const BatchSetup &b, const DevStatus &h, float ms) {
+    const int where = b.g_large == 0 ? 2 : (b.g_small == 0 ? (b.plan_l.lds ? 1 : 0) : 3);
+    const LaunchPlan &shown = b.g_large == 0 ? b.plan_s : b.plan_l;
+    stats_record(h, shown.grid, shown.block, where, ms);
+}
+
+}  // namespace nk
+
+// A captured batched run (see include/nk_bc.h).
+struct nk_batch_plan {
+    int device = 0;
+    nk::Scratch *scr = nullptr;
+    nk::BatchSetup b;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+nk_status nk_bc_exact_batched(int32_t G, const int64_t *vtx_off, const int64_t *arc_off, const int32_t *rowptr_cat,
+                              const int32_t *colidx_cat, double *bc_cat, void *stream) {
+    clear_error();
+    stats_clear();
+    hipStream_t s = (hipStream_t)stream;
+    Scratch scr;
+    BatchSetup b;
+    nk_status st = batch_prepare(G, vtx_off, arc_off, rowptr_cat, colidx_cat, bc_cat, scr, s, &b);
+    if (st != NK_OK || b.nv == 0) return st;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    hipEvent_t ev0, ev1;
+    if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+    if ((st = batch_enqueue(b, s, ev0, ev1)) != NK_OK) return st;
+    st = finish(b.dst, h, s);
     float ms = 0.0f;
     NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    const int where = large.empty() ? 2 : (small.empty() ? (plan_l.lds ? 1 : 0) : 3);
-    const LaunchPlan &shown = large.empty() ? plan_s : plan_l;
-    stats_record(*h, shown.grid, shown.block, where, ms);
+    batch_stats(b, *h, ms);
     return st;
+}
+
+nk_status nk_batch_plan_create(int32_t G, const int64_t *vtx_off, const int64_t *arc_off, const int32_t *rowptr_cat,
+                               const int32_t *colidx_cat, double *bc_cat, nk_batch_plan **out) {
+    clear_error();
+    if (!out) return fail(NK_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    nk_batch_plan *pl = new nk_batch_plan();
+    pl->scr = new Scratch();
+    auto bail = [&](nk_status code) {
+        nk_batch_plan_destroy(pl);
+        return code;
+    };
+    if (hipGetDevice(&pl->device) != hipSuccess) return bail(fail(NK_E_HIP, "hipGetDevice failed"));
+    // a stream of the library's own (default priority): capture cannot run
+    // on the legacy default stream
+    if (hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(NK_E_HIP, "stream creation failed"));
+    nk_status st = batch_prepare(G, vtx_off, arc_off, rowptr_cat, colidx_cat, bc_cat, *pl->scr, pl->cs, &pl->b);
+    if (st != NK_OK) return bail(st);
+    if (hipStreamSynchronize(pl->cs) != hipSuccess) return bail(fail(NK_E_HIP, "stream synchronisation failed"));
+    if (pl->b.nv > 0) {
+        if (hipStreamBeginCapture(pl->cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bail(fail(NK_E_HIP, "stream capture did not start"));
+        st = batch_enqueue(pl->b, pl->cs, nullptr, nullptr);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(pl->cs, &g);
+        pl->graph = g;
+        if (st != NK_OK) return bail(st);
+        if (e != hipSuccess || !g) return bail(fail(NK_E_HIP, "stream capture failed"));
+        if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess)
+            return bail(fail(NK_E_HIP, "graph instantiation failed"));
+    }
+    *out = pl;
+    return NK_OK;
+}
+
+nk_status nk_batch_plan_run(nk_batch_plan *plan, void *stream) {
+    clear_error();
+    stats_clear();
+    if (!plan) return fail(NK_E_INVALID_ARG, "plan is NULL");
+    if (plan->b.nv == 0) return NK_OK;
+    int dev = 0;
+    NK_HIP(hipGetDevice(&dev));
+    if (dev != plan->device) return fail(NK_E_INVALID_ARG, "plan was made on device %d, current is %d", plan->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    DevStatus *h = host_status();
+    if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
+    hipEvent_t ev0, ev1;
+    nk_status st;
+    if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+    NK_HIP(hipEventRecord(ev0, s));
+    NK_HIP(hipGraphLaunch(plan->exec, s));
+    NK_HIP(hipEventRecord(ev1, s));
+    st = finish(plan->b.dst, h, s);
+    float ms = 0.0f;
+    NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    batch_stats(plan->b, *h, ms);
+    return st;
+}
+
+void nk_batch_plan_destroy(nk_batch_plan *plan) {
+    if (!plan) return;
+    if (plan->cs) (void)hipStreamSynchronize(plan->cs);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->cs) (void)hipStreamDestroy(plan->cs);
+    delete plan->scr;
+    delete plan;
 }
 
 }  // extern "C"

@@ -119,6 +119,14 @@ bool plan_lds(size_t dyn_bytes, int32_t n_max, long long ntasks, LaunchPlan *pla
 // recording HIP events around it when ev0/ev1 are non-null.
 nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s, hipEvent_t ev0,
                             hipEvent_t ev1);
+// The two halves of launch_persistent: persistent_alloc takes the scratch
+// and fills the scratch fields of `p` (it enqueues nothing, except in pair
+// mode the fill of a record block that is not clean); persistent_enqueue
+// clears what the kernel expects clear and launches it -- kernels only, so
+// a non-pair launch can be captured into a HIP graph and replayed.
+nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s);
+nk_status persistent_enqueue(const LaunchPlan &plan, const Params &p, hipStream_t s, hipEvent_t ev0,
+                             hipEvent_t ev1);
 
 // Copies the status block to the host, synchronises `s` and maps error bits
 // to a status code.
