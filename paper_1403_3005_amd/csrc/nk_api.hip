@@ -691,11 +691,17 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     } else if (k > 0) {
         where = -1;
         Relabeled g = {rowptr, colidx, nullptr, nullptr};
-        // edge scores are kept per arc of the caller's CSR, so that run keeps
-        // its ids; a directed run keeps them too (one renaming would have to
-        // cover both arc arrays)
-        if (!ebc && !dir)
+        // a directed run keeps its ids (one renaming would have to cover
+        // both arc arrays)
+        if (!dir)
             if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        // edge scores of a relabelled run go to the relabelled arc order
+        // first, then back to the caller's
+        double *ebc_run = ebc;
+        if (ebc && g.perm) {
+            if ((st = scr.get(m > 0 ? m : 1, &ebc_run)) != NK_OK) return st;
+            NK_HIP(launch_fill_f64(ebc_run, 0.0, m, s));
+        }
         // vertices no search can reach: no arcs (undirected) or no in-arcs
         // (directed; unknown without the in-arc CSR)
         if (dir)
@@ -726,7 +732,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
         p.iso = iso;
         p.st = dst;
         p.linear = est == kEstLinear;
-        p.ebc = ebc;
+        p.ebc = ebc_run;
         p.directed = dir != nullptr;
         p.trowptr = dir ? dir->trp : nullptr;
         p.tcolidx = dir ? dir->tci : nullptr;
@@ -737,6 +743,7 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
             NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
         else if (scale != 1.0)
             NK_HIP(launch_scale_f64(bc, scale, n, s));
+        if (ebc && g.perm) NK_HIP(launch_arcs_back(ebc_run, g.rowptr, g.inv, rowptr, n, ebc, s));
         if (ebc) NK_HIP(launch_edge_symmetrize(rowptr, colidx, n, ebc, scale, dst, s));
         st = finish(dst, h, s);
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));

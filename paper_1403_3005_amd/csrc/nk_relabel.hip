@@ -70,6 +70,19 @@ __global__ void k_gather_u32(const uint32_t *in, const int32_t *perm, int32_t n,
     for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) out[v] = in[perm[v]];
 }
 
+// Per-arc values of the relabelled CSR back to the caller's arc order: the
+// relabelling keeps each adjacency list's order, so arc j of internal
+// vertex i is arc j of original vertex inv[i].  One wave per vertex.
+__global__ void k_arcs_back(const double *in, const int32_t *rp_new, const int32_t *inv, const int32_t *rowptr,
+                            int32_t n, double *out) {
+    const long long waves = (long long)gridDim.x * (blockDim.x / kWave);
+    const int lane = lane_id();
+    for (long long i = (long long)blockIdx.x * (blockDim.x / kWave) + wave_id(); i < n; i += waves) {
+        const int32_t a = rp_new[i], b = rp_new[i + 1], o = rowptr[inv[i]];
+        for (int32_t j = lane; j < b - a; j += kWave) out[o + j] = in[a + j];
+    }
+}
+
 static unsigned grid_of(long long count, int block) {
     long long g = (count + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -119,6 +132,13 @@ hipError_t launch_map_sources(const int32_t *src, int32_t k, const int32_t *perm
 hipError_t launch_gather_scale(const double *in, const int32_t *perm, int32_t n, double scale, double *out,
                                hipStream_t s) {
     hipLaunchKernelGGL(k_gather_scale, dim3(grid_of(n, 256)), dim3(256), 0, s, in, perm, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_arcs_back(const double *in, const int32_t *rp_new, const int32_t *inv, const int32_t *rowptr,
+                            int32_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_arcs_back, dim3(grid_of((long long)n * kWave, 256)), dim3(256), 0, s, in, rp_new, inv, rowptr,
+                       n, out);
     return hipGetLastError();
 }
 

@@ -155,6 +155,8 @@ nk_status relabel_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n,
                         Scratch &scr, hipStream_t s, Relabeled *out);
 hipError_t launch_map_sources(const int32_t *src, int32_t k, const int32_t *perm, int32_t n, int32_t *out,
                               hipStream_t s);
+hipError_t launch_arcs_back(const double *in, const int32_t *rp_new, const int32_t *inv, const int32_t *rowptr,
+                            int32_t n, double *out, hipStream_t s);
 hipError_t launch_gather_scale(const double *in, const int32_t *perm, int32_t n, double scale, double *out,
                                hipStream_t s);
 hipError_t launch_gather_u32(const uint32_t *in, const int32_t *perm, int32_t n, uint32_t *out, hipStream_t s);
