@@ -436,7 +436,9 @@ nk_status nk_tuning_lookup(const char *cache_path, int32_t n, int64_t m, int64_t
  *
  * nk_server_create: hbm_budget_bytes bounds the device memory of resident
  *   graphs plus running requests; n_slots (1..16, 0 = 4) requests run at once,
- *   each on its own stream with 1/n_slots of the compute units.
+ *   each on its own stream with 1/n_slots of the workgroups the GPU can hold
+ *   at once for its kernel (fewer when that share's scratch does not fit
+ *   the budget beside the resident graphs).
  * nk_server_add_graph: copies the CSR (DEVICE pointers, same rules as above)
  *   into server memory, relabels it, computes its vertex-diameter bound.
  *   NK_E_BUDGET if it does not fit.  Not concurrent with other calls on the

@@ -337,6 +337,8 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     if (occ < 1) return fail(NK_E_INTERNAL, "kernel does not fit a compute unit (block %d, lds %zu)", block, dyn);
     if (t.wg_per_cu > 0 && t.wg_per_cu < occ) occ = t.wg_per_cu;
     long long grid = (long long)di.cus * occ;
+    // max_slots < 0: a 1/|max_slots| share of the resident-workgroup capacity
+    if (max_slots < 0) grid = std::max(1LL, grid / (-(long long)max_slots));
     if (ntasks < grid) grid = ntasks;
     if (max_slots > 0 && grid > max_slots) grid = max_slots;
     if (grid < 1) grid = 1;

@@ -54,6 +54,8 @@ struct Request {
     double *out = nullptr;         // caller's host buffer, n doubles
     long long work = 0;            // sources or samples
     size_t footprint = 0;
+    int grid = 1;                  // workgroups of its kernel (set at submission, widened at admission)
+    long long tasks = 0;           // sources or samples
     double t_submit = 0, t_start = 0, t_done = 0;
     nk_status status = NK_OK;
     bool done = false;
@@ -78,7 +80,7 @@ struct nk_server {
     size_t budget = 0;
     size_t pool_bytes = 0;       // resident graphs
     size_t running_bytes = 0;    // admitted requests
-    int grid_share = 0;          // workgroups per request kernel
+    int n_share = 1;             // a request's kernel takes 1/n_share of the resident-workgroup capacity
     std::vector<nk::ServerGraph> graphs;
     std::vector<nk::Slot> slots;
     std::deque<nk::Request *> pending;
@@ -162,7 +164,7 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
             return bail(NK_E_HIP);
         (void)launch_map_sources(src_host_dev, (int32_t)k, g.perm, n, src_int, s);
         (void)launch_fill_f64(acc, 0.0, n, s);
-        if ((st = plan_launch(kModeBC, n, k, sv->grid_share, &sl.plan)) != NK_OK) return bail(st);
+        if ((st = plan_launch(kModeBC, n, k, rq->grid, &sl.plan)) != NK_OK) return bail(st);
         Params p;
         memset(&p, 0, sizeof(p));
         p.rowptr = g.rowptr;
@@ -191,7 +193,7 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
         if ((st = scr.get(n, &res)) != NK_OK) return bail(st);
         (void)launch_fill_u32(cnt, 0u, n, s);
         if (r > 0) {
-            if ((st = plan_launch(kModePair, n, r, sv->grid_share, &sl.plan)) != NK_OK) return bail(st);
+            if ((st = plan_launch(kModePair, n, r, rq->grid, &sl.plan)) != NK_OK) return bail(st);
             Params p;
             memset(&p, 0, sizeof(p));
             p.rowptr = g.rowptr;
@@ -249,6 +251,28 @@ static void finish_request(nk_server *sv, Slot &sl) {
     sv->cv_done.notify_all();
 }
 
+// With fewer requests running than slots, a request starting now takes a
+// larger share of the GPU: 1/max(2, running + 1) of the resident-workgroup
+// capacity (half the GPU when alone, so that a second arrival still finds
+// room), if its scratch fits the budget; otherwise it keeps its
+// submission-time share.
+static void widen_grid(nk_server *sv, Request *rq, int busy) {
+    const int div = std::max(2, busy + 1);
+    if (div >= sv->n_share) return;
+    const ServerGraph &g = sv->graphs[rq->graph];
+    const bool pair = rq->sources.empty();
+    LaunchPlan pl;
+    if (plan_launch(pair ? kModePair : kModeBC, g.n, std::max<long long>(rq->tasks, 1), -div, &pl) != NK_OK) {
+        clear_error();
+        return;
+    }
+    if (pl.grid <= rq->grid) return;
+    const size_t fp = request_footprint(g, rq->tasks, pl.grid, pair);
+    if (sv->pool_bytes + sv->running_bytes + fp > sv->budget) return;
+    rq->grid = pl.grid;
+    rq->footprint = fp;
+}
+
 static void worker_main(nk_server *sv) {
     (void)hipSetDevice(sv->device);
     for (;;) {
@@ -265,6 +289,7 @@ static void worker_main(nk_server *sv) {
                 if (sv->slots[i].req) continue;
                 Request *rq = sv->pending.front();
                 if (sv->pool_bytes + sv->running_bytes + rq->footprint > sv->budget && busy > 0) break;
+                widen_grid(sv, rq, busy);
                 sv->pending.pop_front();
                 sv->running_bytes += rq->footprint;
                 sv->slots[i].req = rq;  // reserve
@@ -310,7 +335,7 @@ nk_status nk_server_create(size_t hbm_budget_bytes, int32_t n_slots, nk_server *
     nk_server *sv = new nk_server();
     sv->device = di.device;
     sv->budget = hbm_budget_bytes;
-    sv->grid_share = std::max(1, di.cus / n_slots);
+    sv->n_share = n_slots;
     sv->slots.resize(n_slots);
     for (auto &sl : sv->slots) {
         void *h = nullptr;
@@ -422,8 +447,27 @@ nk_status nk_server_submit(nk_server *sv, int32_t graph_id, const int32_t *sourc
     rq->seed = seed;
     rq->out = bc_out;
     const long long tasks = k > 0 ? k : (g.n >= 2 ? nk_rk_sample_size(eps, delta, g.vd) : 0);
-    rq->footprint = request_footprint(g, tasks, (int)std::min<long long>(std::max<long long>(tasks, 1), sv->grid_share),
-                                      k == 0);
+    // the kernel's grid: an equal share of the workgroups the GPU holds at
+    // once for this kernel (block size and occupancy depend on the graph),
+    // so that n_slots requests together fill the GPU
+    {
+        LaunchPlan pl;
+        const nk_status ps = plan_launch(k > 0 ? kModeBC : kModePair, g.n, std::max<long long>(tasks, 1),
+                                         -sv->n_share, &pl);
+        if (ps != NK_OK) {
+            delete rq;
+            return ps;
+        }
+        rq->grid = pl.grid;
+    }
+    // a smaller grid (slower, but admissible) when that share's scratch does
+    // not fit the budget beside the resident graphs
+    rq->tasks = tasks;
+    rq->footprint = request_footprint(g, tasks, rq->grid, k == 0);
+    while (rq->grid > 1 && sv->pool_bytes + rq->footprint > sv->budget) {
+        rq->grid = (rq->grid + 1) / 2;
+        rq->footprint = request_footprint(g, tasks, rq->grid, k == 0);
+    }
     if (sv->pool_bytes + rq->footprint > sv->budget) {
         const size_t need = rq->footprint;
         delete rq;

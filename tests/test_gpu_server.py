@@ -66,8 +66,9 @@ def test_budget_admission():
         with pytest.raises(nk.NkError) as e:
             sv.add_graph(rp, ci)
         assert e.value.code == nk.NK_E_BUDGET
-    # room for the graph (about 2 MiB) and one running request (about 46 MiB
-    # of per-workgroup scratch at 64 workgroups): requests run one at a time
+    # room for the graph (about 2 MiB) and one running request (its grid
+    # shrinks until the per-workgroup scratch fits: about 46 MiB at 64
+    # workgroups): requests run one at a time
     with nk.NkServer(80 << 20, slots=4) as sv:
         gid = sv.add_graph(rp, ci)
         reqs = [{"id": i, "t": 0.0, "graph": 0, "seed": i, "sources": gg.sample_sources(g.n, 128, 700 + i)}
