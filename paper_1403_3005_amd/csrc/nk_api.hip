@@ -1069,8 +1069,11 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     uint32_t *iso;
     const long long words = ((long long)n + 31) / 32;
     if ((st = scr.get(words, &iso)) != NK_OK) return st;
-    Relabeled g;
-    if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+    // The graph runs under the caller's ids: a pair sample touches a few
+    // thousand vertices, and degree relabelling (a pass over every arc per
+    // call) left the pair kernel's time unchanged on Chung-Lu, R-MAT and
+    // Erdos-Renyi graphs.
+    const Relabeled g = {rowptr, colidx, nullptr, nullptr};
     NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
     uint32_t *cnt = counts;
     if (counts && g.perm) {
