@@ -134,3 +134,45 @@ def test_rmat20_weighted_sampled_vs_oracle(rmat20):
     few = src[:6]
     got = nk.nk_bc_weighted(rp, ci, wt, ivec(few), g.n / 4096).cpu().numpy()
     assert_scores_close(got, oracle.bc_weighted(g.rowptr, g.colidx, w, few, g.n / 4096, nthreads=6), "wrmat20")
+
+
+def test_batched512_first_launch_group_at_full_size():
+    """The batched workload's first launch group exactly as the benchmark
+    builds and runs it (64 graphs of the 512, one call): the graphs the
+    oracle finishes quickly against it, the largest graph by the identity
+    sum of scores = sum over sources s and reached t != s of (d(s, t) - 1)
+    with distances from the inspection call (bit-exact against the oracle
+    elsewhere), every score non-negative."""
+    sizes = gg.batched_sizes(512, 1000, 200_000, 4)[:64]
+    graphs = []
+    for i, n in enumerate(sizes):
+        gs = gg.draw(4, 61, i, 0)
+        graphs.append(gg.erdos_renyi(n, 4 * n, gs) if i % 2 == 0 else gg.barabasi_albert(n, 4, gs))
+    vtx = np.zeros(len(graphs) + 1, dtype=np.int64)
+    arc = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vtx[i + 1] = vtx[i] + g.n
+        arc[i + 1] = arc[i] + g.m
+    rp = torch.from_numpy(np.concatenate([g.rowptr for g in graphs]).astype(np.int32)).cuda()
+    ci = torch.from_numpy(np.concatenate([g.colidx for g in graphs]).astype(np.int32)).cuda()
+    nk.nk_set_tuning()
+    got = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
+    assert nk.nk_last_stats()["sources"] == int(vtx[-1])
+    assert got.min() >= 0.0
+    small = [i for i, g in enumerate(graphs) if g.n <= 2500]
+    assert small
+    for i in small:
+        g = graphs[i]
+        assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx, nthreads=8), f"graph {i}")
+    big = max(range(len(graphs)), key=lambda i: graphs[i].n)
+    g = graphs[big]
+    grp, gci = upload(g)
+    acc = 0.0
+    for c0 in range(0, g.n, 512):
+        src = np.arange(c0, min(g.n, c0 + 512), dtype=np.int32)
+        d, _ = nk.nk_sssp_counts(grp, gci, ivec(src))
+        pos = d[d > 0].to(torch.float64)
+        acc += float((pos - 1.0).sum().item())
+        del d
+    total = float(got[vtx[big]:vtx[big + 1]].sum())
+    assert abs(total - acc) <= 1e-9 * acc, (g.n, total, acc)
