@@ -88,6 +88,8 @@ struct Params {
     int32_t *mark;
     int32_t *wl0;
     int32_t *wl1;
+    int32_t *wl2;              // far pile of the near-far distance rounds
+    long long wdelta;          // threshold step of the near-far rounds (0: one bucket)
     // pair mode: 32-byte per-vertex records of both search sides (path
     // counts and distances from u and from v; `stride` records per slot)
     // and the level lists of the side grown from the target
@@ -131,6 +133,8 @@ hipError_t launch_fill_f64(double *p, double v, long long count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, long long count, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, long long count, hipStream_t s);
 hipError_t launch_validate_weights(const int32_t *wts, long long m, DevStatus *st, hipStream_t s);
+// *sum (zeroed by the caller) += sum of the m weights
+hipError_t launch_sum_weights(const int32_t *wts, long long m, unsigned long long *sum, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long long count, hipStream_t s);
 hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);

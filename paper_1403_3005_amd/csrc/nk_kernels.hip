@@ -66,6 +66,7 @@ struct Scr {
     unsigned long long *dist;   // weighted mode: distances (all-ones = unreached)
     int32_t *mark;              // weighted mode: round that last queued the vertex
     int32_t *wl0, *wl1;         // weighted mode: worklists of the distance rounds
+    int32_t *wl2;               // weighted mode: far pile
     unsigned long long *sigma;  // path counts; coef bits during the backward phase
     double *dacc;               // push-mode dependency sums (kept at zero between uses)
     int32_t *ldeg;              // degree sum of each level
@@ -660,16 +661,26 @@ __device__ __forceinline__ int32_t stage_ids(Tile<BLOCK> &sm, const int32_t *lis
 
 // Distances from src; returns the number of reached vertices, listed in
 // s.cand.  ep: the workgroup's round counter (never repeats in a launch).
+// Near-far ordering (a two-bucket form of delta-stepping): a round relaxes
+// the queued vertices whose distance is below the threshold; an improved
+// vertex joins the next round if its new distance is below the threshold,
+// else a "far" pile (once: s.d flags membership).  When no near vertex is
+// left the threshold rises by p.wdelta and the far vertices now below it
+// move to the next round.  Vertices are then settled roughly in distance
+// order, so fewer of them are relaxed more than once.
 template <int BLOCK>
 __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
                                int32_t &ep, unsigned long long *sd, Counters &c) {
     const int tid = threadIdx.x;
-    __shared__ int32_t s_reach, s_next;
+    __shared__ int32_t s_reach, s_next, s_far, s_keep;
+    const unsigned long long step = p.wdelta > 0 ? (unsigned long long)p.wdelta : kInf;
+    unsigned long long thr = step;
     if (tid == 0) {
         s.dist[src] = 0ULL;
         s.cand[0] = src;
         s.wl0[0] = src;
         s_reach = 1;
+        s_far = 0;
     }
     __syncthreads();
     int32_t cur = 0, ncur = 1;
@@ -693,7 +704,7 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
                 load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
-                    bool first = false, queue = false;
+                    bool first = false, queue = false, far = false;
                     if (kk[j] >= 0) {
                         const int32_t k = kk[j];
                         const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
@@ -702,18 +713,50 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
                             const unsigned long long old = atomicMin(&s.dist[w[j]], nd);
                             if (nd < old) {
                                 first = old == kInf;
-                                queue = atomicExch(&s.mark[w[j]], ep) != ep;
+                                if (nd < thr) {
+                                    queue = atomicExch(&s.mark[w[j]], ep) != ep;
+                                    s.d[w[j]] = 0;   // a far-pile entry of w is stale now
+                                } else {
+                                    far = atomicExch(&s.d[w[j]], 1) == 0;
+                                }
                             }
                         }
                     }
                     wave_append(first, w[j], s.cand, &s_reach, g.n, &p.st->err);
                     wave_append(queue, w[j], out, &s_next, g.n, &p.st->err);
+                    wave_append(far, w[j], s.wl2, &s_far, g.n, &p.st->err);
                 }
             }
             __syncthreads();
         }
-        const int32_t nn = s_next;
+        int32_t nn = s_next;
         __syncthreads();
+        // no near vertex left: raise the threshold until some far vertex is
+        // below it, and move those to the next round
+        while (nn == 0 && s_far > 0) {
+            thr = thr > kInf - step ? kInf : thr + step;
+            const int32_t nf = s_far;
+            if (tid == 0) s_keep = 0;
+            __syncthreads();
+            // far vertices are kept in place (their order matters not);
+            // each pass rewrites the pile's prefix with the ones that stay
+            for (int32_t tb = 0; tb < nf; tb += BLOCK) {
+                const int32_t i = tb + tid;
+                const int32_t v = i < nf ? s.wl2[i] : 0;
+                // an entry whose vertex was queued near since is dropped
+                const bool live = i < nf && s.d[v] != 0;
+                const bool near = live && s.dist[v] < thr;
+                __syncthreads();   // every thread has read its entry before any is rewritten
+                wave_append(near, v, out, &s_next, g.n, &p.st->err);
+                wave_append(live && !near, v, s.wl2, &s_keep, g.n, &p.st->err);
+                if (near) s.d[v] = 0;
+                __syncthreads();
+            }
+            if (tid == 0) s_far = s_keep;
+            __syncthreads();
+            nn = s_next;
+            __syncthreads();
+        }
         if (nn == 0) break;
         cur ^= 1;
         ncur = nn;
@@ -725,8 +768,8 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
 // nreach)): path counts into s.sigma, layers into s.lv/la/ld with offsets
 // s.lvl; s.d holds DAG in-degrees.  Returns the deepest layer.
 template <int BLOCK>
-__device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
-                            int32_t nreach, unsigned long long *sd, Counters &c) {
+__device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
+                                 int32_t nreach, unsigned long long *sd, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t i = tid; i < nreach; i += BLOCK) s.d[s.cand[i]] = 0;
     __syncthreads();
@@ -812,6 +855,113 @@ __device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, cons
         ++L;
     }
     return L;
+}
+
+constexpr int kDistBuckets = 4096;   // distinct distances the bucket ordering handles
+
+// The same layers when every reached distance is below kDistBuckets (and
+// below the per-slot stride): one layer per distance value, found by a
+// counting sort in LDS -- a DAG arc always goes to a larger distance, so
+// the layers are a topological order and no in-degree pass is needed.
+// Layer l holds the vertices at distance l (often none).  Returns the
+// deepest layer.
+template <int BLOCK>
+__device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
+                                    int32_t nreach, int32_t D, int32_t *hist, unsigned long long *sd,
+                                    Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t b = tid; b < D; b += BLOCK) hist[b] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < nreach; i += BLOCK) atomicAdd(&hist[(int32_t)s.dist[s.cand[i]]], 1);
+    __syncthreads();
+    // exclusive prefix of the histogram into s.lvl and into hist (cursors)
+    int32_t carry = 0;
+    for (int32_t b0 = 0; b0 < D; b0 += BLOCK) {
+        const int32_t b = b0 + tid;
+        const int32_t x = b < D ? hist[b] : 0;
+        int32_t total;
+        const int32_t ex = block_excl_scan<BLOCK>(x, sm, total);
+        if (b < D) {
+            s.lvl[b] = carry + ex;
+            hist[b] = carry + ex;
+        }
+        carry += total;
+    }
+    if (tid == 0) s.lvl[D] = carry;
+    __syncthreads();
+    for (int32_t i = tid; i < nreach; i += BLOCK) {
+        const int32_t v = s.cand[i];
+        const int32_t pos = atomicAdd(&hist[(int32_t)s.dist[v]], 1);
+        const int32_t a0 = g.rp[v];
+        s.lv[pos] = v;
+        s.la[pos] = a0;
+        s.ld[pos] = g.rp[v + 1] - a0;
+    }
+    if (tid == 0) s.sigma[src] = 1ULL;
+    __syncthreads();
+    // path counts: each layer pushes to its DAG successors, all in later layers
+    for (int32_t l = 0; l < D; ++l) {
+        const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
+        if (lo == hi) continue;
+        if (tid == 0) c.bu++;
+        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
+            const int32_t cnt = min(BLOCK, hi - tb);
+            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+            if (tid < cnt) {
+                sd[tid] = s.dist[sm.v[tid]];
+                sm.val.u[tid] = s.sigma[sm.v[tid]];
+            }
+            __syncthreads();
+            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                int32_t kk[kChunk], w[kChunk];
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    if (kk[j] < 0) continue;
+                    const int32_t k = kk[j];
+                    const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
+                    if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
+                        const unsigned long long add = sm.val.u[k];
+                        const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
+                        if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
+                        c.dag++;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return D - 1;
+}
+
+// Layers of the shortest-path DAG (see w_layers_kahn / w_layers_buckets):
+// by distance buckets when the reached distances span few values, else by
+// Kahn layering.
+template <int BLOCK>
+__device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
+                            int32_t nreach, unsigned long long *sd, Counters &c) {
+    __shared__ int32_t hist[kDistBuckets];
+    __shared__ unsigned long long s_maxd;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_maxd = 0ULL;
+    __syncthreads();
+    unsigned long long mx = 0ULL;
+    for (int32_t i = tid; i < nreach; i += BLOCK) {
+        const unsigned long long d = s.dist[s.cand[i]];
+        mx = d > mx ? d : mx;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long y = __shfl_xor(mx, off, kWave);
+        mx = y > mx ? y : mx;
+    }
+    if (lane_id() == 0) atomicMax(&s_maxd, mx);
+    __syncthreads();
+    const unsigned long long maxd = s_maxd;
+    __syncthreads();
+    if (maxd + 1 <= (unsigned long long)kDistBuckets && (long long)maxd + 2 <= p.stride)
+        return w_layers_buckets<BLOCK>(p, sm, s, g, src, nreach, (int32_t)maxd + 1, hist, sd, c);
+    return w_layers_kahn<BLOCK>(p, sm, s, g, src, nreach, sd, c);
 }
 
 // Dependencies over the layers in reverse: delta_v = sigma_v * sum over DAG
@@ -1279,6 +1429,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.mark = p.mark ? p.mark + off : nullptr;
     s.wl0 = p.wl0 ? p.wl0 + off : nullptr;
     s.wl1 = p.wl1 ? p.wl1 + off : nullptr;
+    s.wl2 = p.wl2 ? p.wl2 + off : nullptr;
     uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists
@@ -1549,6 +1700,15 @@ __global__ void k_validate_weights(const int32_t *wts, long long m, DevStatus *s
     if (__ballot(bad) != 0ULL && lane_id() == 0) atomicOr(&st->err, kErrGraph);
 }
 
+__global__ void k_sum_weights(const int32_t *wts, long long m, unsigned long long *sum) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    unsigned long long t = 0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
+        t += (unsigned long long)(uint32_t)wts[e];
+    t = wave_sum<unsigned long long>(t);
+    if (lane_id() == 0 && t) atomicAdd(sum, t);
+}
+
 __global__ void k_iso_bitmap(const int32_t *rowptr, int32_t n, uint32_t *iso) {
     const int32_t nw = (n + 31) >> 5;
     const int32_t wi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1688,6 +1848,11 @@ hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale,
 }
 hipError_t launch_validate_weights(const int32_t *wts, long long m, DevStatus *st, hipStream_t s) {
     hipLaunchKernelGGL(k_validate_weights, dim3(grid_for(m, 256)), dim3(256), 0, s, wts, m, st);
+    return hipGetLastError();
+}
+hipError_t launch_sum_weights(const int32_t *wts, long long m, unsigned long long *sum, hipStream_t s) {
+    const unsigned g = grid_for(m, 256);
+    hipLaunchKernelGGL(k_sum_weights, dim3(g < 1024 ? g : 1024), dim3(256), 0, s, wts, m, sum);
     return hipGetLastError();
 }
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s) {

@@ -28,6 +28,8 @@ CASES = [
     (lambda: gg.barabasi_albert(3000, 3, 42), 5, True), (lambda: gg.grid(20, 27), 2, True),
     (lambda: gg.path(300), 7, True), (lambda: gg.rmat(12, 8, 43), 16, True),
     (lambda: gg.directed_rmat(12, 8, 44), 9, False),
+    # weights up to 10^6: distances span more values than the bucket ordering takes (Kahn layers)
+    (lambda: gg.erdos_renyi(2000, 6000, 48), 1000000, True), (lambda: gg.rmat(11, 8, 49), 50000, False),
     (lambda: gg.disjoint_union([gg.grid(6, 7), gg.star(50), gg.path(1), gg.cycle(9), gg.complete(5)]), 4, True),
 ]
 
