@@ -72,3 +72,36 @@ def test_batched_sizes_log_uniform():
     assert min(sizes) >= 1000 and max(sizes) <= 200000
     logs = np.log(sizes)
     assert abs(np.median(logs) - 0.5 * (np.log(1000) + np.log(200000))) < 0.5
+
+
+def test_directed_generators():
+    """Directed graphs: rows sorted, no self-loops or duplicate arcs, not
+    symmetrised; the transpose holds every arc reversed; deterministic."""
+    g = gg.directed_rmat(10, 8, 3)
+    assert g.sha256() == gg.directed_rmat(10, 8, 3).sha256() != gg.directed_rmat(10, 8, 4).sha256()
+    src = np.repeat(np.arange(g.n), g.degrees())
+    assert np.all(src != g.colidx)
+    for v in range(g.n):
+        row = g.colidx[g.rowptr[v]:g.rowptr[v + 1]]
+        assert np.all(np.diff(row) > 0)
+    arcs = set(zip(src.tolist(), g.colidx.tolist()))
+    assert any((b, a) not in arcs for a, b in arcs)          # not symmetric
+    t = gg.transpose(g)
+    tsrc = np.repeat(np.arange(t.n), t.degrees())
+    assert set(zip(t.colidx.tolist(), tsrc.tolist())) == arcs
+    r = gg.directed_random(300, 2000, 9)
+    assert r.m <= 2000 and r.sha256() == gg.directed_random(300, 2000, 9).sha256()
+
+
+def test_edge_weights_symmetric_ranged_deterministic():
+    g = gg.barabasi_albert(500, 3, 10)
+    w = gg.edge_weights(g, 17, 11)
+    assert w.dtype == np.int32 and w.min() >= 1 and w.max() <= 17
+    assert np.array_equal(w, gg.edge_weights(g, 17, 11)) and not np.array_equal(w, gg.edge_weights(g, 17, 12))
+    src = np.repeat(np.arange(g.n), g.degrees())
+    wt = {(int(a), int(b)): int(x) for a, b, x in zip(src, g.colidx, w)}
+    assert all(wt[(b, a)] == x for (a, b), x in wt.items())  # both arcs of an edge agree
+    d = gg.directed_rmat(8, 4, 13)
+    wd = gg.edge_weights(d, 5, 14, symmetric=False)
+    assert wd.shape == (d.m,) and wd.min() >= 1 and wd.max() <= 5
+    assert len(np.unique(gg.edge_weights(gg.erdos_renyi(2000, 8000, 15), 64, 16))) == 64
