@@ -500,11 +500,14 @@ def main():
         print(f"bench: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
     kernel_us = []
+    step_s = []
     stats = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        nk.nk_bc_sources(rp, ci, sv, scale, bc=bc, stream=stream)
+        ts = time.perf_counter()
+        nk.nk_bc_sources(rp, ci, sv, scale, bc=bc, stream=stream)   # returns after its stream is synchronised
+        step_s.append(time.perf_counter() - ts)
         stats = nk.nk_last_stats()
         kernel_us.append(stats["kernel_us"])
     torch.cuda.synchronize()
@@ -541,6 +544,10 @@ def main():
             "scale": scale,
             "arc_gteps": round(2 * value, 3),
             "kernel_ms": round(kern_s * 1e3, 3),
+            "step_ms_median": round(float(np.median(step_s)) * 1e3, 3),
+            "step_ms_min": round(float(np.min(step_s)) * 1e3, 3),
+            "kernel_ms_median": round(float(np.median(kernel_us)) * 1e-3, 3),
+            "kernel_ms_min": round(float(np.min(kernel_us)) * 1e-3, 3),
             "tuning": nk.nk_get_tuning(),
             "workgroups": stats["workgroups"],
             "block": stats["block"],
