@@ -443,7 +443,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path shards by "
-              "source across GPUs with one score all-reduce, which this build does not run).", file=sys.stderr)
+              "source across GPUs with one score all-reduce, which this library does not implement).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
