@@ -251,11 +251,11 @@ static void finish_request(nk_server *sv, Slot &sl) {
     sv->cv_done.notify_all();
 }
 
-// With fewer requests running than slots, a request starting now takes a
-// larger share of the GPU: 1/max(2, running + 1) of the resident-workgroup
-// capacity (half the GPU when alone, so that a second arrival still finds
-// room), if its scratch fits the budget; otherwise it keeps its
-// submission-time share.
+// With fewer requests running than slots and none waiting, a request
+// starting now takes a larger share of the GPU: 1/max(2, running + 1) of
+// the resident-workgroup capacity (half the GPU when alone, so that a
+// second arrival still finds room), if its scratch fits the budget;
+// otherwise it keeps its submission-time share.
 static void widen_grid(nk_server *sv, Request *rq, int busy) {
     const int div = std::max(2, busy + 1);
     if (div >= sv->n_share) return;
@@ -289,8 +289,10 @@ static void worker_main(nk_server *sv) {
                 if (sv->slots[i].req) continue;
                 Request *rq = sv->pending.front();
                 if (sv->pool_bytes + sv->running_bytes + rq->footprint > sv->budget && busy > 0) break;
-                widen_grid(sv, rq, busy);
                 sv->pending.pop_front();
+                // a wider grid only while nothing else waits: under load every
+                // request keeps its fair share
+                if (sv->pending.empty()) widen_grid(sv, rq, busy);
                 sv->running_bytes += rq->footprint;
                 sv->slots[i].req = rq;  // reserve
                 to_start.push_back({(int)i, rq});
