@@ -695,10 +695,19 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     } else if (k > 0) {
         where = -1;
         Relabeled g = {rowptr, colidx, nullptr, nullptr};
-        // a directed run keeps its ids (one renaming would have to cover
-        // both arc arrays)
-        if (!dir)
-            if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        // a directed run renames its in-arcs with the same permutation
+        DirectedArgs dir_run = {nullptr, nullptr};
+        if (dir) {
+            dir_run = *dir;
+            if (dir->trp && g.perm) {
+                int32_t *trp_new, *tci_new;
+                if ((st = relabel_second_csr(dir->trp, dir->tci, n, m, g, dst, scr, s, &trp_new, &tci_new)) != NK_OK)
+                    return st;
+                dir_run = {trp_new, tci_new};
+            }
+            dir = &dir_run;
+        }
         // edge scores of a relabelled run go to the relabelled arc order
         // first, then back to the caller's
         double *ebc_run = ebc;
@@ -833,24 +842,44 @@ nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int
             wdelta = (long long)(hsum / (unsigned long long)m) / 4;
             if (wdelta < 1) wdelta = 1;
         }
-        // the graph keeps its ids: the weights are indexed by arc
+        // degree order, with the weights carried to the renamed arcs
+        Relabeled g = {rowptr, colidx, nullptr, nullptr};
+        if ((st = prepare_graph(rowptr, colidx, n, m, dst, scr, s, &g)) != NK_OK) return st;
+        const int32_t *wts = weights, *src = sources;
+        double *acc = bc;
+        if (g.perm) {
+            int32_t *w_new;
+            if ((st = relabel_weights(weights, rowptr, n, m, g, dst, scr, s, &w_new)) != NK_OK) return st;
+            wts = w_new;
+            if (sources) {
+                int32_t *mapped;
+                if ((st = scr.get(k, &mapped)) != NK_OK) return st;
+                NK_HIP(launch_map_sources(sources, k, g.perm, n, mapped, s));
+                src = mapped;
+            }
+            if ((st = scr.get(n, &acc)) != NK_OK) return st;
+            NK_HIP(launch_fill_f64(acc, 0.0, n, s));
+        }
         if ((st = plan_launch(kModeWeighted, n, k, 0, &plan)) != NK_OK) return st;
         Params p;
         memset(&p, 0, sizeof(p));
-        p.rowptr = rowptr;
-        p.colidx = colidx;
+        p.rowptr = g.rowptr;
+        p.colidx = g.colidx;
         p.n = n;
         p.m = (int32_t)m;
         p.ntasks = k;
-        p.sources = sources;
-        p.bc = bc;
+        p.sources = src;
+        p.bc = acc;
         p.st = dst;
-        p.wts = weights;
+        p.wts = wts;
         p.wdelta = wdelta;
         hipEvent_t ev0, ev1;
         if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
         if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
-        if (scale != 1.0) NK_HIP(launch_scale_f64(bc, scale, n, s));
+        if (g.perm)
+            NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
+        else if (scale != 1.0)
+            NK_HIP(launch_scale_f64(bc, scale, n, s));
         st = finish(dst, h, s);
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     } else {

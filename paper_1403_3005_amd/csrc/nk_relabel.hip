@@ -83,6 +83,35 @@ __global__ void k_arcs_back(const double *in, const int32_t *rp_new, const int32
     }
 }
 
+// Per-arc int32 values into the relabelled arc order (the inverse of
+// k_arcs_back): arc j of internal vertex i is arc j of original vertex inv[i].
+__global__ void k_arcs_fwd_i32(const int32_t *in, const int32_t *rp_new, const int32_t *inv, const int32_t *rowptr,
+                               int32_t n, int32_t *out, const DevStatus *st) {
+    if (st->err & kErrGraph) return;
+    const long long waves = (long long)gridDim.x * (blockDim.x / kWave);
+    const int lane = lane_id();
+    for (long long i = (long long)blockIdx.x * (blockDim.x / kWave) + wave_id(); i < n; i += waves) {
+        const int32_t a = rp_new[i], b = rp_new[i + 1], o = rowptr[inv[i]];
+        for (int32_t j = lane; j < b - a; j += kWave) out[a + j] = in[o + j];
+    }
+}
+
+// Row lengths of a second CSR over the same vertices (the in-arcs of a
+// directed graph) in internal order, plus a zero at n for the scan.
+__global__ void k_inv_degrees(const int32_t *rowptr, const int32_t *inv, int32_t n, int32_t *deg_new,
+                              const DevStatus *st) {
+    if (st->err & kErrGraph) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+        if (i == n) {
+            deg_new[n] = 0;
+            continue;
+        }
+        const int32_t o = inv[i];
+        deg_new[i] = rowptr[o + 1] - rowptr[o];
+    }
+}
+
 static unsigned grid_of(long long count, int block) {
     long long g = (count + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -120,6 +149,40 @@ nk_status relabel_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     out->colidx = ci_new;
     out->perm = perm;
     out->inv = inv;
+    return NK_OK;
+}
+
+nk_status relabel_weights(const int32_t *wts, const int32_t *rowptr, int32_t n, int64_t m, const Relabeled &g,
+                          const DevStatus *st, Scratch &scr, hipStream_t s, int32_t **out) {
+    nk_status rc;
+    if ((rc = scr.get(m > 0 ? m : 1, out)) != NK_OK) return rc;
+    if (m == 0) return NK_OK;
+    hipLaunchKernelGGL(k_arcs_fwd_i32, dim3(grid_of((long long)n * kWave, 256)), dim3(256), 0, s, wts, g.rowptr,
+                       g.inv, rowptr, n, *out, st);
+    NK_HIP(hipGetLastError());
+    return NK_OK;
+}
+
+nk_status relabel_second_csr(const int32_t *rowptr2, const int32_t *colidx2, int32_t n, int64_t m, const Relabeled &g,
+                             const DevStatus *st, Scratch &scr, hipStream_t s, int32_t **rp_out, int32_t **ci_out) {
+    nk_status rc;
+    int32_t *deg_new, *rp_new, *ci_new;
+    if ((rc = scr.get((long long)n + 1, &deg_new)) != NK_OK) return rc;
+    if ((rc = scr.get((long long)n + 1, &rp_new)) != NK_OK) return rc;
+    if ((rc = scr.get(m > 0 ? m : 1, &ci_new)) != NK_OK) return rc;
+    size_t scan_bytes = 0;
+    NK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, deg_new, rp_new, n + 1, s));
+    void *tmp;
+    if ((rc = scr.get(scan_bytes > 0 ? scan_bytes : 1, &tmp)) != NK_OK) return rc;
+    hipLaunchKernelGGL(k_inv_degrees, dim3(grid_of((long long)n + 1, 256)), dim3(256), 0, s, rowptr2, g.inv, n,
+                       deg_new, st);
+    NK_HIP(hipGetLastError());
+    NK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, scan_bytes, deg_new, rp_new, n + 1, s));
+    hipLaunchKernelGGL(k_relabel_arcs, dim3(grid_of((long long)n * kWave, 256)), dim3(256), 0, s, rowptr2, colidx2,
+                       g.inv, g.perm, rp_new, n, ci_new, st);
+    NK_HIP(hipGetLastError());
+    *rp_out = rp_new;
+    *ci_out = ci_new;
     return NK_OK;
 }
 

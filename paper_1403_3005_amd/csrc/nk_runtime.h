@@ -153,6 +153,13 @@ nk_status check_transpose(const int32_t *colidx, int32_t n, int64_t m, const int
 
 nk_status relabel_graph(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const DevStatus *st,
                         Scratch &scr, hipStream_t s, Relabeled *out);
+// The same renaming applied to per-arc int32 values (arc weights), and to a
+// second CSR over the same vertices (the in-arcs of a directed graph; its
+// rows get the renamed in-neighbours, in their original order).
+nk_status relabel_weights(const int32_t *wts, const int32_t *rowptr, int32_t n, int64_t m, const Relabeled &g,
+                          const DevStatus *st, Scratch &scr, hipStream_t s, int32_t **out);
+nk_status relabel_second_csr(const int32_t *rowptr2, const int32_t *colidx2, int32_t n, int64_t m, const Relabeled &g,
+                             const DevStatus *st, Scratch &scr, hipStream_t s, int32_t **rp_out, int32_t **ci_out);
 hipError_t launch_map_sources(const int32_t *src, int32_t k, const int32_t *perm, int32_t n, int32_t *out,
                               hipStream_t s);
 hipError_t launch_arcs_back(const double *in, const int32_t *rp_new, const int32_t *inv, const int32_t *rowptr,

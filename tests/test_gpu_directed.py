@@ -33,7 +33,9 @@ GRAPHS = [
 ]
 
 
-@pytest.mark.parametrize("flags", [0, 4])
+# flags: 2 keeps the caller's vertex ids (no degree relabelling), 4 turns
+# off the all-in-LDS kernel
+@pytest.mark.parametrize("flags", [0, 2, 4])
 @pytest.mark.parametrize("with_t", [False, True])
 @pytest.mark.parametrize("make", GRAPHS)
 def test_directed_exact_and_sampled(make, with_t, flags):

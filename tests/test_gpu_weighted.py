@@ -48,6 +48,19 @@ def test_weighted_exact_and_sampled(make, wmax, sym):
     assert_scores_close(got, oracle.bc_weighted(g.rowptr, g.colidx, w, src, g.n / k), g.name + " sampled")
 
 
+@pytest.mark.parametrize("sym", [True, False])
+def test_weighted_with_and_without_relabelling(sym):
+    """Degree relabelling (the default above 256 vertices) carries each
+    arc's weight to the renamed arc; flag 2 runs under the caller's ids."""
+    g = gg.rmat(12, 8, 50) if sym else gg.directed_rmat(12, 8, 51)
+    w = gg.edge_weights(g, 12, 52, symmetric=sym)
+    rp, ci = upload(g)
+    ref = oracle.bc_weighted(g.rowptr, g.colidx, w, nthreads=8)
+    for flags in (0, 2):
+        nk.nk_set_tuning(flags=flags)
+        assert_scores_close(nk.nk_bc_weighted(rp, ci, _dev(w)).cpu().numpy(), ref, f"flags={flags}")
+
+
 def test_unit_weights_equal_unweighted_on_gpu():
     g = gg.barabasi_albert(4000, 3, 47)
     rp, ci = upload(g)
