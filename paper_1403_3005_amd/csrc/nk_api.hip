@@ -305,7 +305,10 @@ static int auto_block(int32_t n_max) {
     return 1024;
 }
 
-nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan) {
+// Words of a per-slot bitmap over m arcs, rounded to 256 bytes.
+static long long dag_words_of(int64_t m) { return ((m + 31) / 32 + 63) / 64 * 64; }
+
+nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan, int64_t m_arcs) {
     DevInfo di;
     nk_status st = dev_info(&di);
     if (st != NK_OK) return st;
@@ -352,6 +355,8 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         // weighted: + u64 distances, round marks, two worklists and the far pile (24)
         size_t per_slot = (size_t)stride * (mode == kModePair ? 68 : mode == kModeWeighted ? 68 : 44);
         if (mode != kModePair && mode != kModeWeighted && !lds) per_slot += (size_t)wordsr * 4;
+        // weighted: one bit per arc marks the shortest-path DAG
+        if (mode == kModeWeighted) per_slot += (size_t)dag_words_of(m_arcs) * 4;
         size_t avail;
         if (t.scratch_mib > 0) {
             avail = (size_t)t.scratch_mib << 20;
@@ -381,6 +386,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     plan->bm_words = (words + 63) / 64 * 64;
     plan->kernel = kr;
     plan->pair_rec = nullptr;
+    plan->dag_words = mode == kModeWeighted ? dag_words_of(m_arcs) : 0;
     return NK_OK;
 }
 
@@ -435,6 +441,8 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
     p.dist = nullptr;
     p.mark = nullptr;
     p.wl0 = p.wl1 = p.wl2 = nullptr;
+    p.dagm = nullptr;
+    p.dag_words = plan.dag_words;
     if ((st = scr.get(cells, &p.dacc)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
@@ -463,6 +471,7 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
             if ((st = scr.get(cells, &p.wl0)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.wl1)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.wl2)) != NK_OK) return st;
+            if ((st = scr.get(slots * plan.dag_words, &p.dagm)) != NK_OK) return st;
         } else if (!plan.lds) {
             if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
         }
@@ -482,6 +491,7 @@ nk_status persistent_enqueue(const LaunchPlan &plan, const Params &p, hipStream_
             NK_HIP(launch_fill_u64(p.dist, ~0ULL, cells, s));
             NK_HIP(launch_fill_i32(p.mark, -1, cells, s));
             NK_HIP(launch_fill_i32(p.d, 0, cells, s));   // far-pile flags
+            NK_HIP(launch_fill_u32(p.dagm, 0u, (long long)plan.grid * plan.dag_words, s));
         }
         NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
         // the push accumulator of the dependency sweep must start at zero
@@ -860,7 +870,7 @@ nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int
             if ((st = scr.get(n, &acc)) != NK_OK) return st;
             NK_HIP(launch_fill_f64(acc, 0.0, n, s));
         }
-        if ((st = plan_launch(kModeWeighted, n, k, 0, &plan)) != NK_OK) return st;
+        if ((st = plan_launch(kModeWeighted, n, k, 0, &plan, m)) != NK_OK) return st;
         Params p;
         memset(&p, 0, sizeof(p));
         p.rowptr = g.rowptr;

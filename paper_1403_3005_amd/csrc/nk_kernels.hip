@@ -67,6 +67,7 @@ struct Scr {
     int32_t *mark;              // weighted mode: round that last queued the vertex
     int32_t *wl0, *wl1;         // weighted mode: worklists of the distance rounds
     int32_t *wl2;               // weighted mode: far pile
+    uint32_t *dagm;             // weighted mode: DAG-arc bitmap over the arcs
     unsigned long long *sigma;  // path counts; coef bits during the backward phase
     double *dacc;               // push-mode dependency sums (kept at zero between uses)
     int32_t *ldeg;              // degree sum of each level
@@ -766,7 +767,8 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
 
 // Shortest-path DAG layers from src over the reached vertices (s.cand[0,
 // nreach)): path counts into s.sigma, layers into s.lv/la/ld with offsets
-// s.lvl; s.d holds DAG in-degrees.  Returns the deepest layer.
+// s.lvl, DAG arcs into the bitmap s.dagm; s.d holds DAG in-degrees.
+// Returns the deepest layer.
 template <int BLOCK>
 __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
                                  int32_t nreach, unsigned long long *sd, Counters &c) {
@@ -789,6 +791,7 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
                 const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
                 if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
                     atomicAdd(&s.d[w[j]], 1);
+                    atomicOr(&s.dagm[arc >> 5], 1u << (arc & 31));
                     c.dag++;
                 }
             }
@@ -815,10 +818,7 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
             const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
-            if (tid < cnt) {
-                sd[tid] = s.dist[sm.v[tid]];
-                sm.val.u[tid] = s.sigma[sm.v[tid]];
-            }
+            if (tid < cnt) sm.val.u[tid] = s.sigma[sm.v[tid]];
             __syncthreads();
             for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
                 int32_t kk[kChunk], w[kChunk];
@@ -829,7 +829,7 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
                     if (kk[j] >= 0) {
                         const int32_t k = kk[j];
                         const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                        if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
+                        if ((s.dagm[arc >> 5] >> (arc & 31)) & 1u) {
                             const unsigned long long add = sm.val.u[k];
                             const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
                             if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
@@ -915,6 +915,8 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
             for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
                 int32_t kk[kChunk], w[kChunk];
                 load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                int32_t word = -1;
+                uint32_t bits = 0u;
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     if (kk[j] < 0) continue;
@@ -925,8 +927,15 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
                         const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
                         if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
                         c.dag++;
+                        if ((arc >> 5) != word) {
+                            if (bits) atomicOr(&s.dagm[word], bits);
+                            word = arc >> 5;
+                            bits = 0u;
+                        }
+                        bits |= 1u << (arc & 31);
                     }
                 }
+                if (bits) atomicOr(&s.dagm[word], bits);
             }
             __syncthreads();
         }
@@ -966,10 +975,13 @@ __device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, cons
 
 // Dependencies over the layers in reverse: delta_v = sigma_v * sum over DAG
 // successors x of (1 + delta_x) / sigma_x, kept as coefficients in place
-// of sigma; bc[v] += delta_v for every layer but the source's.
+// of sigma; bc[v] += delta_v for every layer but the source's.  The DAG
+// arcs are the bits the path-count pass set in s.dagm (a few percent of the
+// arcs on weighted graphs, whose shortest paths are mostly unique), so
+// the sweep reads no distances and no weights.
 template <int BLOCK>
 __device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t Ld, double *bcg,
-                           unsigned long long *sd, Counters &c) {
+                           Counters &c) {
     const int tid = threadIdx.x;
     if (Ld == 0) return;
     for (int32_t i = s.lvl[Ld] + tid; i < s.lvl[Ld + 1]; i += BLOCK) {
@@ -983,22 +995,39 @@ __device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const
             const int32_t cnt = min(BLOCK, hi - tb);
             if (tid < cnt) sm.val.f[tid] = 0.0;
             const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
-            if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
             __syncthreads();
             if (tid == 0) c.arcs_bwd += (unsigned long long)total;
             for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                int32_t kk[kChunk], w[kChunk];
-                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                // the DAG bitmap picks the arcs: only those load their head
+                // and its coefficient; their bits are cleared on the way
+                const int32_t i0 = rb + tid * kChunk;
+                int32_t kk[kChunk];
                 double cf[kChunk];
+                int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
+                int32_t word = -1;
+                uint32_t wv = 0u, bits = 0u;
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
+                    const int32_t i = i0 + j;
+                    kk[j] = -1;
                     cf[j] = 0.0;
-                    if (kk[j] >= 0) {
-                        const int32_t k = kk[j];
-                        const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                        if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) cf[j] = as_f64(s.sigma[w[j]]);
+                    if (i < total) {
+                        while (sm.pre[k + 1] <= i) ++k;
+                        kk[j] = k;
+                        const int32_t arc = sm.a0[k] + (i - sm.pre[k]);
+                        if ((arc >> 5) != word) {
+                            if (bits) atomicAnd(&s.dagm[word], ~bits);
+                            word = arc >> 5;
+                            wv = s.dagm[word];
+                            bits = 0u;
+                        }
+                        if ((wv >> (arc & 31)) & 1u) {
+                            bits |= 1u << (arc & 31);
+                            cf[j] = as_f64(s.sigma[g.ci[arc]]);
+                        }
                     }
                 }
+                if (bits) atomicAnd(&s.dagm[word], ~bits);
                 int32_t kcur = kk[0];
                 double acc = 0.0;
 #pragma unroll
@@ -1430,6 +1459,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.wl0 = p.wl0 ? p.wl0 + off : nullptr;
     s.wl1 = p.wl1 ? p.wl1 + off : nullptr;
     s.wl2 = p.wl2 ? p.wl2 + off : nullptr;
+    s.dagm = p.dagm ? p.dagm + slot * p.dag_words : nullptr;
     uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists
@@ -1526,13 +1556,20 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             const int32_t Ld = w_layers<BLOCK>(p, sm, s, g, src, nreach, wsd, c);
             phase_end<BLOCK>(sm, kPhBu);
             phase_start<BLOCK>(sm);
-            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, wsd, c);
+            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, c);
             phase_end<BLOCK>(sm, kPhPull);
             phase_start<BLOCK>(sm);
             for (int32_t i = tid; i < nreach; i += BLOCK) {
                 const int32_t v = s.cand[i];
                 s.sigma[v] = 0ULL;
                 s.dist[v] = kInf;
+            }
+            {
+                // the sweep cleared the DAG bits of every layer but the
+                // source's; the words of the source's arcs hold no others now
+                const int32_t a = g.rp[src], b = g.rp[src + 1];
+                if (b > a)
+                    for (int32_t wd = (a >> 5) + tid; wd <= ((b - 1) >> 5); wd += BLOCK) s.dagm[wd] = 0u;
             }
             if (tid == 0) {
                 c.reached += (unsigned long long)nreach;

@@ -83,11 +83,14 @@ struct LaunchPlan {
     long long bm_words;
     KernelRef kernel;
     void *pair_rec;   // pair mode: the record block the launch used (set by the caller after the launch)
+    long long dag_words;   // weighted mode: per-slot words of the DAG-arc bitmap
 };
 
 // Picks block size, bitmap placement and grid for graphs of at most n_max
-// vertices and `ntasks` tasks.  max_slots > 0 caps the grid.
-nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan);
+// vertices and `ntasks` tasks.  max_slots > 0 caps the grid.  m_arcs: the
+// arcs of the graph (weighted mode sizes its DAG-arc bitmap by them).
+nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan,
+                      int64_t m_arcs = 0);
 
 // Grid-wide direction-optimising breadth-first search (nk_bfs.hip).
 struct BfsWork {
