@@ -152,6 +152,23 @@ __device__ __forceinline__ void load_chunk(const Tile<BLOCK> &sm, const GView &g
     }
 }
 
+// Tile rows of the thread's chunk [i0, i0 + kChunk) of the tile's arcs
+// (-1 past the end), without loading the arcs' heads.
+template <int BLOCK>
+__device__ __forceinline__ void candidate_rows(const Tile<BLOCK> &sm, int32_t cnt, int32_t total, int32_t i0,
+                                               int32_t (&kk)[kChunk]) {
+    int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+        const int32_t i = i0 + j;
+        kk[j] = -1;
+        if (i < total) {
+            while (sm.pre[k + 1] <= i) ++k;
+            kk[j] = k;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- forward --
 
 // Top-down expansion of level `lvl` (list[f0, f1)) into list[f1, ...).
@@ -703,6 +720,8 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
             for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
                 int32_t kk[kChunk], w[kChunk];
                 load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                int32_t word = -1;
+                uint32_t bits = 0u;
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     bool first = false, queue = false, far = false;
@@ -710,7 +729,19 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
                         const int32_t k = kk[j];
                         const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
                         const unsigned long long nd = sd[k] + (unsigned long long)p.wts[arc];
-                        if (nd < s.dist[w[j]]) {
+                        const unsigned long long cur = s.dist[w[j]];
+                        // an arc that ties or improves its head's distance may
+                        // end in the shortest-path DAG: every DAG arc does so
+                        // when its tail is relaxed at its final distance
+                        if (nd <= cur) {
+                            if ((arc >> 5) != word) {
+                                if (bits) atomicOr(&s.dagm[word], bits);
+                                word = arc >> 5;
+                                bits = 0u;
+                            }
+                            bits |= 1u << (arc & 31);
+                        }
+                        if (nd < cur) {
                             const unsigned long long old = atomicMin(&s.dist[w[j]], nd);
                             if (nd < old) {
                                 first = old == kInf;
@@ -727,6 +758,7 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
                     wave_append(queue, w[j], out, &s_next, g.n, &p.st->err);
                     wave_append(far, w[j], s.wl2, &s_far, g.n, &p.st->err);
                 }
+                if (bits) atomicOr(&s.dagm[word], bits);
             }
             __syncthreads();
         }
@@ -782,19 +814,32 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
         if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
         __syncthreads();
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-            int32_t kk[kChunk], w[kChunk];
-            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+            int32_t kk[kChunk];
+            int32_t word = -1;
+            uint32_t wv = 0u, drop = 0u;
+            candidate_rows<BLOCK>(sm, cnt, total, rb + tid * kChunk, kk);
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 if (kk[j] < 0) continue;
                 const int32_t k = kk[j];
                 const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
-                    atomicAdd(&s.d[w[j]], 1);
-                    atomicOr(&s.dagm[arc >> 5], 1u << (arc & 31));
+                if ((arc >> 5) != word) {
+                    if (drop) atomicAnd(&s.dagm[word], ~drop);
+                    word = arc >> 5;
+                    wv = s.dagm[word];
+                    drop = 0u;
+                }
+                const uint32_t bit = 1u << (arc & 31);
+                if (!(wv & bit)) continue;
+                const int32_t x = g.ci[arc];
+                if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[x]) {
+                    atomicAdd(&s.d[x], 1);
                     c.dag++;
+                } else {
+                    drop |= bit;
                 }
             }
+            if (drop) atomicAnd(&s.dagm[word], ~drop);
         }
         __syncthreads();
     }
@@ -913,29 +958,34 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
             }
             __syncthreads();
             for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                int32_t kk[kChunk], w[kChunk];
-                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                int32_t kk[kChunk];
                 int32_t word = -1;
-                uint32_t bits = 0u;
+                uint32_t wv = 0u, drop = 0u;
+                candidate_rows<BLOCK>(sm, cnt, total, rb + tid * kChunk, kk);
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     if (kk[j] < 0) continue;
                     const int32_t k = kk[j];
                     const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                    if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[w[j]]) {
+                    if ((arc >> 5) != word) {
+                        if (drop) atomicAnd(&s.dagm[word], ~drop);
+                        word = arc >> 5;
+                        wv = s.dagm[word];
+                        drop = 0u;
+                    }
+                    const uint32_t bit = 1u << (arc & 31);
+                    if (!(wv & bit)) continue;
+                    const int32_t x = g.ci[arc];
+                    if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[x]) {
                         const unsigned long long add = sm.val.u[k];
-                        const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
+                        const unsigned long long o = atomicAdd(&s.sigma[x], add);
                         if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
                         c.dag++;
-                        if ((arc >> 5) != word) {
-                            if (bits) atomicOr(&s.dagm[word], bits);
-                            word = arc >> 5;
-                            bits = 0u;
-                        }
-                        bits |= 1u << (arc & 31);
+                    } else {
+                        drop |= bit;
                     }
                 }
-                if (bits) atomicOr(&s.dagm[word], bits);
+                if (drop) atomicAnd(&s.dagm[word], ~drop);
             }
             __syncthreads();
         }
