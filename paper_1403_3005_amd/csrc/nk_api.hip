@@ -323,18 +323,20 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
     const long long words = ((long long)n_max + 31) / 32;
     const size_t bm_bytes = (size_t)words * 4;
     bool lds = false;
+    // weighted mode: the distance-bucket histogram shares the dynamic LDS
+    // with the settled-vertex bitmap (or has it alone)
+    const size_t hist_bytes = mode == kModeWeighted ? (size_t)kDistBuckets * 4 : 0;
     {
         KernelRef probe = brandes_kernel(mode, block, true);
         hipFuncAttributes attr;
         NK_HIP(hipFuncGetAttributes(&attr, probe.fn));
         // pair mode keeps two visited bitmaps (one per search side) in global memory
-        // (the weighted mode keeps no visited bitmap)
-        lds = attr.sharedSizeBytes + bm_bytes <= di.lds_per_block && !(t.flags & 1) && mode != kModePair &&
-              mode != kModeWeighted;
+        lds = attr.sharedSizeBytes + std::max(bm_bytes, hist_bytes) <= di.lds_per_block && !(t.flags & 1) &&
+              mode != kModePair;
     }
     KernelRef kr = brandes_kernel(mode, block, lds);
-    size_t dyn = lds ? bm_bytes : 0;
-    if (lds) NK_HIP(hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    size_t dyn = std::max(lds ? bm_bytes : 0, hist_bytes);
+    if (dyn > 0) NK_HIP(hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     int occ = 0;
     NK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kr.fn, block, dyn));
     if (occ < 1) return fail(NK_E_INTERNAL, "kernel does not fit a compute unit (block %d, lds %zu)", block, dyn);
@@ -354,7 +356,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         // bitmap when it does not sit in LDS
         // weighted: + u64 distances, round marks, two worklists and the far pile (24)
         size_t per_slot = (size_t)stride * (mode == kModePair ? 68 : mode == kModeWeighted ? 68 : 44);
-        if (mode != kModePair && mode != kModeWeighted && !lds) per_slot += (size_t)wordsr * 4;
+        if (mode != kModePair && !lds) per_slot += (size_t)wordsr * 4;
         // weighted: one bit per arc marks the shortest-path DAG
         if (mode == kModeWeighted) per_slot += (size_t)dag_words_of(m_arcs) * 4;
         size_t avail;
@@ -472,9 +474,9 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
             if ((st = scr.get(cells, &p.wl1)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.wl2)) != NK_OK) return st;
             if ((st = scr.get(slots * plan.dag_words, &p.dagm)) != NK_OK) return st;
-        } else if (!plan.lds) {
-            if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
         }
+        if (!plan.lds)
+            if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
     }
     p.stride = plan.stride;
     p.bm_words = plan.bm_words;

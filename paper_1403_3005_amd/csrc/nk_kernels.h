@@ -19,6 +19,10 @@ enum Mode : int {
     kModeWeighted = 5  // betweenness over positive integer arc weights
 };
 
+// Weighted mode: distinct distances the bucket layering handles; its
+// histogram takes kDistBuckets ints of dynamic LDS.
+constexpr int kDistBuckets = 4096;
+
 // Everything a persistent launch reads.  Per-slot scratch arrays hold
 // `stride` elements per workgroup slot (slot = blockIdx.x).
 struct Params {
@@ -62,7 +66,7 @@ struct Params {
     int32_t *ld;
     int32_t *lvl;
     int32_t *cand;
-    uint32_t *bmg;             // global bitmaps (when not in LDS)
+    uint32_t *bmg;             // global bitmaps (when not in LDS; weighted mode: settled vertices)
     const uint32_t *iso;       // isolated-vertex bitmap of a single graph, or NULL
     long long stride;          // per-slot elements of the n-sized arrays
     long long bm_words;        // per-slot words of a global bitmap

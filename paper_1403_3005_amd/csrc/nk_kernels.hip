@@ -687,12 +687,19 @@ __device__ __forceinline__ int32_t stage_ids(Tile<BLOCK> &sm, const int32_t *lis
 // move to the next round.  Vertices are then settled roughly in distance
 // order, so fewer of them are relaxed more than once.
 template <int BLOCK>
-__device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
-                               int32_t &ep, unsigned long long *sd, Counters &c) {
+__device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g,
+                               int32_t src, int32_t &ep, unsigned long long *sd, Counters &c) {
     const int tid = threadIdx.x;
     __shared__ int32_t s_reach, s_next, s_far, s_keep;
     const unsigned long long step = p.wdelta > 0 ? (unsigned long long)p.wdelta : kInf;
     unsigned long long thr = step;
+    // bm: settled vertices.  When no near vertex is left below the
+    // threshold, every vertex whose distance is below it is final; those
+    // processed since the last rise (listed in s.lv, the pending list) are
+    // marked then, and later rounds skip arcs into them: with weights >= 1
+    // such an arc can neither improve nor tie their distance.
+    const int32_t nw = (g.n + 31) >> 5;
+    for (int32_t wi = tid; wi < nw; wi += BLOCK) bm[wi] = 0u;
     if (tid == 0) {
         s.dist[src] = 0ULL;
         s.cand[0] = src;
@@ -702,6 +709,7 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
     }
     __syncthreads();
     int32_t cur = 0, ncur = 1;
+    long long npend = 0;   // pending list length (uniform across the workgroup)
     for (;;) {
         ++ep;
         const int32_t *in = cur == 0 ? s.wl0 : s.wl1;
@@ -709,6 +717,12 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
         if (tid == 0) {
             s_next = 0;
             c.td++;
+        }
+        // this round's vertices join the pending list while it has room (a
+        // vertex left out is only not skipped later)
+        if (npend + ncur <= p.stride) {
+            for (int32_t i = tid; i < ncur; i += BLOCK) s.lv[npend + i] = in[i];
+            npend += ncur;
         }
         __syncthreads();
         for (int32_t tb = 0; tb < ncur; tb += BLOCK) {
@@ -725,7 +739,7 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
 #pragma unroll
                 for (int j = 0; j < kChunk; ++j) {
                     bool first = false, queue = false, far = false;
-                    if (kk[j] >= 0) {
+                    if (kk[j] >= 0 && !bit_test(bm, w[j])) {
                         const int32_t k = kk[j];
                         const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
                         const unsigned long long nd = sd[k] + (unsigned long long)p.wts[arc];
@@ -764,6 +778,12 @@ __device__ int32_t w_distances(const Params &p, Tile<BLOCK> &sm, const Scr &s, c
         }
         int32_t nn = s_next;
         __syncthreads();
+        if (nn == 0 && s_far > 0) {
+            // the threshold rises: the pending vertices are final
+            for (long long i = tid; i < npend; i += BLOCK) bit_set(bm, s.lv[i]);
+            npend = 0;
+            __syncthreads();
+        }
         // no near vertex left: raise the threshold until some far vertex is
         // below it, and move those to the next round
         while (nn == 0 && s_far > 0) {
@@ -902,7 +922,6 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
     return L;
 }
 
-constexpr int kDistBuckets = 4096;   // distinct distances the bucket ordering handles
 
 // The same layers when every reached distance is below kDistBuckets (and
 // below the per-slot stride): one layer per distance value, found by a
@@ -998,8 +1017,7 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
 // Kahn layering.
 template <int BLOCK>
 __device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t src,
-                            int32_t nreach, unsigned long long *sd, Counters &c) {
-    __shared__ int32_t hist[kDistBuckets];
+                            int32_t nreach, int32_t *hist, unsigned long long *sd, Counters &c) {
     __shared__ unsigned long long s_maxd;
     const int tid = threadIdx.x;
     if (tid == 0) s_maxd = 0ULL;
@@ -1600,10 +1618,13 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             continue;
         } else if constexpr (MODE == kModeWeighted) {
             phase_start<BLOCK>(sm);
-            const int32_t nreach = w_distances<BLOCK>(p, sm, s, g, src, ep, wsd, c);
+            const int32_t nreach = w_distances<BLOCK>(p, sm, bm, s, g, src, ep, wsd, c);
             phase_end<BLOCK>(sm, kPhTd);
             phase_start<BLOCK>(sm);
-            const int32_t Ld = w_layers<BLOCK>(p, sm, s, g, src, nreach, wsd, c);
+            // the distance-bucket histogram sits at the start of the dynamic
+            // LDS (the settled bitmap's place when that is in LDS; it is not
+            // needed past the distance rounds)
+            const int32_t Ld = w_layers<BLOCK>(p, sm, s, g, src, nreach, reinterpret_cast<int32_t *>(lds_bm), wsd, c);
             phase_end<BLOCK>(sm, kPhBu);
             phase_start<BLOCK>(sm);
             w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, c);

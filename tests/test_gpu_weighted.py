@@ -51,12 +51,13 @@ def test_weighted_exact_and_sampled(make, wmax, sym):
 @pytest.mark.parametrize("sym", [True, False])
 def test_weighted_with_and_without_relabelling(sym):
     """Degree relabelling (the default above 256 vertices) carries each
-    arc's weight to the renamed arc; flag 2 runs under the caller's ids."""
+    arc's weight to the renamed arc; flag 2 runs under the caller's ids,
+    flag 1 keeps the settled-vertex bitmap in global memory."""
     g = gg.rmat(12, 8, 50) if sym else gg.directed_rmat(12, 8, 51)
     w = gg.edge_weights(g, 12, 52, symmetric=sym)
     rp, ci = upload(g)
     ref = oracle.bc_weighted(g.rowptr, g.colidx, w, nthreads=8)
-    for flags in (0, 2):
+    for flags in (0, 1, 2, 3):
         nk.nk_set_tuning(flags=flags)
         assert_scores_close(nk.nk_bc_weighted(rp, ci, _dev(w)).cpu().numpy(), ref, f"flags={flags}")
 
