@@ -94,6 +94,7 @@ struct Params {
     int32_t *wl1;
     int32_t *wl2;              // far pile of the near-far distance rounds
     long long wdelta;          // threshold step of the near-far rounds (0: one bucket)
+    double *pacc;              // bisection: push accumulator of the truncated sweeps (kept at zero)
     uint32_t *dagm;            // per-slot bitmap over the arcs: shortest-path DAG arcs of
     long long dag_words;       // the current source (all clear between sources); words per slot
     // pair mode: 32-byte per-vertex records of both search sides (path

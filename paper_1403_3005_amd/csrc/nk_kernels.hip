@@ -68,6 +68,7 @@ struct Scr {
     int32_t *wl0, *wl1;         // weighted mode: worklists of the distance rounds
     int32_t *wl2;               // weighted mode: far pile
     uint32_t *dagm;             // weighted mode: DAG-arc bitmap over the arcs
+    double *pacc;               // bisection: push accumulator of the truncated sweeps
     unsigned long long *sigma;  // path counts; coef bits during the backward phase
     double *dacc;               // push-mode dependency sums (kept at zero between uses)
     int32_t *ldeg;              // degree sum of each level
@@ -534,11 +535,13 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // As in the full sweep, the visited bitmap tells the level below: on
 // entry every reached level is marked; levels T.. are cleared first and
 // each processed level after its pass, so an unmarked neighbour of level
-// j is on level j+1.  On exit dacc is clear and every level is marked
-// again.
+// j is on level j+1 and a marked neighbour of level j+1 is on level j.
+// Like the full sweep, a level whose successor level has far fewer arcs
+// is done by push from that level (sums in s.pacc, left at zero).  On exit
+// dacc is clear and every level is marked again.
 template <int BLOCK>
 __device__ void bis_sweep(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g, int32_t T, int32_t Ld,
-                          double *bcg, Counters &c) {
+                          double *bcg, float bw_ratio, Counters &c) {
     const int tid = threadIdx.x;
     const int32_t lmin = (T + 1) / 2;
     for (int32_t i = s.lvl[T] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_clear(bm, s.lv[i]);
@@ -549,6 +552,39 @@ __device__ void bis_sweep(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GVi
     __syncthreads();
     for (int32_t l = T - 1; l >= lmin; --l) {
         const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
+        if ((double)s.ldeg[l + 1] < (double)bw_ratio * (double)s.ldeg[l]) {
+            if (tid == 0) c.bw_push++;
+            const int32_t hi1 = s.lvl[l + 2];
+            for (int32_t tb = hi; tb < hi1; tb += BLOCK) {
+                const int32_t cnt = min(BLOCK, hi1 - tb);
+                if (tid < cnt) sm.val.f[tid] = s.dacc[s.lv[tb + tid]];
+                const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+                __syncthreads();
+                if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+                for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                    int32_t kk[kChunk], v[kChunk];
+                    load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
+#pragma unroll
+                    for (int j = 0; j < kChunk; ++j)
+                        if (kk[j] >= 0 && bit_test(bm, v[j])) atomicAdd(s.pacc + v[j], sm.val.f[kk[j]]);
+                }
+                __syncthreads();
+            }
+            for (int32_t i = lo + tid; i < hi; i += BLOCK) {
+                const int32_t v = s.lv[i];
+                const double sg = (double)s.sigma[v];
+                const double delta = sg * s.pacc[v];
+                s.pacc[v] = 0.0;
+                if (l > lmin)
+                    s.dacc[v] = (1.0 + delta) / sg;
+                else if (delta != 0.0)
+                    atomicAdd(bcg + v, 0.5 * delta);
+            }
+            __syncthreads();
+            for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
+            __syncthreads();
+            continue;
+        }
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
             if (tid < cnt) sm.val.f[tid] = 0.0;
@@ -604,7 +640,7 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     // sweep below overwrites with coefficients, so they run first
     if constexpr (BIS) {
         phase_start<BLOCK>(sm);
-        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, bm, s, g, T, Ld, bcg, c);
+        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, bm, s, g, T, Ld, bcg, p.bw_ratio, c);
         phase_end<BLOCK>(sm, kPhPull);
     }
     {
@@ -1528,6 +1564,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.wl1 = p.wl1 ? p.wl1 + off : nullptr;
     s.wl2 = p.wl2 ? p.wl2 + off : nullptr;
     s.dagm = p.dagm ? p.dagm + slot * p.dag_words : nullptr;
+    s.pacc = p.pacc ? p.pacc + off : nullptr;
     uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists

@@ -91,6 +91,28 @@ def test_bisect_exact_sources(make):
     assert_scores_close(got, oracle.bc_sources_bisect(g.rowptr, g.colidx, src, 2.0 * g.n / k), g.name + " sampled")
 
 
+@pytest.mark.parametrize("bw_ratio", [0.0, 0.1, 1e9])
+def test_bisect_sweep_directions(bw_ratio):
+    """The truncated sweeps by pull only (ratio 0), by the default choice,
+    and by push wherever a level has arcs (ratio 1e9)."""
+    nk.nk_set_tuning(bw_ratio=bw_ratio)
+    try:
+        for g in (gg.rmat(11, 8, 90), gg.barabasi_albert(2500, 2, 91),
+                  gg.disjoint_union([gg.grid(9, 13), gg.random_tree(700, 92), gg.path(40)])):
+            src = gg.sample_sources(g.n, 80, 93)
+            rp, ci = upload(g)
+            got = nk.nk_bc_sources_bisect(rp, ci, ivec(src), 2.0 * g.n / 80).cpu().numpy()
+            st = nk.nk_last_stats()
+            if bw_ratio > 1:
+                assert st["levels_bw_push"] > 0
+            if bw_ratio == 0.0:
+                assert st["levels_bw_push"] == 0
+            ref = oracle.bc_sources_bisect(g.rowptr, g.colidx, src, 2.0 * g.n / 80, nthreads=8)
+            assert_scores_close(got, ref, f"{g.name} bw_ratio={bw_ratio}")
+    finally:
+        nk.nk_set_tuning()
+
+
 def test_bisect_all_sources_is_half_of_exact_on_gpu():
     g = gg.barabasi_albert(3000, 3, 85)
     rp, ci = upload(g)
