@@ -684,12 +684,14 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 // Positive integer arc weights.  Per source: (1) distances by label-
 // correcting rounds: each round relaxes the out-arcs of the vertices whose
 // distance dropped in the previous round (64-bit atomicMin), queueing each
-// improved vertex once per round; (2) the shortest-path DAG (arcs with
-// dist_v + w = dist_x): in-degrees, then Kahn layers -- a vertex joins the
-// layer after the one holding its last predecessor, and each layer pushes
-// its path counts to its DAG successors -- so every DAG arc goes from a
-// layer to a later one; (3) the dependency pull over the layers in reverse
-// with the DAG test by distances.
+// improved vertex once per round, and marks every arc that ties or improves
+// its head's distance as a DAG candidate in the per-slot arc bitmap; (2) the
+// shortest-path DAG (arcs with dist_v + w = dist_x, tested on candidates
+// only, the others' bits dropped) in layers -- one per distance value, or
+// Kahn layers after an in-degree pass -- with each layer pushing its path
+// counts to its DAG successors, so every DAG arc goes from a layer to a
+// later one; (3) the dependency pull over the layers in reverse over the
+// arcs whose bits are set, clearing them.
 
 constexpr unsigned long long kInf = ~0ULL;
 
