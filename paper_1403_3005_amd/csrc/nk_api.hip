@@ -844,10 +844,11 @@ nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int
     LaunchPlan plan = {};
     float ms = 0.0f;
     if (k > 0) {
-        // near-far threshold step: a quarter of the mean arc weight (on
+        // near-far threshold step: an eighth of the mean arc weight (on
         // R-MAT-20 with weights 1..64 the distance rounds relaxed 2.1x the
         // reached arcs in one bucket, 1.8x at the mean weight, 1.25x at a
-        // quarter of it, and an eighth gained nothing more)
+        // quarter of it; with settled vertices skipped, an eighth (step 4)
+        // ran 5% faster than a quarter and a sixteenth (step 2) 2% slower)
         long long wdelta = 0;
         if (m > 0) {
             unsigned long long *wsum;
@@ -857,7 +858,7 @@ nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int
             unsigned long long hsum = 0;
             NK_HIP(hipMemcpyAsync(&hsum, wsum, 8, hipMemcpyDeviceToHost, s));
             NK_HIP(hipStreamSynchronize(s));
-            wdelta = (long long)(hsum / (unsigned long long)m) / 4;
+            wdelta = (long long)(hsum / (unsigned long long)m) / 8;
             if (wdelta < 1) wdelta = 1;
         }
         // degree order, with the weights carried to the renamed arcs
