@@ -355,9 +355,11 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         // lists) + 4 (meeting list); otherwise 8 + 8 + 7 x 4 and a global
         // bitmap when it does not sit in LDS
         // weighted: + u64 distances, round marks, two worklists and the far pile (24)
-        // bisection: + the truncated sweeps' push accumulator (8)
-        size_t per_slot =
-            (size_t)stride * (mode == kModePair ? 68 : mode == kModeWeighted ? 68 : mode == kModeBisect ? 52 : 44);
+        // bisection: + kBisK cutoff coefficients per vertex
+        size_t per_slot = (size_t)stride * (mode == kModePair       ? 68
+                                            : mode == kModeWeighted ? 68
+                                            : mode == kModeBisect   ? 44 + 8 * kBisK
+                                                                    : 44);
         if (mode != kModePair && !lds) per_slot += (size_t)wordsr * 4;
         // weighted: one bit per arc marks the shortest-path DAG
         if (mode == kModeWeighted) per_slot += (size_t)dag_words_of(m_arcs) * 4;
@@ -447,7 +449,7 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
     p.wl0 = p.wl1 = p.wl2 = nullptr;
     p.dagm = nullptr;
     p.dag_words = plan.dag_words;
-    p.pacc = nullptr;
+    p.bvec = nullptr;
     if ((st = scr.get(cells, &p.dacc)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
@@ -479,7 +481,7 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
             if ((st = scr.get(slots * plan.dag_words, &p.dagm)) != NK_OK) return st;
         }
         if (plan.mode == kModeBisect)
-            if ((st = scr.get(cells, &p.pacc)) != NK_OK) return st;
+            if ((st = scr.get(cells * kBisK, &p.bvec)) != NK_OK) return st;
         if (!plan.lds)
             if ((st = scr.get(slots * plan.bm_words, &p.bmg)) != NK_OK) return st;
     }
@@ -503,7 +505,6 @@ nk_status persistent_enqueue(const LaunchPlan &plan, const Params &p, hipStream_
         NK_HIP(launch_fill_u64(p.sigma, 0ULL, cells, s));
         // the push accumulator of the dependency sweep must start at zero
         if (plan.mode == kModeBC || plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.dacc, 0.0, cells, s));
-        if (plan.mode == kModeBisect) NK_HIP(launch_fill_f64(p.pacc, 0.0, cells, s));
     }
     if (ev0) NK_HIP(hipEventRecord(ev0, s));
     plan.kernel.launch(dim3(plan.grid), dim3(plan.block), plan.dyn_lds, s, p);

@@ -23,6 +23,10 @@ enum Mode : int {
 // histogram takes kDistBuckets ints of dynamic LDS.
 constexpr int kDistBuckets = 4096;
 
+// Bisection: cutoff depths served by one truncated pass (coefficients per
+// vertex; one vector fills an aligned line of 8 * kBisK bytes).
+constexpr int kBisK = 4;
+
 // Everything a persistent launch reads.  Per-slot scratch arrays hold
 // `stride` elements per workgroup slot (slot = blockIdx.x).
 struct Params {
@@ -94,7 +98,7 @@ struct Params {
     int32_t *wl1;
     int32_t *wl2;              // far pile of the near-far distance rounds
     long long wdelta;          // threshold step of the near-far rounds (0: one bucket)
-    double *pacc;              // bisection: push accumulator of the truncated sweeps (kept at zero)
+    double *bvec;              // bisection: kBisK cutoff coefficients per vertex (kBisK * stride per slot)
     uint32_t *dagm;            // per-slot bitmap over the arcs: shortest-path DAG arcs of
     long long dag_words;       // the current source (all clear between sources); words per slot
     // pair mode: 32-byte per-vertex records of both search sides (path

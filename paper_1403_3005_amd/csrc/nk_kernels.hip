@@ -68,7 +68,7 @@ struct Scr {
     int32_t *wl0, *wl1;         // weighted mode: worklists of the distance rounds
     int32_t *wl2;               // weighted mode: far pile
     uint32_t *dagm;             // weighted mode: DAG-arc bitmap over the arcs
-    double *pacc;               // bisection: push accumulator of the truncated sweeps
+    double *bvec;               // bisection: kBisK cutoff coefficients per vertex
     unsigned long long *sigma;  // path counts; coef bits during the backward phase
     double *dacc;               // push-mode dependency sums (kept at zero between uses)
     int32_t *ldeg;              // degree sum of each level
@@ -527,37 +527,57 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
     __syncthreads();
 }
 
-// Bisection estimator, one cutoff depth T (2 <= T < Ld): delta^T counts
-// only targets at depth <= T.  A vertex on level l takes half of
-// delta^(2l-1) and half of delta^(2l), so this sweep serves level
-// ceil(T/2) only and runs from level T-1 up to it.  The targets' inverse
-// path counts and then (1 + delta^T) / sigma sit in dacc (zero elsewhere).
-// As in the full sweep, the visited bitmap tells the level below: on
-// entry every reached level is marked; levels T.. are cleared first and
-// each processed level after its pass, so an unmarked neighbour of level
-// j is on level j+1 and a marked neighbour of level j+1 is on level j.
-// Like the full sweep, a level whose successor level has far fewer arcs
-// is done by push from that level (sums in s.pacc, left at zero).  On exit
-// dacc is clear and every level is marked again.
+// Bisection estimator, truncated dependencies: delta^T (2 <= T < Ld)
+// counts only targets at depth <= T, and a vertex on level l takes half of
+// delta^(2l-1) and half of delta^(2l).  Cutoff T therefore needs the levels
+// T-1 down to lmin(T) = ceil(T/2) only.  One pass serves a group of up to
+// kBisK consecutive cutoffs T0..T1: every vertex keeps a vector of kBisK
+// coefficients (one 32-byte line, slot T - T0) in s.bvec -- 1/sigma when
+// it sits on level T itself (the targets), (1 + delta^T)/sigma above it --
+// and level l is scanned once for all cutoffs active there (l < T <= 2l).
+// A vertex on level lmin(T) adds delta^T / 2 to its score instead.
+// As in the full sweep, the visited bitmap tells the level below: on entry
+// every reached level is marked; levels T1.. are cleared first and each
+// processed level after its pass, so an unmarked neighbour of level l is on
+// level l+1 and a marked neighbour of level l+1 is on level l.  A level
+// whose successor level has far fewer arcs is done by push from that level
+// (its sums built in the same vector slots, cleared first).  Every slot a
+// pass reads was written earlier in the same pass.  On exit every level is
+// marked again.
+
 template <int BLOCK>
-__device__ void bis_sweep(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g, int32_t T, int32_t Ld,
-                          double *bcg, float bw_ratio, Counters &c) {
+__device__ void bis_group(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GView &g, int32_t T0, int32_t T1,
+                          int32_t Ld, double *bcg, float bw_ratio, Counters &c) {
+    constexpr int TV = BLOCK / kBisK;   // vertices per tile: their sums fill sm.val.f
     const int tid = threadIdx.x;
-    const int32_t lmin = (T + 1) / 2;
-    for (int32_t i = s.lvl[T] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_clear(bm, s.lv[i]);
-    for (int32_t i = s.lvl[T] + tid; i < s.lvl[T + 1]; i += BLOCK) {
+    const int32_t lmin0 = (T0 + 1) / 2;
+    double *vec = s.bvec;
+    for (int32_t i = s.lvl[T1] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_clear(bm, s.lv[i]);
+    for (int32_t i = s.lvl[T1] + tid; i < s.lvl[T1 + 1]; i += BLOCK) {
         const int32_t w = s.lv[i];
-        s.dacc[w] = 1.0 / (double)s.sigma[w];
+        vec[(long long)w * kBisK + (T1 - T0)] = 1.0 / (double)s.sigma[w];
     }
     __syncthreads();
-    for (int32_t l = T - 1; l >= lmin; --l) {
+    for (int32_t l = T1 - 1; l >= lmin0; --l) {
         const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
-        if ((double)s.ldeg[l + 1] < (double)bw_ratio * (double)s.ldeg[l]) {
+        // active cutoffs at level l: slots qa..qb
+        const int qa = max(T0, l + 1) - T0, qb = min(T1, 2 * l) - T0;
+        const bool seed = l >= T0;   // level l holds the targets of cutoff T = l
+        const bool push = (double)s.ldeg[l + 1] < (double)bw_ratio * (double)s.ldeg[l];
+        if (push) {
             if (tid == 0) c.bw_push++;
+            for (int32_t i = lo + tid; i < hi; i += BLOCK) {
+                double *x = vec + (long long)s.lv[i] * kBisK;
+                for (int q = qa; q <= qb; ++q) x[q] = 0.0;
+            }
+            __syncthreads();
             const int32_t hi1 = s.lvl[l + 2];
-            for (int32_t tb = hi; tb < hi1; tb += BLOCK) {
-                const int32_t cnt = min(BLOCK, hi1 - tb);
-                if (tid < cnt) sm.val.f[tid] = s.dacc[s.lv[tb + tid]];
+            for (int32_t tb = hi; tb < hi1; tb += TV) {
+                const int32_t cnt = min(TV, hi1 - tb);
+                if (tid < cnt * kBisK) {
+                    const int32_t r = tid / kBisK, q = tid % kBisK;
+                    sm.val.f[tid] = (q >= qa && q <= qb) ? vec[(long long)s.lv[tb + r] * kBisK + q] : 0.0;
+                }
                 const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
                 __syncthreads();
                 if (tid == 0) c.arcs_bwd += (unsigned long long)total;
@@ -566,68 +586,90 @@ __device__ void bis_sweep(Tile<BLOCK> &sm, uint32_t *bm, const Scr &s, const GVi
                     load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
 #pragma unroll
                     for (int j = 0; j < kChunk; ++j)
-                        if (kk[j] >= 0 && bit_test(bm, v[j])) atomicAdd(s.pacc + v[j], sm.val.f[kk[j]]);
+                        if (kk[j] >= 0 && bit_test(bm, v[j]))
+                            for (int q = qa; q <= qb; ++q)
+                                atomicAdd(vec + (long long)v[j] * kBisK + q, sm.val.f[kk[j] * kBisK + q]);
                 }
                 __syncthreads();
             }
             for (int32_t i = lo + tid; i < hi; i += BLOCK) {
                 const int32_t v = s.lv[i];
+                double *x = vec + (long long)v * kBisK;
                 const double sg = (double)s.sigma[v];
-                const double delta = sg * s.pacc[v];
-                s.pacc[v] = 0.0;
-                if (l > lmin)
-                    s.dacc[v] = (1.0 + delta) / sg;
-                else if (delta != 0.0)
-                    atomicAdd(bcg + v, 0.5 * delta);
-            }
-            __syncthreads();
-            for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
-            __syncthreads();
-            continue;
-        }
-        for (int32_t tb = lo; tb < hi; tb += BLOCK) {
-            const int32_t cnt = min(BLOCK, hi - tb);
-            if (tid < cnt) sm.val.f[tid] = 0.0;
-            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
-            __syncthreads();
-            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
-            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                int32_t kk[kChunk], w[kChunk];
-                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
-                double cf[kChunk];
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) cf[j] = (kk[j] >= 0 && !bit_test(bm, w[j])) ? s.dacc[w[j]] : 0.0;
-                int32_t kcur = kk[0];
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    if (kk[j] < 0) continue;
-                    if (kk[j] != kcur) {
-                        if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
-                        kcur = kk[j];
-                        acc = 0.0;
-                    }
-                    acc += cf[j];
+                double add = 0.0;
+                for (int q = qa; q <= qb; ++q) {
+                    const double delta = sg * x[q];
+                    if (l > (T0 + q + 1) / 2)
+                        x[q] = (1.0 + delta) / sg;
+                    else
+                        add += 0.5 * delta;
                 }
-                if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                if (seed) x[l - T0] = 1.0 / sg;
+                if (add != 0.0) atomicAdd(bcg + v, add);
             }
             __syncthreads();
-            if (tid < cnt) {
-                const int32_t v = sm.v[tid];
-                const double sg = (double)s.sigma[v];
-                const double delta = sg * sm.val.f[tid];
-                if (l > lmin)
-                    s.dacc[v] = (1.0 + delta) / sg;
-                else if (delta != 0.0)
-                    atomicAdd(bcg + v, 0.5 * delta);
+        } else {
+            for (int32_t tb = lo; tb < hi; tb += TV) {
+                const int32_t cnt = min(TV, hi - tb);
+                if (tid < cnt * kBisK) sm.val.f[tid] = 0.0;
+                const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+                __syncthreads();
+                if (tid == 0) c.arcs_bwd += (unsigned long long)total;
+                for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+                    int32_t kk[kChunk], w[kChunk];
+                    load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+                    int32_t kcur = kk[0];
+                    double acc[kBisK] = {};
+#pragma unroll
+                    for (int j = 0; j < kChunk; ++j) {
+                        if (kk[j] < 0) continue;
+                        if (kk[j] != kcur) {
+#pragma unroll
+                            for (int q = 0; q < kBisK; ++q)
+                                if (acc[q] != 0.0) atomicAdd(&sm.val.f[kcur * kBisK + q], acc[q]);
+                            kcur = kk[j];
+#pragma unroll
+                            for (int q = 0; q < kBisK; ++q) acc[q] = 0.0;
+                        }
+                        if (!bit_test(bm, w[j])) {
+                            // the vector is one aligned line: 16-byte loads
+                            const double2 *x = reinterpret_cast<const double2 *>(vec + (long long)w[j] * kBisK);
+#pragma unroll
+                            for (int h = 0; h < kBisK / 2; ++h) {
+                                const double2 y = x[h];
+                                if (2 * h >= qa && 2 * h <= qb) acc[2 * h] += y.x;
+                                if (2 * h + 1 >= qa && 2 * h + 1 <= qb) acc[2 * h + 1] += y.y;
+                            }
+                        }
+                    }
+                    if (kcur >= 0)
+#pragma unroll
+                        for (int q = 0; q < kBisK; ++q)
+                            if (acc[q] != 0.0) atomicAdd(&sm.val.f[kcur * kBisK + q], acc[q]);
+                }
+                __syncthreads();
+                if (tid < cnt) {
+                    const int32_t v = sm.v[tid];
+                    double *x = vec + (long long)v * kBisK;
+                    const double sg = (double)s.sigma[v];
+                    double add = 0.0;
+                    for (int q = qa; q <= qb; ++q) {
+                        const double delta = sg * sm.val.f[tid * kBisK + q];
+                        if (l > (T0 + q + 1) / 2)
+                            x[q] = (1.0 + delta) / sg;
+                        else
+                            add += 0.5 * delta;
+                    }
+                    if (seed) x[l - T0] = 1.0 / sg;
+                    if (add != 0.0) atomicAdd(bcg + v, add);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
         for (int32_t i = lo + tid; i < hi; i += BLOCK) bit_clear(bm, s.lv[i]);
         __syncthreads();
     }
-    for (int32_t i = s.lvl[lmin + 1] + tid; i < s.lvl[T + 1]; i += BLOCK) s.dacc[s.lv[i]] = 0.0;
-    for (int32_t i = s.lvl[lmin] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_set(bm, s.lv[i]);
+    for (int32_t i = s.lvl[lmin0] + tid; i < s.lvl[Ld + 1]; i += BLOCK) bit_set(bm, s.lv[i]);
     __syncthreads();
 }
 
@@ -640,7 +682,8 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
     // sweep below overwrites with coefficients, so they run first
     if constexpr (BIS) {
         phase_start<BLOCK>(sm);
-        for (int32_t T = 2; T < Ld; ++T) bis_sweep<BLOCK>(sm, bm, s, g, T, Ld, bcg, p.bw_ratio, c);
+        for (int32_t T0 = 2; T0 < Ld; T0 += kBisK)
+            bis_group<BLOCK>(sm, bm, s, g, T0, min(T0 + kBisK - 1, Ld - 1), Ld, bcg, p.bw_ratio, c);
         phase_end<BLOCK>(sm, kPhPull);
     }
     {
@@ -1566,7 +1609,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.wl1 = p.wl1 ? p.wl1 + off : nullptr;
     s.wl2 = p.wl2 ? p.wl2 + off : nullptr;
     s.dagm = p.dagm ? p.dagm + slot * p.dag_words : nullptr;
-    s.pacc = p.pacc ? p.pacc + off : nullptr;
+    s.bvec = p.bvec ? p.bvec + off * kBisK : nullptr;
     uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists

@@ -113,6 +113,23 @@ def test_bisect_sweep_directions(bw_ratio):
         nk.nk_set_tuning()
 
 
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_bisect_block_sizes_deep_graph(block):
+    """Cutoff groups of every block size (tiles of block/4 vertices) on a
+    graph deep enough for several groups."""
+    nk.nk_set_tuning(block=block)
+    try:
+        g = gg.disjoint_union([gg.barabasi_albert(1500, 2, 94), gg.path(60), gg.grid(5, 40)])
+        src = gg.sample_sources(g.n, 120, 95)
+        rp, ci = upload(g)
+        got = nk.nk_bc_sources_bisect(rp, ci, ivec(src), 2.0 * g.n / 120).cpu().numpy()
+        assert nk.nk_last_stats()["block"] == block
+        ref = oracle.bc_sources_bisect(g.rowptr, g.colidx, src, 2.0 * g.n / 120, nthreads=8)
+        assert_scores_close(got, ref, f"block {block}")
+    finally:
+        nk.nk_set_tuning()
+
+
 def test_bisect_all_sources_is_half_of_exact_on_gpu():
     g = gg.barabasi_albert(3000, 3, 85)
     rp, ci = upload(g)
