@@ -170,6 +170,45 @@ __device__ __forceinline__ void candidate_rows(const Tile<BLOCK> &sm, int32_t cn
     }
 }
 
+// Word-granular staging of the level list [tb, tb + cnt): row k's arc range
+// is [sm.a0[k], ends[k]), and sm.pre holds the exclusive prefix of the
+// 32-arc bitmap words each range touches (sm.pre[cnt] = total words, the
+// return value).  deg: the thread's row length (0 past cnt).  Callers that
+// need the vertex ids stage them themselves.
+template <int BLOCK>
+__device__ __forceinline__ int32_t stage_words(Tile<BLOCK> &sm, const Scr &s, int32_t tb, int32_t cnt, int32_t *ends,
+                                               int32_t &deg) {
+    const int tid = threadIdx.x;
+    int32_t wc = 0;
+    deg = 0;
+    if (tid < cnt) {
+        const int32_t a0 = s.la[tb + tid];
+        deg = s.ld[tb + tid];
+        sm.a0[tid] = a0;
+        ends[tid] = a0 + deg;
+        wc = deg > 0 ? ((a0 + deg - 1) >> 5) - (a0 >> 5) + 1 : 0;
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<BLOCK>(wc, sm, total);
+    if (tid < cnt) sm.pre[tid] = ex;
+    if (tid == 0) sm.pre[cnt] = total;
+    return total;
+}
+
+// Word wi of a word-staged tile: its row k, the word's index W in the arc
+// bitmap, and the mask of the bits that belong to row k's arcs.
+template <int BLOCK>
+__device__ __forceinline__ void tile_word(const Tile<BLOCK> &sm, const int32_t *ends, int32_t cnt, int32_t wi,
+                                          int32_t &k, long long &W, uint32_t &range) {
+    k = tile_search(sm.pre, cnt, wi);
+    const int32_t a0 = sm.a0[k], a1 = ends[k];
+    W = (long long)(a0 >> 5) + (wi - sm.pre[k]);
+    const long long base = W * 32;
+    const int32_t blo = a0 > base ? (int32_t)(a0 - base) : 0;
+    const int32_t bhi = (long long)a1 - base < 32 ? (int32_t)(a1 - base) : 32;
+    range = (bhi >= 32 ? ~0u : ((1u << bhi) - 1u)) & ~((1u << blo) - 1u);
+}
+
 // ---------------------------------------------------------------- forward --
 
 // Top-down expansion of level `lvl` (list[f0, f1)) into list[f1, ...).
@@ -1051,30 +1090,27 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
         if (tid == 0) c.bu++;
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
-            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
             if (tid < cnt) {
-                sd[tid] = s.dist[sm.v[tid]];
-                sm.val.u[tid] = s.sigma[sm.v[tid]];
+                const int32_t v = s.lv[tb + tid];
+                sd[tid] = s.dist[v];
+                sm.val.u[tid] = s.sigma[v];
             }
+            // the rows' ends take the place of the vertex ids
+            int32_t deg;
+            const int32_t total = stage_words<BLOCK>(sm, s, tb, cnt, sm.v, deg);
             __syncthreads();
-            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                int32_t kk[kChunk];
-                int32_t word = -1;
-                uint32_t wv = 0u, drop = 0u;
-                candidate_rows<BLOCK>(sm, cnt, total, rb + tid * kChunk, kk);
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    if (kk[j] < 0) continue;
-                    const int32_t k = kk[j];
-                    const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                    if ((arc >> 5) != word) {
-                        if (drop) atomicAnd(&s.dagm[word], ~drop);
-                        word = arc >> 5;
-                        wv = s.dagm[word];
-                        drop = 0u;
-                    }
-                    const uint32_t bit = 1u << (arc & 31);
-                    if (!(wv & bit)) continue;
+            // a thread per bitmap word: only candidate arcs are looked at
+            for (int32_t wi = tid; wi < total; wi += BLOCK) {
+                int32_t k;
+                long long W;
+                uint32_t bits;
+                tile_word<BLOCK>(sm, sm.v, cnt, wi, k, W, bits);
+                bits &= s.dagm[W];
+                uint32_t drop = 0u;
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const int32_t arc = (int32_t)(W * 32 + b);
                     const int32_t x = g.ci[arc];
                     if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[x]) {
                         const unsigned long long add = sm.val.u[k];
@@ -1082,10 +1118,10 @@ __device__ int32_t w_layers_buckets(const Params &p, Tile<BLOCK> &sm, const Scr 
                         if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
                         c.dag++;
                     } else {
-                        drop |= bit;
+                        drop |= 1u << b;
                     }
                 }
-                if (drop) atomicAnd(&s.dagm[word], ~drop);
+                if (drop) atomicAnd(&s.dagm[W], ~drop);
             }
             __syncthreads();
         }
@@ -1130,7 +1166,7 @@ __device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, cons
 // the sweep reads no distances and no weights.
 template <int BLOCK>
 __device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t Ld, double *bcg,
-                           Counters &c) {
+                           int32_t *ends, Counters &c) {
     const int tid = threadIdx.x;
     if (Ld == 0) return;
     for (int32_t i = s.lvl[Ld] + tid; i < s.lvl[Ld + 1]; i += BLOCK) {
@@ -1142,54 +1178,31 @@ __device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const
         const int32_t lo = s.lvl[l], hi = s.lvl[l + 1];
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
-            if (tid < cnt) sm.val.f[tid] = 0.0;
-            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+            if (tid < cnt) {
+                sm.val.f[tid] = 0.0;
+                sm.v[tid] = s.lv[tb + tid];
+            }
+            int32_t deg;
+            const int32_t total = stage_words<BLOCK>(sm, s, tb, cnt, ends, deg);
             __syncthreads();
-            if (tid == 0) c.arcs_bwd += (unsigned long long)total;
-            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                // the DAG bitmap picks the arcs: only those load their head
-                // and its coefficient; their bits are cleared on the way
-                const int32_t i0 = rb + tid * kChunk;
-                int32_t kk[kChunk];
-                double cf[kChunk];
-                int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
-                int32_t word = -1;
-                uint32_t wv = 0u, bits = 0u;
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    const int32_t i = i0 + j;
-                    kk[j] = -1;
-                    cf[j] = 0.0;
-                    if (i < total) {
-                        while (sm.pre[k + 1] <= i) ++k;
-                        kk[j] = k;
-                        const int32_t arc = sm.a0[k] + (i - sm.pre[k]);
-                        if ((arc >> 5) != word) {
-                            if (bits) atomicAnd(&s.dagm[word], ~bits);
-                            word = arc >> 5;
-                            wv = s.dagm[word];
-                            bits = 0u;
-                        }
-                        if ((wv >> (arc & 31)) & 1u) {
-                            bits |= 1u << (arc & 31);
-                            cf[j] = as_f64(s.sigma[g.ci[arc]]);
-                        }
-                    }
-                }
-                if (bits) atomicAnd(&s.dagm[word], ~bits);
-                int32_t kcur = kk[0];
+            c.arcs_bwd += (unsigned long long)deg;
+            // a thread per bitmap word: the DAG arcs load their head's
+            // coefficient; their bits are cleared on the way
+            for (int32_t wi = tid; wi < total; wi += BLOCK) {
+                int32_t k;
+                long long W;
+                uint32_t bits;
+                tile_word<BLOCK>(sm, ends, cnt, wi, k, W, bits);
+                bits &= s.dagm[W];
+                if (bits == 0u) continue;
+                atomicAnd(&s.dagm[W], ~bits);
                 double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    if (kk[j] < 0) continue;
-                    if (kk[j] != kcur) {
-                        if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
-                        kcur = kk[j];
-                        acc = 0.0;
-                    }
-                    acc += cf[j];
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    acc += as_f64(s.sigma[g.ci[(int32_t)(W * 32 + b)]]);
                 }
-                if (acc != 0.0) atomicAdd(&sm.val.f[kcur], acc);
+                atomicAdd(&sm.val.f[k], acc);
             }
             __syncthreads();
             if (tid < cnt) {
@@ -1709,7 +1722,9 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             const int32_t Ld = w_layers<BLOCK>(p, sm, s, g, src, nreach, reinterpret_cast<int32_t *>(lds_bm), wsd, c);
             phase_end<BLOCK>(sm, kPhBu);
             phase_start<BLOCK>(sm);
-            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, c);
+            // the rows' ends of the sweep's tiles go where the staged
+            // distances were
+            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, reinterpret_cast<int32_t *>(wsd), c);
             phase_end<BLOCK>(sm, kPhPull);
             phase_start<BLOCK>(sm);
             for (int32_t i = tid; i < nreach; i += BLOCK) {
@@ -1778,11 +1793,13 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     // counters: wave sums, one atomic per wave and counter
     unsigned long long dag = wave_sum<unsigned long long>(c.dag);
     if (lane_id() == 0) atomicAdd(&p.st->stat[kStDag], dag);
+    // (every thread of the weighted sweep counts its own rows' arcs)
+    unsigned long long abw = wave_sum<unsigned long long>(c.arcs_bwd);
+    if (lane_id() == 0) atomicAdd(&p.st->stat[kStArcsBwd], abw);
     if (tid == 0) {
         atomicAdd(&p.st->stat[kStSources], c.tasks);
         atomicAdd(&p.st->stat[kStReached], c.reached);
         atomicAdd(&p.st->stat[kStArcsFwd], c.arcs_fwd);
-        atomicAdd(&p.st->stat[kStArcsBwd], c.arcs_bwd);
         atomicAdd(&p.st->stat[kStTd], c.td);
         atomicAdd(&p.st->stat[kStBu], c.bu);
         atomicAdd(&p.st->stat[kStArcsReached], c.arcs_reached);
