@@ -134,6 +134,26 @@ __device__ __forceinline__ int32_t stage_list(Tile<BLOCK> &sm, const Scr &s, int
     return total;
 }
 
+// Stages list[tb, tb+cnt) (vertex ids) with their arc ranges in g.
+template <int BLOCK>
+__device__ __forceinline__ int32_t stage_ids(Tile<BLOCK> &sm, const int32_t *list, const GView &g, int32_t tb,
+                                             int32_t cnt) {
+    const int tid = threadIdx.x;
+    int32_t dg = 0;
+    if (tid < cnt) {
+        const int32_t v = list[tb + tid];
+        const int32_t a0 = g.rp[v];
+        sm.v[tid] = v;
+        sm.a0[tid] = a0;
+        dg = g.rp[v + 1] - a0;
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
+    if (tid < cnt) sm.pre[tid] = ex;
+    if (tid == 0) sm.pre[cnt] = total;
+    return total;
+}
+
 // Column indices of the thread's chunk [i0, i0 + kChunk) of the tile's arcs;
 // kk[j] = tile row of arc j, or -1 past the end.
 template <int BLOCK>
@@ -536,14 +556,19 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // Level l by push: every vertex w of level l+1 (list[lo1, hi1)) adds its
 // coef to dacc of its marked (= level l) neighbours; then each vertex v of
 // level l (list[lo, hi)) takes delta_v = sigma_v * dacc[v] and clears dacc.
+// A directed graph pushes over the in-arcs (g is then the in-arc view: an
+// in-neighbour of level l+1 is on level l or deeper, so a marked one is on
+// level l) and skips the vertices no search reaches (`iso`, in-degree 0),
+// which stay marked.
 template <int BLOCK>
 __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
-                        int32_t lo1, int32_t hi1, double *bcg, double wfac, double owt, Counters &c) {
+                        int32_t lo1, int32_t hi1, double *bcg, double wfac, double owt, bool in_arcs,
+                        const uint32_t *iso, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t tb = lo1; tb < hi1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, hi1 - tb);
         if (tid < cnt) sm.val.f[tid] = as_f64(s.sigma[s.lv[tb + tid]]);
-        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+        const int32_t total = in_arcs ? stage_ids<BLOCK>(sm, s.lv, g, tb, cnt) : stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_bwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
@@ -551,7 +576,8 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
             load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
 #pragma unroll
             for (int j = 0; j < kChunk; ++j)
-                if (kk[j] >= 0 && bit_test(bm, v[j])) atomicAdd(s.dacc + v[j], sm.val.f[kk[j]]);
+                if (kk[j] >= 0 && bit_test(bm, v[j]) && !(iso && bit_test(iso, v[j])))
+                    atomicAdd(s.dacc + v[j], sm.val.f[kk[j]]);
         }
         __syncthreads();
     }
@@ -745,13 +771,22 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         // bisection: level l takes the full dependency once for each of the
         // depths 2l-1, 2l that reach the deepest level Ld
         const double owt = BIS ? 0.5 * ((2 * l - 1 >= Ld ? 1.0 : 0.0) + (2 * l >= Ld ? 1.0 : 0.0)) : 1.0;
-        // scan whichever side of the level pair has fewer arcs
-        // (a push scans in-arcs, which a directed run may not have)
-        const bool push = !p.ebc && !p.directed && (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
+        // scan whichever side of the level pair has fewer arcs (a push
+        // scans in-arcs, which a directed run has only with the in-arc CSR;
+        // its level degree sums count out-arcs, the proxy used there too)
+        const bool push = !p.ebc && (!p.directed || p.trowptr) &&
+                          (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
         phase_start<BLOCK>(sm);
         if (push) {
             if (tid == 0) c.bw_push++;
-            bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, owt, c);
+            if (p.directed) {
+                GView gin = g;
+                gin.rp = g.trp;
+                gin.ci = g.tci;
+                bw_push<BLOCK>(sm, bm, s, gin, lo, hi, hi, hi1, bcg, wfac, owt, true, p.iso, c);
+            } else {
+                bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, owt, false, nullptr, c);
+            }
         } else {
             bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, wfac, owt, p.ebc, l >= 1, c);
         }
@@ -776,26 +811,6 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
 // arcs whose bits are set, clearing them.
 
 constexpr unsigned long long kInf = ~0ULL;
-
-// Stages list[tb, tb+cnt) (vertex ids) with their out-arc ranges.
-template <int BLOCK>
-__device__ __forceinline__ int32_t stage_ids(Tile<BLOCK> &sm, const int32_t *list, const GView &g, int32_t tb,
-                                             int32_t cnt) {
-    const int tid = threadIdx.x;
-    int32_t dg = 0;
-    if (tid < cnt) {
-        const int32_t v = list[tb + tid];
-        const int32_t a0 = g.rp[v];
-        sm.v[tid] = v;
-        sm.a0[tid] = a0;
-        dg = g.rp[v + 1] - a0;
-    }
-    int32_t total;
-    const int32_t ex = block_excl_scan<BLOCK>(dg, sm, total);
-    if (tid < cnt) sm.pre[tid] = ex;
-    if (tid == 0) sm.pre[cnt] = total;
-    return total;
-}
 
 // Distances from src; returns the number of reached vertices, listed in
 // s.cand.  ep: the workgroup's round counter (never repeats in a launch).

@@ -76,6 +76,37 @@ def test_directed_bottom_up_variants(bu_ratio, block):
     assert_scores_close(got, oracle.bc_directed(g.rowptr, g.colidx, src), "drmat13 variant")
 
 
+@pytest.mark.parametrize("bw_ratio", [0.0, 0.1, 1e9])
+@pytest.mark.parametrize("flags", [0, 2])
+def test_directed_sweep_push_over_in_arcs(bw_ratio, flags):
+    """The dependency sweep by pull only, by the default choice, and by push
+    over in-arcs wherever a level has arcs, on a graph with many vertices of
+    in-degree 0 that have out-arcs (marked unreachable, never pushed to),
+    relabelled and not."""
+    nk.nk_set_tuning(bw_ratio=bw_ratio, flags=flags | 4)
+    g = gg.directed_rmat(12, 6, 27)
+    rng = np.random.default_rng(28)
+    # 300 extra vertices with out-arcs only
+    extra_u = np.repeat(np.arange(g.n, g.n + 300), 3)
+    extra_v = rng.integers(0, g.n, extra_u.size)
+    src_u, src_v = [], []
+    for u in range(g.n):
+        for e in range(g.rowptr[u], g.rowptr[u + 1]):
+            src_u.append(u)
+            src_v.append(int(g.colidx[e]))
+    h = gg.directed_from_arcs(g.n + 300, np.concatenate([src_u, extra_u]), np.concatenate([src_v, extra_v]), "drmat12+sources")
+    t = gg.transpose(h)
+    rp, ci = upload(h)
+    src = np.concatenate([gg.sample_sources(g.n, 150, 29), np.arange(g.n, g.n + 20)]).astype(np.int32)
+    got = nk.nk_bc_directed(rp, ci, ivec(src), 1.0, _dev(t.rowptr), _dev(t.colidx)).cpu().numpy()
+    st = nk.nk_last_stats()
+    if bw_ratio > 1e6:
+        assert st["levels_bw_push"] > 0
+    if bw_ratio == 0.0:
+        assert st["levels_bw_push"] == 0
+    assert_scores_close(got, oracle.bc_directed(h.rowptr, h.colidx, src, nthreads=8), f"push {bw_ratio} flags {flags}")
+
+
 def test_symmetric_directed_equals_undirected():
     g = gg.barabasi_albert(4000, 3, 26)
     rp, ci = upload(g)
