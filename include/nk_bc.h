@@ -158,8 +158,10 @@ nk_status nk_bc_sources_bisect(const int32_t *rowptr, const int32_t *colidx, int
  *   sources, k, scale  as nk_bc_sources (NULL with k = n: every vertex, the
  *                      exact scores);
  *   bc                 FP64[n] DEVICE, overwritten.
- * The dependency sweep always pulls over out-arcs.  The graph keeps its own
- * ids (no degree relabelling).  Same errors as nk_bc_sources.
+ * The dependency sweep pulls over out-arcs or, with the in-arc CSR, pushes
+ * over in-arcs where the next level is much smaller.  The run renames the
+ * vertices by out-degree internally (scores come back by the caller's ids).
+ * Same errors as nk_bc_sources.
  */
 nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int32_t *trowptr,
                          const int32_t *tcolidx, int32_t n, int64_t m, const int32_t *sources, int32_t k,
@@ -179,7 +181,9 @@ nk_status nk_bc_directed(const int32_t *rowptr, const int32_t *colidx, const int
  *                   (NK_E_INVALID_GRAPH otherwise); distances are 64-bit;
  *   sources, k, scale, bc  as nk_bc_sources (NULL with k = n: exact).
  * Integer weights keep "d(s, v) + w = d(s, x)" exact on both sides of a
- * comparison.  The graph keeps its ids.  Same errors as nk_bc_sources.
+ * comparison.  The run renames the vertices by out-degree internally,
+ * carrying each arc's weight along (scores come back by the caller's ids).
+ * Same errors as nk_bc_sources.
  */
 nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int32_t *weights, int32_t n,
                          int64_t m, const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
@@ -206,8 +210,9 @@ nk_status nk_transpose(const int32_t *rowptr, const int32_t *colidx, int32_t n, 
  *   bc       FP64[n] DEVICE or NULL: the vertex scores of the same run,
  *            times `scale`.
  * Needs the reverse of every arc and ascending adjacency (the CSR rules
- * above); a missing reverse arc is NK_E_INVALID_GRAPH.  Runs under the
- * caller's vertex ids (no internal relabelling).
+ * above); a missing reverse arc is NK_E_INVALID_GRAPH.  The run renames the
+ * vertices by degree internally; edge and vertex scores come back in the
+ * caller's arc order and vertex ids.
  */
 nk_status nk_edge_bc(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
                      int32_t k, double scale, double *ebc, double *bc, void *stream);

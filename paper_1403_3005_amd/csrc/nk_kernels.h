@@ -82,8 +82,8 @@ struct Params {
     // the per-arc edge terms (single graph, pull sweep down to level 0)
     int32_t linear;
     // directed graph (single graph, BC modes): rowptr/colidx are the out-
-    // arcs; trowptr/tcolidx the in-arcs for bottom-up levels (NULL: top-down
-    // only).  The dependency sweep always pulls over out-arcs.
+    // arcs; trowptr/tcolidx the in-arcs for bottom-up levels and push sweep
+    // levels (NULL: top-down levels and pull sweep levels only).
     int32_t directed;
     double *ebc;
     const int32_t *trowptr;
