@@ -559,11 +559,14 @@ __device__ void bw_pull(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
 // A directed graph pushes over the in-arcs (g is then the in-arc view: an
 // in-neighbour of level l+1 is on level l or deeper, so a marked one is on
 // level l) and skips the vertices no search reaches (`iso`, in-degree 0),
-// which stay marked.
+// which stay marked.  Edge scores (undirected): the DAG arc v -> w adds
+// sigma_v * coef_w to the slot of its reverse arc w -> v, the one this
+// scan holds (the two arcs of an edge are summed at the end).  add_bc:
+// level l's dependencies are scores (not for the source's level).
 template <int BLOCK>
 __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const GView &g, int32_t lo, int32_t hi,
                         int32_t lo1, int32_t hi1, double *bcg, double wfac, double owt, bool in_arcs,
-                        const uint32_t *iso, Counters &c) {
+                        const uint32_t *iso, double *ebc, bool add_bc, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t tb = lo1; tb < hi1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, hi1 - tb);
@@ -576,8 +579,13 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
             load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, v);
 #pragma unroll
             for (int j = 0; j < kChunk; ++j)
-                if (kk[j] >= 0 && bit_test(bm, v[j]) && !(iso && bit_test(iso, v[j])))
-                    atomicAdd(s.dacc + v[j], sm.val.f[kk[j]]);
+                if (kk[j] >= 0 && bit_test(bm, v[j]) && !(iso && bit_test(iso, v[j]))) {
+                    const double cw = sm.val.f[kk[j]];
+                    atomicAdd(s.dacc + v[j], cw);
+                    if (ebc)
+                        atomicAdd(ebc + sm.a0[kk[j]] + (rb + tid * kChunk + j - sm.pre[kk[j]]),
+                                  (double)s.sigma[v[j]] * cw);
+                }
         }
         __syncthreads();
     }
@@ -587,7 +595,7 @@ __device__ void bw_push(Tile<BLOCK> &sm, const uint32_t *bm, const Scr &s, const
         const double delta = sg * s.dacc[v] * wfac;
         s.dacc[v] = 0.0;
         s.sigma[v] = as_u64((1.0 + delta) / sg);
-        if (delta != 0.0 && owt != 0.0) atomicAdd(bcg + v, delta * owt);
+        if (add_bc && delta != 0.0 && owt != 0.0) atomicAdd(bcg + v, delta * owt);
     }
     __syncthreads();
 }
@@ -774,7 +782,7 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
         // scan whichever side of the level pair has fewer arcs (a push
         // scans in-arcs, which a directed run has only with the in-arc CSR;
         // its level degree sums count out-arcs, the proxy used there too)
-        const bool push = !p.ebc && (!p.directed || p.trowptr) &&
+        const bool push = (!p.directed || p.trowptr) &&
                           (double)s.ldeg[l + 1] < (double)p.bw_ratio * (double)s.ldeg[l];
         phase_start<BLOCK>(sm);
         if (push) {
@@ -783,9 +791,9 @@ __device__ void backward(const Params &p, Tile<BLOCK> &sm, uint32_t *bm, const S
                 GView gin = g;
                 gin.rp = g.trp;
                 gin.ci = g.tci;
-                bw_push<BLOCK>(sm, bm, s, gin, lo, hi, hi, hi1, bcg, wfac, owt, true, p.iso, c);
+                bw_push<BLOCK>(sm, bm, s, gin, lo, hi, hi, hi1, bcg, wfac, owt, true, p.iso, nullptr, l >= 1, c);
             } else {
-                bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, owt, false, nullptr, c);
+                bw_push<BLOCK>(sm, bm, s, g, lo, hi, hi, hi1, bcg, wfac, owt, false, nullptr, p.ebc, l >= 1, c);
             }
         } else {
             bw_pull<BLOCK>(sm, bm, s, g, lo, hi, bcg, wfac, owt, p.ebc, l >= 1, c);
