@@ -79,7 +79,7 @@ struct Params {
     DevStatus *st;
     // estimator variants (BC mode): linear != 0 weights each pair (s, t)
     // by d(s, v) / d(s, t) (linear scaling); ebc != NULL also accumulates
-    // the per-arc edge terms (single graph, pull sweep down to level 0)
+    // the per-arc edge terms (single graph, sweep down to level 0)
     int32_t linear;
     // directed graph (single graph, BC modes): rowptr/colidx are the out-
     // arcs; trowptr/tcolidx the in-arcs for bottom-up levels and push sweep
