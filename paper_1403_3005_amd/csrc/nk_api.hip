@@ -905,7 +905,7 @@ nk_status nk_bc_weighted(const int32_t *rowptr, const int32_t *colidx, const int
     } else {
         st = finish(dst, h, s);
     }
-    stats_record(*h, plan.grid, plan.block, 0, ms);
+    stats_record(*h, plan.grid, plan.block, plan.lds ? 1 : 0, ms);
     return st;
 }
 

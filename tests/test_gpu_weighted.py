@@ -60,6 +60,7 @@ def test_weighted_with_and_without_relabelling(sym):
     for flags in (0, 1, 2, 3):
         nk.nk_set_tuning(flags=flags)
         assert_scores_close(nk.nk_bc_weighted(rp, ci, _dev(w)).cpu().numpy(), ref, f"flags={flags}")
+        assert nk.nk_last_stats()["bitmap_lds"] == (0 if flags & 1 else 1)
 
 
 def test_unit_weights_equal_unweighted_on_gpu():
