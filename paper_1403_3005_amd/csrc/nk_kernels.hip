@@ -173,23 +173,6 @@ __device__ __forceinline__ void load_chunk(const Tile<BLOCK> &sm, const GView &g
     }
 }
 
-// Tile rows of the thread's chunk [i0, i0 + kChunk) of the tile's arcs
-// (-1 past the end), without loading the arcs' heads.
-template <int BLOCK>
-__device__ __forceinline__ void candidate_rows(const Tile<BLOCK> &sm, int32_t cnt, int32_t total, int32_t i0,
-                                               int32_t (&kk)[kChunk]) {
-    int32_t k = (i0 < total) ? tile_search(sm.pre, cnt, i0) : 0;
-#pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-        const int32_t i = i0 + j;
-        kk[j] = -1;
-        if (i < total) {
-            while (sm.pre[k + 1] <= i) ++k;
-            kk[j] = k;
-        }
-    }
-}
-
 // Word-granular staging of the level list [tb, tb + cnt): row k's arc range
 // is [sm.a0[k], ends[k]), and sm.pre holds the exclusive prefix of the
 // 32-arc bitmap words each range touches (sm.pre[cnt] = total words, the
@@ -207,6 +190,27 @@ __device__ __forceinline__ int32_t stage_words(Tile<BLOCK> &sm, const Scr &s, in
         sm.a0[tid] = a0;
         ends[tid] = a0 + deg;
         wc = deg > 0 ? ((a0 + deg - 1) >> 5) - (a0 >> 5) + 1 : 0;
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<BLOCK>(wc, sm, total);
+    if (tid < cnt) sm.pre[tid] = ex;
+    if (tid == 0) sm.pre[cnt] = total;
+    return total;
+}
+
+// As stage_words, for the vertex list list[tb, tb + cnt) (arc ranges from
+// g.rp).
+template <int BLOCK>
+__device__ __forceinline__ int32_t stage_words_ids(Tile<BLOCK> &sm, const int32_t *list, const GView &g, int32_t tb,
+                                                   int32_t cnt, int32_t *ends) {
+    const int tid = threadIdx.x;
+    int32_t wc = 0;
+    if (tid < cnt) {
+        const int32_t v = list[tb + tid];
+        const int32_t a0 = g.rp[v], a1 = g.rp[v + 1];
+        sm.a0[tid] = a0;
+        ends[tid] = a1;
+        wc = a1 > a0 ? ((a1 - 1) >> 5) - (a0 >> 5) + 1 : 0;
     }
     int32_t total;
     const int32_t ex = block_excl_scan<BLOCK>(wc, sm, total);
@@ -970,39 +974,33 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
     const int tid = threadIdx.x;
     for (int32_t i = tid; i < nreach; i += BLOCK) s.d[s.cand[i]] = 0;
     __syncthreads();
-    // DAG in-degrees
+    // DAG in-degrees, a thread per arc-bitmap word (candidate arcs only;
+    // the rows' ends take the place of the vertex ids)
     for (int32_t tb = 0; tb < nreach; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, nreach - tb);
-        const int32_t total = stage_ids<BLOCK>(sm, s.cand, g, tb, cnt);
-        if (tid < cnt) sd[tid] = s.dist[sm.v[tid]];
+        if (tid < cnt) sd[tid] = s.dist[s.cand[tb + tid]];
+        const int32_t total = stage_words_ids<BLOCK>(sm, s.cand, g, tb, cnt, sm.v);
         __syncthreads();
-        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-            int32_t kk[kChunk];
-            int32_t word = -1;
-            uint32_t wv = 0u, drop = 0u;
-            candidate_rows<BLOCK>(sm, cnt, total, rb + tid * kChunk, kk);
-#pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                if (kk[j] < 0) continue;
-                const int32_t k = kk[j];
-                const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                if ((arc >> 5) != word) {
-                    if (drop) atomicAnd(&s.dagm[word], ~drop);
-                    word = arc >> 5;
-                    wv = s.dagm[word];
-                    drop = 0u;
-                }
-                const uint32_t bit = 1u << (arc & 31);
-                if (!(wv & bit)) continue;
+        for (int32_t wi = tid; wi < total; wi += BLOCK) {
+            int32_t k;
+            long long W;
+            uint32_t bits;
+            tile_word<BLOCK>(sm, sm.v, cnt, wi, k, W, bits);
+            bits &= s.dagm[W];
+            uint32_t drop = 0u;
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int32_t arc = (int32_t)(W * 32 + b);
                 const int32_t x = g.ci[arc];
                 if (sd[k] + (unsigned long long)p.wts[arc] == s.dist[x]) {
                     atomicAdd(&s.d[x], 1);
                     c.dag++;
                 } else {
-                    drop |= bit;
+                    drop |= 1u << b;
                 }
             }
-            if (drop) atomicAnd(&s.dagm[word], ~drop);
+            if (drop) atomicAnd(&s.dagm[W], ~drop);
         }
         __syncthreads();
     }
