@@ -1023,30 +1023,36 @@ __device__ int32_t w_layers_kahn(const Params &p, Tile<BLOCK> &sm, const Scr &s,
         __syncthreads();
         for (int32_t tb = lo; tb < hi; tb += BLOCK) {
             const int32_t cnt = min(BLOCK, hi - tb);
-            const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
-            if (tid < cnt) sm.val.u[tid] = s.sigma[sm.v[tid]];
+            if (tid < cnt) sm.val.u[tid] = s.sigma[s.lv[tb + tid]];
+            // a thread per arc-bitmap word, DAG arcs only (the rows' ends
+            // take the place of the vertex ids); a head whose last DAG
+            // in-arc this is joins the next layer by an LDS counter
+            int32_t deg;
+            const int32_t total = stage_words<BLOCK>(sm, s, tb, cnt, sm.v, deg);
             __syncthreads();
-            for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-                int32_t kk[kChunk], w[kChunk];
-                load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
-#pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
-                    bool ready = false;
-                    if (kk[j] >= 0) {
-                        const int32_t k = kk[j];
-                        const int32_t arc = sm.a0[k] + (rb + tid * kChunk + j - sm.pre[k]);
-                        if ((s.dagm[arc >> 5] >> (arc & 31)) & 1u) {
-                            const unsigned long long add = sm.val.u[k];
-                            const unsigned long long o = atomicAdd(&s.sigma[w[j]], add);
-                            if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
-                            ready = atomicSub(&s.d[w[j]], 1) == 1;
+            for (int32_t wi = tid; wi < total; wi += BLOCK) {
+                int32_t k;
+                long long W;
+                uint32_t bits;
+                tile_word<BLOCK>(sm, sm.v, cnt, wi, k, W, bits);
+                bits &= s.dagm[W];
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const int32_t x = g.ci[(int32_t)(W * 32 + b)];
+                    const unsigned long long add = sm.val.u[k];
+                    const unsigned long long o = atomicAdd(&s.sigma[x], add);
+                    if (o + add < o) atomicOr(&p.st->err, kErrOverflow);
+                    if (atomicSub(&s.d[x], 1) == 1) {
+                        const int32_t pos = atomicAdd(&sm.count, 1);
+                        if (pos < g.n - hi) {
+                            const int32_t a0 = g.rp[x];
+                            s.lv[hi + pos] = x;
+                            s.la[hi + pos] = a0;
+                            s.ld[hi + pos] = g.rp[x + 1] - a0;
+                        } else {
+                            atomicOr(&p.st->err, kErrInternal);
                         }
-                    }
-                    const int32_t pos = wave_append_pos(ready, w[j], s.lv + hi, &sm.count, g.n - hi, &p.st->err);
-                    if (pos >= 0) {
-                        const int32_t a0 = g.rp[w[j]];
-                        s.la[hi + pos] = a0;
-                        s.ld[hi + pos] = g.rp[w[j] + 1] - a0;
                     }
                 }
             }
