@@ -27,7 +27,14 @@
 //             sigma_v (the only value the level above reads), then adds
 //             delta_v to bc[v] (FP64 atomic add).  This is the dependency
 //             recursion of Brandes' algorithm rearranged as a pull, so no
-//             vertex is written by two threads.
+//             vertex is written by two threads.  A level whose successor
+//             level has far fewer arcs is done the other way round: the
+//             successor level pushes its coefficients into an accumulator
+//             of its marked neighbours, which are exactly level l.
+//
+// The other modes (pair sampling, closeness, the bisection estimator,
+// weighted graphs) reuse the same tiles and bitmap; each has its own
+// section below.
 //
 // Visited state lives in one bitmap (LDS when it fits, else a per-slot
 // global bitmap).  Isolated vertices start marked.  During the forward phase
