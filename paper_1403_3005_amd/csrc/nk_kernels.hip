@@ -1199,8 +1199,8 @@ __device__ int32_t w_layers(const Params &p, Tile<BLOCK> &sm, const Scr &s, cons
 // arcs on weighted graphs, whose shortest paths are mostly unique), so
 // the sweep reads no distances and no weights.
 template <int BLOCK>
-__device__ void w_backward(const Params &p, Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t Ld, double *bcg,
-                           int32_t *ends, Counters &c) {
+__device__ void w_backward(Tile<BLOCK> &sm, const Scr &s, const GView &g, int32_t Ld, double *bcg, int32_t *ends,
+                           Counters &c) {
     const int tid = threadIdx.x;
     if (Ld == 0) return;
     for (int32_t i = s.lvl[Ld] + tid; i < s.lvl[Ld + 1]; i += BLOCK) {
@@ -1758,7 +1758,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             phase_start<BLOCK>(sm);
             // the rows' ends of the sweep's tiles go where the staged
             // distances were
-            w_backward<BLOCK>(p, sm, s, g, Ld, p.bc, reinterpret_cast<int32_t *>(wsd), c);
+            w_backward<BLOCK>(sm, s, g, Ld, p.bc, reinterpret_cast<int32_t *>(wsd), c);
             phase_end<BLOCK>(sm, kPhPull);
             phase_start<BLOCK>(sm);
             for (int32_t i = tid; i < nreach; i += BLOCK) {
