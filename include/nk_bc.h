@@ -277,8 +277,13 @@ int64_t nk_rk_sample_size(double eps, double delta, int32_t vd);
  * pairs (u, v), u != v, one uniformly chosen shortest u-v path each; with
  * probability >= 1 - delta every |bc[v]/(n(n-1)) - BC(v)/(n(n-1))| <= eps.
  *   eps, delta in (0, 1); seed selects the sample (counter-based
- *   SplitMix64: pair j draws u from stream 1 and v from stream 2, step t of
- *   its path walk draws from stream 3).
+ *   SplitMix64: pair j draws u from stream 1 and v from stream 2; its path
+ *   comes from a balanced bidirectional search with path counts on both
+ *   sides, which draws the meeting vertex from stream 4 (weight
+ *   sigma_u(z) * sigma_v(z)), then step t of the walk from the meeting
+ *   vertex towards v from stream 5 and step t of the walk towards u from
+ *   stream 3, each choosing a predecessor with probability proportional to
+ *   its path count).
  *   bc      FP64[n] DEVICE, counts[v] / r * n * (n-1);
  *   counts  uint32[n] DEVICE or NULL: samples whose path has v inside;
  *   r_out   HOST int64 or NULL: number of samples r;

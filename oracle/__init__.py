@@ -75,6 +75,8 @@ def _load():
         "or_rk_sample_size": (c.c_int64, [c.c_double, c.c_double, c.c_int32]),
         "or_sample_path": (c.c_int, g + [c.c_uint64, c.c_int64, i32p, i32p, i32p]),
         "or_sample_path_uv": (c.c_int, g + [c.c_uint64, c.c_int64, c.c_int32, c.c_int32, i32p, i32p]),
+        "or_sample_path_given": (c.c_int, g + [c.c_int32, c.c_int32, u64p, c.c_int32, u64p, u64p, c.c_int32, i32p,
+                                               i32p, i32p]),
         "or_pair_counts": (c.c_int, g + [c.c_int64, c.c_uint64, u32p]),
         "or_pair_sample": (c.c_int, g + [c.c_double, c.c_double, c.c_uint64, u32p, f64p, i64p, i32p]),
     }
@@ -331,6 +333,39 @@ def sample_path_uv(rowptr, colidx, seed: int, j: int, u: int, v: int):
                                      _ptr(ln, ctypes.c_int32)), "sample_path_uv")
     L = int(ln[0])
     return None if L < 0 else [int(x) for x in interior[:L]]
+
+
+def sample_path_given(rowptr, colidx, u: int, v: int, given, with_keys: bool = False):
+    """(interior, ranges[, keys]): the path the sampler yields for the pair
+    (u, v) when its random choices are the values `given` (in the order the
+    sample requests them; missing ones are 0) instead of generator draws,
+    the range N of every choice it requested and, with_keys, the generator
+    index (stream, t) each choice stands for.  interior is None when v is
+    unreachable from u."""
+    n, m, rowptr, colidx = _graph_args(rowptr, colidx)
+    giv = np.ascontiguousarray(np.asarray(given, dtype=np.uint64).reshape(-1))
+    if giv.size == 0:
+        giv = np.zeros(1, dtype=np.uint64)
+        ng = 0
+    else:
+        ng = int(giv.size)
+    cap = 4 * max(n, 1) + 8
+    ranges = np.zeros(cap, dtype=np.uint64)
+    keys = np.zeros(cap, dtype=np.uint64)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    used = ctypes.c_int32(0)
+    ln = ctypes.c_int32(0)
+    _check(_load().or_sample_path_given(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32), int(u),
+                                        int(v), _ptr(giv, ctypes.c_uint64), ng, _ptr(ranges, ctypes.c_uint64),
+                                        _ptr(keys, ctypes.c_uint64), cap, ctypes.byref(used),
+                                        _ptr(out, ctypes.c_int32), ctypes.byref(ln)),
+           "sample_path_given")
+    k = min(used.value, cap)
+    rng = [int(x) for x in ranges[:k]]
+    interior = None if ln.value < 0 else [int(x) for x in out[:ln.value]]
+    if with_keys:
+        return interior, rng, [(int(x) >> 32, int(x) & 0xFFFFFFFF) for x in keys[:k]]
+    return interior, rng
 
 
 def pair_counts(rowptr, colidx, r: int, seed: int) -> np.ndarray:

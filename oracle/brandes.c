@@ -1099,18 +1099,49 @@ static void side_reset(side_t *x) {
     }
 }
 
-/* Walks from `from` to the side's root: at w (step t) draws
- * r = bounded(draw(seed, stream, j, t), sigma[w]) and takes the first
+/*
+ * Where a sample's random choices come from.  Normally each choice is
+ * bounded(draw(seed, stream, j, t), N): uniform on [0, N) up to the
+ * multiply-shift bias.  For inspection the caller may instead give the
+ * chosen values themselves, consumed in the order the sample asks for them
+ * (meeting vertex, then the walk towards v, then the walk towards u); the
+ * range N of every request is recorded, so that a test can enumerate every
+ * outcome of a sample and weigh it exactly.
+ */
+typedef struct {
+    uint64_t seed;
+    int64_t j;
+    const uint64_t *given;   /* NULL: the counter generator */
+    int32_t ngiven;          /* values in `given`; later requests take 0 */
+    int32_t used;            /* requests made so far */
+    uint64_t *ranges;        /* inspection: N of each request (cap entries) */
+    uint64_t *keys;          /* inspection: stream << 32 | t of each request */
+    int32_t cap;
+    int bad;                 /* a given value was outside its range */
+} chooser_t;
+
+static uint64_t choose(chooser_t *c, uint64_t stream, uint64_t t, uint64_t N) {
+    if (!c->given) return or_bounded(or_draw(c->seed, stream, (uint64_t)c->j, t), N);
+    int32_t i = c->used++;
+    if (c->ranges && i < c->cap) c->ranges[i] = N;
+    if (c->keys && i < c->cap) c->keys[i] = stream << 32 | t;
+    uint64_t x = i < c->ngiven ? c->given[i] : 0;
+    if (x >= N) { c->bad = 1; x = 0; }
+    return x;
+}
+
+/* Walks from `from` to the side's root: at w (step t) chooses
+ * r in [0, sigma[w]) (choice stream `stream`, index t) and takes the first
  * neighbour p one level closer to the root, in adjacency order, whose
  * running sigma sum exceeds r (so p has probability sigma[p] / sigma[w]).
  * Writes the vertices strictly between `from` and the root to out in walk
  * order and returns their number. */
-static int32_t walk_to_root(const graph_t *g, const side_t *x, int32_t from, uint64_t seed, uint64_t stream,
-                            int64_t j, int32_t *out) {
+static int32_t walk_to_root(const graph_t *g, const side_t *x, int32_t from, chooser_t *ch, uint64_t stream,
+                            int32_t *out) {
     int32_t w = from, len = 0;
     uint64_t t = 0;
     while (x->d[w] > 0) {
-        uint64_t r = or_bounded(or_draw(seed, stream, (uint64_t)j, t), x->sigma[w]);
+        uint64_t r = choose(ch, stream, t, x->sigma[w]);
         uint64_t acc = 0;
         int32_t pick = -1;
         for (int32_t e = g->rowptr[w]; e < g->rowptr[w + 1]; ++e) {
@@ -1146,18 +1177,19 @@ static int cmp_i32(const void *a, const void *b) {
  * its component: v is unreachable.
  *
  * Path: z in M is taken with probability sigma_A(z) sigma_B(z) / sigma_uv
- * (the first z in increasing id order whose running weight sum exceeds
- * bounded(draw(seed, 4, j, 0), sigma_uv)); then a walk from z to u on side
- * A (draws of stream 3) and one from z to v on side B (stream 5), each
- * choosing predecessors in proportion to their path counts.  Every shortest
- * path is therefore drawn with probability 1 / sigma_uv.
+ * (the first z in increasing id order whose running weight sum exceeds a
+ * choice in [0, sigma_uv), stream 4); then a walk from z to v on side B
+ * (stream 5) and one from z to u on side A (stream 3), each choosing
+ * predecessors in proportion to their path counts.  The walk factors
+ * telescope to 1 / (sigma_A(z) sigma_B(z)), so every shortest path is drawn
+ * with probability 1 / sigma_uv.
  *
  * Interior vertices are written from v's side towards u.  Returns their
  * number, -1 if v is unreachable, or OR_E_SIGMA_OVERFLOW - 100 when a path
  * count (or sigma_uv) reaches 2^64.
  */
-static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u, int32_t v,
-                          side_t *A, side_t *B, int32_t *interior, int32_t *scratch) {
+static int32_t sample_one(const graph_t *g, chooser_t *ch, int32_t u, int32_t v, side_t *A, side_t *B,
+                          int32_t *interior, int32_t *scratch) {
     side_start(g, A, u);
     side_start(g, B, v);
     int32_t result = -1;
@@ -1177,7 +1209,7 @@ static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u,
         for (int32_t a = 0; a < nm; ++a)
             total += (unsigned __int128)A->sigma[scratch[a]] * B->sigma[scratch[a]];
         if (total >> 64) { result = OR_E_SIGMA_OVERFLOW - 100; break; }
-        uint64_t r = or_bounded(or_draw(seed, 4, (uint64_t)j, 0), (uint64_t)total);
+        uint64_t r = choose(ch, 4, 0, (uint64_t)total);
         unsigned __int128 acc = 0;
         int32_t z = -1;
         for (int32_t a = 0; a < nm; ++a) {
@@ -1185,10 +1217,10 @@ static int32_t sample_one(const graph_t *g, uint64_t seed, int64_t j, int32_t u,
             if (acc > r) { z = scratch[a]; break; }
         }
         /* v's side first, reversed so the list runs from v towards u */
-        int32_t len = walk_to_root(g, B, z, seed, 5, j, scratch);
+        int32_t len = walk_to_root(g, B, z, ch, 5, scratch);
         for (int32_t a = 0; a < len; ++a) interior[a] = scratch[len - 1 - a];
         if (z != u && z != v) interior[len++] = z;
-        len += walk_to_root(g, A, z, seed, 3, j, interior + len);
+        len += walk_to_root(g, A, z, ch, 3, interior + len);
         result = len;
         break;
     }
@@ -1237,9 +1269,37 @@ int or_sample_path_uv(int32_t n, int64_t m, const int32_t *rowptr, const int32_t
     graph_t g = {n, rowptr, colidx};
     pair_work_t w;
     if (pair_work_alloc(&w, n) != OR_OK) { pair_work_free(&w); return OR_E_NO_MEMORY; }
-    int32_t l = sample_one(&g, seed, j, u, v, &w.A, &w.B, interior, w.scratch);
+    chooser_t ch = {seed, j, NULL, 0, 0, NULL, NULL, 0, 0};
+    int32_t l = sample_one(&g, &ch, u, v, &w.A, &w.B, interior, w.scratch);
     pair_work_free(&w);
     if (l < -1) return OR_E_SIGMA_OVERFLOW;
+    *len = l;
+    return OR_OK;
+}
+
+/*
+ * The path an explicit pair (u, v) yields when the sample's choices are the
+ * given values (in request order; missing ones are 0) instead of draws: for
+ * enumerating every outcome of the procedure.  ranges[i] receives the range
+ * N of request i and keys[i] its generator index stream << 32 | t (up to
+ * cap entries each), *nused the number of requests made.  A given value
+ * outside its range is an invalid argument.
+ */
+int or_sample_path_given(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx, int32_t u, int32_t v,
+                         const uint64_t *given, int32_t ngiven, uint64_t *ranges, uint64_t *keys, int32_t cap,
+                         int32_t *nused, int32_t *interior, int32_t *len) {
+    int st = or_validate(n, m, rowptr, colidx);
+    if (st != OR_OK) return st;
+    if (u < 0 || u >= n || v < 0 || v >= n || u == v || ngiven < 0 || cap < 0) return OR_E_INVALID_ARG;
+    graph_t g = {n, rowptr, colidx};
+    pair_work_t w;
+    if (pair_work_alloc(&w, n) != OR_OK) { pair_work_free(&w); return OR_E_NO_MEMORY; }
+    chooser_t ch = {0, 0, given, ngiven, 0, ranges, keys, cap, 0};
+    int32_t l = sample_one(&g, &ch, u, v, &w.A, &w.B, interior, w.scratch);
+    pair_work_free(&w);
+    if (l < -1) return OR_E_SIGMA_OVERFLOW;
+    if (ch.bad) return OR_E_INVALID_ARG;
+    *nused = ch.used;
     *len = l;
     return OR_OK;
 }
@@ -1254,7 +1314,8 @@ int or_sample_path(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     pair_work_t w;
     if (pair_work_alloc(&w, n) != OR_OK) { pair_work_free(&w); return OR_E_NO_MEMORY; }
     pair_of(seed, j, n, &uv[0], &uv[1]);
-    int32_t l = sample_one(&g, seed, j, uv[0], uv[1], &w.A, &w.B, interior, w.scratch);
+    chooser_t ch = {seed, j, NULL, 0, 0, NULL, NULL, 0, 0};
+    int32_t l = sample_one(&g, &ch, uv[0], uv[1], &w.A, &w.B, interior, w.scratch);
     pair_work_free(&w);
     if (l < -1) return OR_E_SIGMA_OVERFLOW;
     *len = l;
@@ -1276,7 +1337,8 @@ int or_pair_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     for (int64_t j = 0; j < r; ++j) {
         int32_t u, v;
         pair_of(seed, j, n, &u, &v);
-        int32_t l = sample_one(&g, seed, j, u, v, &w.A, &w.B, interior, w.scratch);
+        chooser_t ch = {seed, j, NULL, 0, 0, NULL, NULL, 0, 0};
+        int32_t l = sample_one(&g, &ch, u, v, &w.A, &w.B, interior, w.scratch);
         if (l < -1) { st = OR_E_SIGMA_OVERFLOW; break; }
         for (int32_t i = 0; i < l; ++i) counts[interior[i]]++;
     }

@@ -48,6 +48,9 @@ struct ServerGraph {
 struct Request {
     int64_t ticket = 0;
     int32_t graph = 0;
+    // the pooled graph, taken under the server lock at submission; graphs
+    // live in a deque, so adding graphs later never moves it
+    const ServerGraph *g = nullptr;
     std::vector<int32_t> sources;  // original ids (k-requests)
     double eps = 0.0, delta = 0.0;
     uint64_t seed = 0;
@@ -81,7 +84,7 @@ struct nk_server {
     size_t pool_bytes = 0;       // resident graphs
     size_t running_bytes = 0;    // admitted requests
     int n_share = 1;             // a request's kernel takes 1/n_share of the resident-workgroup capacity
-    std::vector<nk::ServerGraph> graphs;
+    std::deque<nk::ServerGraph> graphs;   // stable element addresses: requests hold pointers
     std::vector<nk::Slot> slots;
     std::deque<nk::Request *> pending;
     std::map<int64_t, nk::Request *> requests;
@@ -125,7 +128,8 @@ static size_t request_footprint(const ServerGraph &g, long long k, int grid, boo
 }
 
 static void start_request(nk_server *sv, Slot &sl, Request *rq) {
-    ServerGraph &g = sv->graphs[rq->graph];
+    (void)sv;
+    const ServerGraph &g = *rq->g;
     hipStream_t s = sl.stream;
     sl.req = rq;
     sl.scr = new Scratch();
@@ -221,7 +225,7 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
 
 static void finish_request(nk_server *sv, Slot &sl) {
     Request *rq = sl.req;
-    ServerGraph &g = sv->graphs[rq->graph];
+    const ServerGraph &g = *rq->g;
     if (rq->status == NK_OK) {
         const int32_t err = sl.hst->err;
         if (err & kErrGraph) rq->status = NK_E_INVALID_GRAPH;
@@ -259,7 +263,7 @@ static void finish_request(nk_server *sv, Slot &sl) {
 static void widen_grid(nk_server *sv, Request *rq, int busy) {
     const int div = std::max(2, busy + 1);
     if (div >= sv->n_share) return;
-    const ServerGraph &g = sv->graphs[rq->graph];
+    const ServerGraph &g = *rq->g;
     const bool pair = rq->sources.empty();
     LaunchPlan pl;
     if (plan_launch(pair ? kModePair : kModeBC, g.n, std::max<long long>(rq->tasks, 1), -div, &pl) != NK_OK) {
@@ -435,6 +439,7 @@ nk_status nk_server_submit(nk_server *sv, int32_t graph_id, const int32_t *sourc
         return fail(NK_E_INVALID_ARG, "eps and delta must lie in (0, 1)");
     Request *rq = new Request();
     rq->graph = graph_id;
+    rq->g = &g;
     if (k > 0) {
         rq->sources.assign(sources, sources + k);
         for (int32_t v : rq->sources)

@@ -16,6 +16,7 @@ import math
 import networkx as nx
 import numpy as np
 import pytest
+from scipy.stats import chi2 as chi2_dist
 
 import graphgen as gg
 import oracle
@@ -60,7 +61,7 @@ def test_path_walk_uniform_on_grid():
     assert len(counts) == math.comb(6, 3) == 20
     exp = N / 20
     chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
-    assert chi2 < 43.8  # 99.9% quantile of chi-square with 19 degrees of freedom
+    assert chi2 < chi2_dist.ppf(0.999, 19)  # 43.82
     for p in list(counts)[:5]:
         assert _is_shortest_path(g, 0, 15, list(p))
 
@@ -80,7 +81,7 @@ def test_bidirectional_sampler_uniform_vs_enumeration(make, u, v):
         (u, v), _ = max(paths.items(), key=lambda kv: (len(kv[1]), -kv[0][0], -kv[0][1]))
     want = {tuple(reversed(p[1:-1])) for p in paths[(u, v)]}   # interior from v's side
     assert len(want) >= 3
-    N = 400 * len(want)
+    N = 1000 * len(want)
     counts = {}
     for j in range(N):
         p = tuple(oracle.sample_path_uv(g.rowptr, g.colidx, 7, j, u, v))
@@ -89,8 +90,7 @@ def test_bidirectional_sampler_uniform_vs_enumeration(make, u, v):
     assert set(counts) == want
     exp = N / len(want)
     chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
-    dof = len(want) - 1
-    assert chi2 < dof + 4.5 * math.sqrt(2 * dof) + 10
+    assert chi2 < chi2_dist.ppf(0.999, len(want) - 1)
 
 
 def test_bidirectional_sampler_all_pairs_small():
@@ -220,4 +220,4 @@ def test_pairs_uniform_and_distinct():
     assert len(counts) == 12
     exp = N / 12
     chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
-    assert chi2 < 31.3  # 99.9% quantile, 11 degrees of freedom
+    assert chi2 < chi2_dist.ppf(0.999, 11)  # 31.26
