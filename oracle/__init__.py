@@ -77,7 +77,7 @@ def _load():
         "or_sample_path_uv": (c.c_int, g + [c.c_uint64, c.c_int64, c.c_int32, c.c_int32, i32p, i32p]),
         "or_sample_path_given": (c.c_int, g + [c.c_int32, c.c_int32, u64p, c.c_int32, u64p, u64p, c.c_int32, i32p,
                                                i32p, i32p]),
-        "or_pair_counts": (c.c_int, g + [c.c_int64, c.c_uint64, u32p]),
+        "or_pair_counts": (c.c_int, g + [c.c_int64, c.c_uint64, u32p, c.c_int32]),
         "or_pair_sample": (c.c_int, g + [c.c_double, c.c_double, c.c_uint64, u32p, f64p, i64p, i32p]),
     }
     for name, (res, args) in sig.items():
@@ -368,11 +368,13 @@ def sample_path_given(rowptr, colidx, u: int, v: int, given, with_keys: bool = F
     return interior, rng
 
 
-def pair_counts(rowptr, colidx, r: int, seed: int) -> np.ndarray:
+def pair_counts(rowptr, colidx, r: int, seed: int, nthreads: int = 1) -> np.ndarray:
+    """Samples 0 .. r-1 of the pair sequence `seed`: cnt[v] = samples whose
+    path has v inside (nthreads: contiguous blocks of samples, summed)."""
     n, m, rowptr, colidx = _graph_args(rowptr, colidx)
     cnt = np.zeros(max(n, 1), dtype=np.uint32)
     _check(_load().or_pair_counts(n, m, _ptr(rowptr, ctypes.c_int32), _ptr(colidx, ctypes.c_int32),
-                                  r, seed, _ptr(cnt, ctypes.c_uint32)), "pair_counts")
+                                  r, seed, _ptr(cnt, ctypes.c_uint32), int(nthreads)), "pair_counts")
     return cnt[:n]
 
 

@@ -1322,28 +1322,86 @@ int or_sample_path(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     return OR_OK;
 }
 
-/* Counts cnt[p] = number of samples j in [0, r) whose path has p inside. */
+/* Counts cnt[p] = number of samples j in [j0, j1) whose path has p inside
+ * (added into counts). */
+typedef struct {
+    const graph_t *g;
+    uint64_t seed;
+    int64_t j0, j1;
+    uint32_t *counts;
+    int status;
+} pair_job_t;
+
+static void *run_pair_job(void *arg) {
+    pair_job_t *jb = (pair_job_t *)arg;
+    const graph_t *g = jb->g;
+    pair_work_t w;
+    int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
+    if (pair_work_alloc(&w, g->n) != OR_OK || !interior) {
+        pair_work_free(&w);
+        free(interior);
+        jb->status = OR_E_NO_MEMORY;
+        return NULL;
+    }
+    jb->status = OR_OK;
+    for (int64_t j = jb->j0; j < jb->j1; ++j) {
+        int32_t u, v;
+        pair_of(jb->seed, j, g->n, &u, &v);
+        chooser_t ch = {jb->seed, j, NULL, 0, 0, NULL, NULL, 0, 0};
+        int32_t l = sample_one(g, &ch, u, v, &w.A, &w.B, interior, w.scratch);
+        if (l < -1) { jb->status = OR_E_SIGMA_OVERFLOW; break; }
+        for (int32_t i = 0; i < l; ++i) jb->counts[interior[i]]++;
+    }
+    pair_work_free(&w);
+    free(interior);
+    return NULL;
+}
+
+/* Counts cnt[p] = number of samples j in [0, r) whose path has p inside.
+ * The timing mode splits [0, r) into nthreads contiguous blocks with
+ * private counts, added at the end (integer sums: the result does not
+ * depend on nthreads). */
 int or_pair_counts(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *colidx,
-                   int64_t r, uint64_t seed, uint32_t *counts) {
+                   int64_t r, uint64_t seed, uint32_t *counts, int32_t nthreads) {
     int st = or_validate(n, m, rowptr, colidx);
     if (st != OR_OK) return st;
     for (int32_t i = 0; i < n; ++i) counts[i] = 0;
     if (n < 2 || r <= 0) return OR_OK;
     graph_t g = {n, rowptr, colidx};
-    pair_work_t w;
-    int32_t *interior = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    if (pair_work_alloc(&w, n) != OR_OK || !interior) { pair_work_free(&w); free(interior); return OR_E_NO_MEMORY; }
-    st = OR_OK;
-    for (int64_t j = 0; j < r; ++j) {
-        int32_t u, v;
-        pair_of(seed, j, n, &u, &v);
-        chooser_t ch = {seed, j, NULL, 0, 0, NULL, NULL, 0, 0};
-        int32_t l = sample_one(&g, &ch, u, v, &w.A, &w.B, interior, w.scratch);
-        if (l < -1) { st = OR_E_SIGMA_OVERFLOW; break; }
-        for (int32_t i = 0; i < l; ++i) counts[interior[i]]++;
+    if (nthreads <= 1) {
+        pair_job_t jb = {&g, seed, 0, r, counts, OR_OK};
+        run_pair_job(&jb);
+        return jb.status;
     }
-    pair_work_free(&w);
-    free(interior);
+    if ((int64_t)nthreads > r) nthreads = (int32_t)r;
+    pair_job_t *jobs = (pair_job_t *)calloc((size_t)nthreads, sizeof(pair_job_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    char *started = (char *)calloc((size_t)nthreads, 1);
+    if (!jobs || !th || !started) { free(jobs); free(th); free(started); return OR_E_NO_MEMORY; }
+    for (int32_t t = 0; t < nthreads; ++t) {
+        jobs[t].g = &g;
+        jobs[t].seed = seed;
+        jobs[t].j0 = r * t / nthreads;
+        jobs[t].j1 = r * (t + 1) / nthreads;
+        jobs[t].counts = (uint32_t *)calloc((size_t)n, sizeof(uint32_t));
+        jobs[t].status = jobs[t].counts ? OR_OK : OR_E_NO_MEMORY;
+    }
+    for (int32_t t = 0; t < nthreads; ++t)
+        if (jobs[t].status == OR_OK) started[t] = pthread_create(&th[t], NULL, run_pair_job, &jobs[t]) == 0;
+    for (int32_t t = 0; t < nthreads; ++t)
+        if (started[t]) pthread_join(th[t], NULL);
+        else if (jobs[t].status == OR_OK) jobs[t].status = OR_E_NO_MEMORY;
+    st = OR_OK;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        if (jobs[t].status != OR_OK && st == OR_OK) st = jobs[t].status;
+        if (jobs[t].counts) {
+            for (int32_t i = 0; i < n; ++i) counts[i] += jobs[t].counts[i];
+            free(jobs[t].counts);
+        }
+    }
+    free(started);
+    free(jobs);
+    free(th);
     return st;
 }
 
@@ -1363,7 +1421,7 @@ int or_pair_sample(int32_t n, int64_t m, const int32_t *rowptr, const int32_t *c
     int64_t r = n >= 2 ? or_rk_sample_size(eps, delta, info[4]) : 0;
     *r_out = r;
     *vd_out = info[4];
-    st = or_pair_counts(n, m, rowptr, colidx, r, seed, counts);
+    st = or_pair_counts(n, m, rowptr, colidx, r, seed, counts, 1);
     if (st != OR_OK) return st;
     double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
     for (int32_t i = 0; i < n; ++i) bc[i] = (double)counts[i] * scale;

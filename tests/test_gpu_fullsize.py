@@ -36,6 +36,24 @@ def test_rmat20_sampled_sources_vs_oracle(rmat20):
         assert np.array_equal(s[i].cpu().numpy().view(np.uint64), os_)
 
 
+def test_rmat20_strided_512_sources_vs_oracle(rmat20):
+    """Every eighth benchmark source (512 of the 4096) in the benchmark's
+    launch form (256 workgroups of 1024 threads, bottom-up and push levels
+    on): twice as many sources as workgroups, so slots run further sources
+    on state the previous one left, and two calls in a row; every score
+    against the oracle."""
+    g, src, rp, ci = rmat20
+    nk.nk_set_tuning()
+    part = np.ascontiguousarray(src[::8])
+    ref = oracle.bc_sources(g.rowptr, g.colidx, part, g.n / 4096, nthreads=16)
+    for call in range(2):
+        got = nk.nk_bc_sources(rp, ci, ivec(part), g.n / 4096).cpu().numpy()
+        st = nk.nk_last_stats()
+        assert st["workgroups"] == 256 and st["block"] == 1024, st
+        assert st["levels_bu"] > 0 and st["levels_bw_push"] > 0, st
+        assert_scores_close(got, ref, f"rmat20 strided sources, call {call}")
+
+
 def test_rmat20_all_4096_sources_sum_invariant(rmat20):
     """The benchmark call itself (4096 sources, scale n/4096): the scores sum
     to scale x sum over sources and reached t of (d(s,t) - 1), with d from
@@ -88,6 +106,41 @@ def test_chunglu4m_sampled_pairs_bit_exact(chunglu4m):
             assert path[j, :len(interior)].cpu().tolist() == interior
     got = nk.nk_pair_counts(rp, ci, 10, 3).cpu().numpy().view(np.uint32)
     assert np.array_equal(got, oracle.pair_counts(g.rowptr, g.colidx, 10, 3))
+
+
+def test_chunglu4m_full_sample_bit_exact(chunglu4m):
+    """The benchmark call itself (eps 0.01, delta 0.1, seed 3: r = 31,513
+    samples on 512 slots of 256 threads), twice, so the second call runs on
+    the per-vertex records the first left (reused without a fill): all
+    counts identical to the oracle's over the whole sample."""
+    g, rp, ci = chunglu4m
+    nk.nk_set_tuning()
+    _, cnt0, r, vd = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
+    assert r == oracle.rk_sample_size(0.01, 0.1, vd)
+    ref = oracle.pair_counts(g.rowptr, g.colidx, r, 3, nthreads=16)
+    assert np.array_equal(cnt0.cpu().numpy().view(np.uint32), ref)
+    _, cnt1, r1, _ = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
+    assert r1 == r and np.array_equal(cnt1.cpu().numpy().view(np.uint32), ref)
+
+
+def test_batched_with_50k_vertex_graphs():
+    """A batch holding an ER and a BA graph of 5e4 vertices (mean degree 8,
+    the batched workload's generators) beside small graphs, in one call:
+    every score of every graph against the oracle."""
+    graphs = [gg.erdos_renyi(50_000, 200_000, 811), gg.barabasi_albert(50_000, 4, 812),
+              gg.erdos_renyi(1500, 6000, 813), gg.barabasi_albert(4000, 4, 814), gg.erdos_renyi(9000, 36000, 815)]
+    vtx = np.zeros(len(graphs) + 1, dtype=np.int64)
+    arc = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vtx[i + 1] = vtx[i] + g.n
+        arc[i + 1] = arc[i] + g.m
+    rp = torch.from_numpy(np.concatenate([g.rowptr for g in graphs]).astype(np.int32)).cuda()
+    ci = torch.from_numpy(np.concatenate([g.colidx for g in graphs]).astype(np.int32)).cuda()
+    nk.nk_set_tuning()
+    got = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
+    assert nk.nk_last_stats()["sources"] == int(vtx[-1])
+    for i, g in enumerate(graphs):
+        assert_scores_close(got[vtx[i]:vtx[i + 1]], oracle.bc_exact(g.rowptr, g.colidx, nthreads=16), f"graph {i}")
 
 
 def test_batched_c4_sized_graphs():

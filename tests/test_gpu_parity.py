@@ -197,22 +197,36 @@ def test_scratch_cap_shrinks_the_grid():
 
 
 @pytest.mark.parametrize("flags", PATHS)
-def test_work_counters_match_oracle(flags):
-    # top-down only (the all-in-LDS kernel always is): forward arcs = arcs of reached vertices
-    nk.nk_set_tuning(block=0, bu_ratio=0.0, flags=flags)
+@pytest.mark.parametrize("bu_ratio,bw_ratio", [(0.0, 0.1), (16.0, 0.1), (1e9, 1e9), (1e9, 0.0)])
+def test_work_counters_match_oracle(flags, bu_ratio, bw_ratio):
+    """The counts behind the algorithmic bytes (reached vertices, arcs of
+    reached vertices, shortest-path DAG arcs) equal the oracle's in every
+    direction mix: top-down only, the benchmark's thresholds, bottom-up and
+    push wherever allowed, bottom-up with pull only.  The all-in-LDS kernel
+    (flags 0 on this graph) is always top-down and pull."""
+    nk.nk_set_tuning(block=0, bu_ratio=bu_ratio, bw_ratio=bw_ratio, flags=flags)
     g = gg.barabasi_albert(3000, 3, 41)
     src = gg.sample_sources(g.n, 100, 42)
     rp, ci = upload(g)
-    nk.nk_bc_sources(rp, ci, ivec(src), 1.0)
+    got = nk.nk_bc_sources(rp, ci, ivec(src), 1.0).cpu().numpy()
     st = nk.nk_last_stats()
     reached, arcs, dag, depth = oracle.work_counts(g.rowptr, g.colidx, src)
     assert st["sources"] == 100
     assert st["reached"] == reached
-    assert st["arcs_fwd"] == arcs
     assert st["arcs_reached"] == arcs
     assert st["dag_arcs"] == dag
-    assert st["levels_td"] == depth + 100  # one extra (empty) expansion per source
-    assert st["bitmap_lds"] == (2 if flags == 0 else 1)
+    assert st["levels_td"] + st["levels_bu"] == depth + 100  # one extra (empty) expansion per source
+    lds = st["bitmap_lds"] == 2
+    assert lds == (flags == 0)
+    if bu_ratio == 0.0 or lds:
+        assert st["arcs_fwd"] == arcs and st["levels_bu"] == 0
+    else:
+        assert st["levels_bu"] > 0
+    if bw_ratio >= 1e9 and not lds:
+        assert st["levels_bw_push"] > 0
+    if bw_ratio == 0.0:
+        assert st["levels_bw_push"] == 0
+    assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src), "counters run")
 
 
 def test_sources_forms_and_duplicates():

@@ -1,10 +1,12 @@
-"""Serving: results through the server equal the direct calls, each request
-gives the same result alone and inside a concurrent mix, admission respects
-the HBM budget."""
+"""Serving: results through the server equal the CPU oracle's (and the
+direct calls'), each request gives the same result alone and inside a
+concurrent mix, admission respects the HBM budget, and graphs can be added
+while requests run."""
 import numpy as np
 import pytest
 
 import graphgen as gg
+import oracle
 import paper_1403_3005_amd as nk
 from paper_1403_3005_amd.serving import replay
 from nkutil import assert_scores_close, ivec, upload
@@ -16,6 +18,60 @@ GIB = 1 << 30
 
 def _pool():
     return [gg.rmat(13, 16, 501), gg.barabasi_albert(20000, 4, 502), gg.rmat(15, 16, 503), gg.erdos_renyi(3000, 9000, 504)]
+
+
+def _oracle_request(g, rq):
+    """The oracle's answer to one request: scores of the k listed sources
+    scaled by n/k, or pair-sampling scores (counts / r * n(n-1))."""
+    if "sources" in rq:
+        k = len(rq["sources"])
+        return oracle.bc_sources(g.rowptr, g.colidx, rq["sources"], g.n / k, nthreads=16), None
+    est, cnt, r, vd = oracle.pair_sample(g.rowptr, g.colidx, rq["eps"], rq["delta"], rq["seed"])
+    return est, (cnt, r)
+
+
+def test_server_matches_oracle():
+    """Every request of a mixed stream over the pool against the CPU oracle:
+    source requests within the score tolerance, pair requests with counts
+    identical to the oracle's (recovered from the scores and the oracle's r)."""
+    pool = _pool()
+    with nk.NkServer(64 * GIB, slots=4) as sv:
+        ids = [sv.add_graph(*upload(g)) for g in pool]
+        reqs = gg.request_stream(30, 1000.0, [g.n for g in pool], seed=19)
+        assert {("sources" in rq) for rq in reqs} == {True, False}
+        results, _ = replay(sv, ids, reqs)
+        for rq, (scores, lat) in zip(reqs, results):
+            g = pool[rq["graph"]]
+            ref, pair = _oracle_request(g, rq)
+            if pair is None:
+                assert_scores_close(scores, ref, f"request {rq['id']} vs oracle")
+            else:
+                cnt, r = pair
+                scale = g.n * (g.n - 1) / r
+                assert np.array_equal(np.rint(scores / scale).astype(np.int64), cnt.astype(np.int64)), rq["id"]
+                assert_scores_close(scores, ref, f"pair request {rq['id']} vs oracle")
+
+
+def test_add_graph_while_requests_run():
+    """Graphs added while requests are in flight: earlier requests finish
+    with the oracle's scores and the new graphs serve requests too."""
+    pool = _pool()
+    with nk.NkServer(64 * GIB, slots=4) as sv:
+        ids = [sv.add_graph(*upload(pool[0]))]
+        tickets = []
+        for i in range(8):
+            src = gg.sample_sources(pool[0].n, 256, 900 + i)
+            tickets.append((0, src, sv.submit(ids[0], sources=src)))
+            if i < 3:
+                ids.append(sv.add_graph(*upload(pool[i + 1])))
+        for gi in range(1, 4):
+            src = gg.sample_sources(pool[gi].n, 64, 950 + gi)
+            tickets.append((gi, src, sv.submit(ids[gi], sources=src)))
+        for gi, src, t in tickets:
+            scores, _ = sv.wait(t)
+            g = pool[gi]
+            ref = oracle.bc_sources(g.rowptr, g.colidx, src, g.n / len(src), nthreads=16)
+            assert_scores_close(scores, ref, f"graph {gi}")
 
 
 def test_server_matches_direct_calls():

@@ -221,3 +221,13 @@ def test_pairs_uniform_and_distinct():
     exp = N / 12
     chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
     assert chi2 < chi2_dist.ppf(0.999, 11)  # 31.26
+
+
+def test_pair_counts_threads_agree():
+    """The timing mode's contiguous blocks of samples add up to the
+    sequential counts exactly."""
+    g = gg.barabasi_albert(400, 3, 21)
+    one = oracle.pair_counts(g.rowptr, g.colidx, 1500, 8)
+    assert one.sum() > 0
+    for t in (2, 3, 7):
+        assert np.array_equal(oracle.pair_counts(g.rowptr, g.colidx, 1500, 8, nthreads=t), one)
