@@ -111,6 +111,25 @@ nk_status nk_bc_sources(const int32_t *rowptr, const int32_t *colidx, int32_t n,
                         const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
 
 /*
+ * nk_bc_sources for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results (within the score tolerance: the summation order
+ * differs) and errors as nk_bc_sources.  It calls no hipMalloc, hipFree or
+ * allocating library routine: its scratch (status block, isolated-vertex
+ * bitmap, per-workgroup state of the persistent kernel) is carved from one
+ * fixed 128 MiB array in device memory that each device the library runs
+ * on holds until the process ends; the graph runs under the caller's ids
+ * (no degree relabelling) and the grid shrinks until the workgroups' state
+ * fits.  A graph whose state for one workgroup does not fit (n above about
+ * 2.9 million vertices) is NK_E_BUDGET, reported before any launch.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other threads or streams) race and must be serialised by the
+ * caller.  Synchronises `stream` before returning.
+ */
+nk_status nk_bc_sources_noalloc(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m,
+                                const int32_t *sources, int32_t k, double scale, double *bc, void *stream);
+
+/*
  * Linear-scaling estimator of Geisberger, Sanders and Schultes (the
  * reference the paper cites for approximating betweenness from a few
  * shortest-path trees, "Heuristics and Approximation Algorithms"): every

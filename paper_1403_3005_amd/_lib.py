@@ -32,6 +32,7 @@ NK_E_INTERNAL = -8
 
 EXPORTS = [
     "nk_last_error", "nk_version", "nk_shutdown", "nk_validate_graph", "nk_bc_exact", "nk_bc_sources",
+    "nk_bc_sources_noalloc",
     "nk_bc_sources_linear", "nk_bc_sources_bisect", "nk_bc_directed", "nk_bc_weighted", "nk_transpose", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_batch_plan_create", "nk_batch_plan_run", "nk_batch_plan_destroy",
@@ -71,6 +72,7 @@ def load():
         "nk_validate_graph": (c.c_int32, g + [c.c_int32, vp]),
         "nk_bc_exact": (c.c_int32, g + [vp, vp]),
         "nk_bc_sources": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
+        "nk_bc_sources_noalloc": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_bc_sources_linear": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_bc_sources_bisect": (c.c_int32, g + [vp, c.c_int32, c.c_double, vp, vp]),
         "nk_bc_directed": (c.c_int32, [vp, vp, vp, vp, c.c_int32, c.c_int64, vp, c.c_int32, c.c_double, vp, vp]),
@@ -172,6 +174,19 @@ def nk_bc_sources(rowptr, colidx, sources, scale: float = 1.0, bc=None, stream=N
     k = sources.numel()
     sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
     _check(load().nk_bc_sources(rp, ci, n, m, sp, k, float(scale), _dev(bc, torch.float64, "bc"), _stream(stream)))
+    return bc
+
+
+def nk_bc_sources_noalloc(rowptr, colidx, sources, scale: float = 1.0, bc=None, stream=None):
+    """nk_bc_sources with the library's fixed device scratch (no allocation
+    inside the call; `bc` may be passed in so the call allocates nothing)."""
+    rp, ci, n, m = _graph(rowptr, colidx)
+    if bc is None:
+        bc = torch.empty(max(n, 0), dtype=torch.float64, device=rowptr.device)
+    k = sources.numel()
+    sp = _dev(sources, torch.int32, "sources") if k > 0 else ctypes.c_void_p(0)
+    _check(load().nk_bc_sources_noalloc(rp, ci, n, m, sp, k, float(scale), _dev(bc, torch.float64, "bc"),
+                                        _stream(stream)))
     return bc
 
 

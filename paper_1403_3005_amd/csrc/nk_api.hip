@@ -299,7 +299,7 @@ nk_status check_graph_args(const int32_t *rowptr, const int32_t *colidx, int32_t
 
 // ----------------------------------------------------------------- planner --
 
-static int auto_block(int32_t n_max) {
+int auto_block(int32_t n_max) {
     if (n_max < 20000) return 256;
     if (n_max < 200000) return 512;
     return 1024;

@@ -91,6 +91,9 @@ struct LaunchPlan {
 // arcs of the graph (weighted mode sizes its DAG-arc bitmap by them).
 nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, LaunchPlan *plan,
                       int64_t m_arcs = 0);
+// Block size of a persistent launch over graphs of at most n_max vertices
+// when the tuning leaves it open.
+int auto_block(int32_t n_max);
 
 // Grid-wide direction-optimising breadth-first search (nk_bfs.hip).
 struct BfsWork {
