@@ -426,6 +426,14 @@ nk_status nk_last_stats(int64_t *out);
  *              free or idle in the library's pool.  The grid shrinks to fit;
  *              if a single slot does not fit the call fails with
  *              NK_E_NO_MEMORY.
+ *   batch      sources per workgroup task in exact and source-set
+ *              betweenness (plain and linear scaling) of graphs the
+ *              all-in-LDS kernel does not take: 1 = one source per task;
+ *              4, 8 or 16 = the multi-source kernel, which runs that many
+ *              sources level by level over the union of their frontiers,
+ *              reading each adjacency row once per union level and keeping
+ *              the sources' path counts of a vertex side by side; 0 =
+ *              chosen by graph size.
  * nk_set_tuning applies to later calls from every thread.
  */
 typedef struct {
@@ -435,7 +443,8 @@ typedef struct {
     int32_t flags;
     float bw_ratio;
     int32_t scratch_mib;
-    int32_t reserved[2];
+    int32_t batch;
+    int32_t reserved;
 } nk_tuning;
 
 nk_status nk_set_tuning(const nk_tuning *t);

@@ -51,7 +51,7 @@ class NkError(RuntimeError):
 class NkTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("bu_ratio", ctypes.c_float), ("wg_per_cu", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("bw_ratio", ctypes.c_float), ("scratch_mib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def load():
@@ -419,7 +419,7 @@ class NkBatchPlan:
 
 
 STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",
-             "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "reserved13", "reserved14",
+             "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "sources_per_task", "reserved14",
              "reserved15", "cyc_init", "cyc_topdown", "cyc_bottomup", "cyc_mark", "cyc_pull", "cyc_push",
              "cyc_reset", "cyc_other", "sub_bu_stage", "sub_bu_arcs", "sub_bu_finalize", "sub_pull_stage",
              "sub_pull_arcs", "sub_pull_finalize", "reserved30", "reserved31"]
@@ -432,21 +432,20 @@ def nk_last_stats() -> dict:
 
 
 def nk_set_tuning(block: int = 0, bu_ratio: float = 16.0, wg_per_cu: int = 0, flags: int = 0, bw_ratio: float = 0.1,
-                  scratch_mib: int = 0):
-    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio, scratch_mib)
+                  scratch_mib: int = 0, batch: int = 0):
+    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio, scratch_mib, batch)
     _check(load().nk_set_tuning(ctypes.byref(t)))
 
 
 def nk_get_tuning() -> dict:
     t = NkTuning()
     _check(load().nk_get_tuning(ctypes.byref(t)))
-    return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
-            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib}
+    return _tuning_dict(t)
 
 
 def _tuning_dict(t) -> dict:
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
-            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib}
+            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib, "batch": t.batch}
 
 
 def nk_autotune(rowptr, colidx, sources, cache_path: str | None = None, stream=None) -> dict:

@@ -219,7 +219,7 @@ size_t pool_bytes_in_use() {
 // ------------------------------------------------------------------ tuning --
 
 static std::mutex g_tune_mu;
-static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, 0, {0, 0}};
+static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, 0, 0, 0};
 
 nk_tuning tuning_get() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -235,6 +235,8 @@ void tuning_set(const nk_tuning &t) {
 
 void stats_clear() { memset(t_stats, 0, sizeof(t_stats)); }
 
+void stats_set_batch(int b) { t_stats[13] = b; }
+
 void stats_record(const DevStatus &st, int grid, int block, int lds, float kernel_ms) {
     t_stats[0] = (int64_t)st.stat[kStSources];
     t_stats[1] = (int64_t)st.stat[kStReached];
@@ -249,7 +251,8 @@ void stats_record(const DevStatus &st, int grid, int block, int lds, float kerne
     t_stats[10] = lds;
     t_stats[11] = (int64_t)st.stat[kStArcsReached];
     t_stats[12] = (int64_t)st.stat[kStBwPush];
-    t_stats[13] = t_stats[14] = t_stats[15] = 0;
+    t_stats[13] = 1;
+    t_stats[14] = t_stats[15] = 0;
     for (int i = 0; i < kNumPhases; ++i) t_stats[16 + i] = (int64_t)st.cycles[i];
     for (int i = 0; i < 8; ++i) t_stats[24 + i] = (int64_t)st.sub[i];
 }
@@ -432,6 +435,114 @@ bool plan_lds(size_t dyn_bytes, int32_t n_max, long long ntasks, LaunchPlan *pla
     return true;
 }
 
+// ------------------------------------------------------ multi-source plan --
+
+int ms_batch_for(int32_t n_max, long long nsources) {
+    const int t = tuning_get().batch;
+    if (t == 1 || t == 4 || t == 8 || t == 16) return t;
+    (void)n_max;
+    (void)nsources;
+    return 1;
+}
+
+nk_status plan_ms(int b, int32_t n_max, long long nsources, MsPlan *mp) {
+    DevInfo di;
+    nk_status st = dev_info(&di);
+    if (st != NK_OK) return st;
+    const nk_tuning t = tuning_get();
+    int block = t.block;
+    if (block != 256 && block != 512 && block != 1024) block = 1024;
+    KernelRef kr = brandes_ms_kernel(block, b);
+    hipFuncAttributes attr;
+    NK_HIP(hipFuncGetAttributes(&attr, kr.fn));
+    const int per_word = 4 / ms_mask_bytes(b);
+    const size_t room = di.lds_per_block > attr.sharedSizeBytes ? di.lds_per_block - attr.sharedSizeBytes : 0;
+    long long nl = (long long)(room / 4) * per_word;
+    const long long n_round = ((long long)n_max + per_word - 1) / per_word * per_word;
+    if (nl > n_round) nl = n_round;
+    const size_t dyn = (size_t)(nl / per_word) * 4;
+    NK_HIP(hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    int occ = 0;
+    NK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kr.fn, block, dyn));
+    if (occ < 1) return fail(NK_E_INTERNAL, "multi-source kernel does not fit a compute unit (block %d)", block);
+    if (t.wg_per_cu > 0 && t.wg_per_cu < occ) occ = t.wg_per_cu;
+    const long long ntasks = (nsources + b - 1) / b;
+    long long grid = (long long)di.cus * occ;
+    if (ntasks < grid) grid = ntasks;
+    if (grid < 1) grid = 1;
+    const long long stride = (((long long)n_max + 2) + 63) / 64 * 64;
+    const long long cap = stride * b;
+    const long long visg_words = ((stride + per_word - 1) / per_word + 63) / 64 * 64;
+    // per slot: interleaved path counts, new-source masks, four list arrays
+    // of cap entries, level offsets, bottom-up candidates, global masks
+    const size_t per_slot = (size_t)stride * b * 8 + (size_t)stride * 4 * 3 + (size_t)cap * 4 * 4 +
+                            (size_t)visg_words * 4;
+    size_t avail;
+    if (t.scratch_mib > 0) {
+        avail = (size_t)t.scratch_mib << 20;
+    } else {
+        size_t fr = 0, tot = 0;
+        NK_HIP(hipMemGetInfo(&fr, &tot));
+        avail = (size_t)((double)(fr + pool_bytes_idle()) * 0.85);
+    }
+    const long long fit = (long long)(avail / per_slot);
+    if (fit < 1)
+        return fail(NK_E_NO_MEMORY, "one multi-source workgroup slot needs %zu bytes of scratch; %zu available",
+                    per_slot, avail);
+    if (grid > fit) grid = fit > di.cus ? fit / di.cus * di.cus : fit;
+    mp->b = b;
+    mp->nl = (int32_t)nl;
+    mp->stride = stride;
+    mp->cap = cap;
+    mp->visg_words = visg_words;
+    mp->ntasks = ntasks;
+    mp->lp.mode = kModeBC;
+    mp->lp.block = block;
+    mp->lp.lds = true;
+    mp->lp.grid = (int)grid;
+    mp->lp.dyn_lds = dyn;
+    mp->lp.stride = stride;
+    mp->lp.bm_words = 0;
+    mp->lp.kernel = kr;
+    mp->lp.pair_rec = nullptr;
+    mp->lp.dag_words = 0;
+    return NK_OK;
+}
+
+nk_status ms_alloc(const MsPlan &mp, Params &p, Scratch &scr) {
+    const long long slots = mp.lp.grid;
+    nk_status st;
+    if ((st = scr.get(slots * mp.stride * mp.b, &p.sigma)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.stride, &p.nx)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.stride, &p.lvl)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.stride, &p.cand)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.cap, &p.lv)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.cap, &p.la)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.cap, &p.ld)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.cap, &p.lm)) != NK_OK) return st;
+    if ((st = scr.get(slots * mp.visg_words, &p.visg)) != NK_OK) return st;
+    p.stride = mp.stride;
+    p.ms_b = mp.b;
+    p.ms_nl = mp.nl;
+    p.ms_cap = mp.cap;
+    p.visg_words = mp.visg_words;
+    p.bu_ratio = tuning_get().bu_ratio;
+    p.bw_ratio = tuning_get().bw_ratio;
+    return NK_OK;
+}
+
+nk_status ms_enqueue(const MsPlan &mp, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const long long slots = mp.lp.grid;
+    NK_HIP(launch_fill_u64(p.sigma, 0ULL, slots * mp.stride * mp.b, s));
+    NK_HIP(launch_fill_u32(p.nx, 0u, slots * mp.stride, s));
+    NK_HIP(launch_fill_u32(p.visg, 0u, slots * mp.visg_words, s));
+    if (ev0) NK_HIP(hipEventRecord(ev0, s));
+    mp.lp.kernel.launch(dim3(mp.lp.grid), dim3(mp.lp.block), mp.lp.dyn_lds, s, p);
+    NK_HIP(hipGetLastError());
+    if (ev1) NK_HIP(hipEventRecord(ev1, s));
+    return NK_OK;
+}
+
 nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s) {
     const long long slots = plan.grid;
     const long long cells = slots * plan.stride;
@@ -604,6 +715,8 @@ nk_status nk_set_tuning(const nk_tuning *t) {
         return fail(NK_E_INVALID_ARG, "block must be 0, 256, 512 or 1024");
     if (!(t->bu_ratio >= 0.0f) || !(t->bw_ratio >= 0.0f) || t->wg_per_cu < 0 || t->scratch_mib < 0)
         return fail(NK_E_INVALID_ARG, "bad tuning values");
+    if (t->batch != 0 && t->batch != 1 && t->batch != 4 && t->batch != 8 && t->batch != 16)
+        return fail(NK_E_INVALID_ARG, "batch must be 0, 1, 4, 8 or 16");
     tuning_set(*t);
     return NK_OK;
 }
@@ -750,6 +863,39 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
             }
             if ((st = scr.get(n, &acc)) != NK_OK) return st;
             NK_HIP(launch_fill_f64(acc, 0.0, n, s));
+        }
+        // plain and linear-scaling sweeps of undirected graphs without edge
+        // scores may run several sources per task
+        const int msb = (!ebc && !dir && est != kEstBisect) ? ms_batch_for(n, k) : 1;
+        if (msb > 1) {
+            MsPlan mp;
+            if ((st = plan_ms(msb, n, k, &mp)) != NK_OK) return st;
+            Params p;
+            memset(&p, 0, sizeof(p));
+            p.rowptr = g.rowptr;
+            p.colidx = g.colidx;
+            p.n = n;
+            p.m = (int32_t)m;
+            p.sources = src;
+            p.nsources = k;
+            p.ntasks = mp.ntasks;
+            p.bc = acc;
+            p.iso = iso;
+            p.st = dst;
+            p.linear = est == kEstLinear;
+            if ((st = ms_alloc(mp, p, scr)) != NK_OK) return st;
+            hipEvent_t ev0, ev1;
+            if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+            if ((st = ms_enqueue(mp, p, s, ev0, ev1)) != NK_OK) return st;
+            if (g.perm)
+                NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
+            else if (scale != 1.0)
+                NK_HIP(launch_scale_f64(bc, scale, n, s));
+            st = finish(dst, h, s);
+            NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            stats_record(*h, mp.lp.grid, mp.lp.block, 4, ms);
+            stats_set_batch(msb);
+            return st;
         }
         if ((st = plan_launch(est == kEstBisect ? kModeBisect : kModeBC, n, k, 0, &plan)) != NK_OK) return st;
         Params p;
@@ -1296,6 +1442,8 @@ struct BatchSetup {
     DevStatus *dst = nullptr;
     Params p;
     LaunchPlan plan_s = {}, plan_l = {};
+    int ms_b = 1;              // sources per task of the large graphs' launch
+    MsPlan mplan = {};
     long long *t_small = nullptr, *t_large = nullptr;
     int32_t *o_small = nullptr, *o_large = nullptr;
     long long k_small = 0, k_large = 0;
@@ -1368,11 +1516,13 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
     auto by_work = [&](int32_t x, int32_t y) { return work[x] > work[y]; };
     std::stable_sort(small.begin(), small.end(), by_work);
     std::stable_sort(large.begin(), large.end(), by_work);
-    auto tables = [&](const std::vector<int32_t> &ids, long long **d_task, int32_t **d_order,
-                      long long *ntasks) -> nk_status {
+    // task prefix over the graphs in processing order: one task per source,
+    // or per group of `per` sources
+    auto tables = [&](const std::vector<int32_t> &ids, long long **d_task, int32_t **d_order, long long *ntasks,
+                      int per) -> nk_status {
         const int32_t K = (int32_t)ids.size();
         std::vector<long long> pre(K + 1, 0);
-        for (int32_t i = 0; i < K; ++i) pre[i + 1] = pre[i] + (vtx_off[ids[i] + 1] - vtx_off[ids[i]]);
+        for (int32_t i = 0; i < K; ++i) pre[i + 1] = pre[i] + (vtx_off[ids[i] + 1] - vtx_off[ids[i]] + per - 1) / per;
         nk_status e;
         if ((e = scr.get(K + 1, d_task)) != NK_OK) return e;
         if ((e = scr.get(K, d_order)) != NK_OK) return e;
@@ -1393,13 +1543,23 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
     b->g_small = (int32_t)small.size();
     b->g_large = (int32_t)large.size();
     if (!small.empty()) {
-        if ((st = tables(small, &b->t_small, &b->o_small, &b->k_small)) != NK_OK) return st;
+        if ((st = tables(small, &b->t_small, &b->o_small, &b->k_small, 1)) != NK_OK) return st;
         if (!plan_lds(dyn_max, n_small, b->k_small, &b->plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
     }
     if (!large.empty()) {
-        if ((st = tables(large, &b->t_large, &b->o_large, &b->k_large)) != NK_OK) return st;
-        if ((st = plan_launch(kModeBC, b->n_large, b->k_large, 0, &b->plan_l)) != NK_OK) return st;
-        if ((st = persistent_alloc(b->plan_l, b->p, scr, s)) != NK_OK) return st;
+        long long nsrc_large = 0;
+        for (int32_t g : large) nsrc_large += vtx_off[g + 1] - vtx_off[g];
+        b->ms_b = ms_batch_for(b->n_large, nsrc_large);
+        if ((st = tables(large, &b->t_large, &b->o_large, &b->k_large, b->ms_b)) != NK_OK) return st;
+        if (b->ms_b > 1) {
+            if ((st = plan_ms(b->ms_b, b->n_large, nsrc_large, &b->mplan)) != NK_OK) return st;
+            b->mplan.ntasks = b->k_large;
+            if ((st = ms_alloc(b->mplan, b->p, scr)) != NK_OK) return st;
+            b->plan_l = b->mplan.lp;
+        } else {
+            if ((st = plan_launch(kModeBC, b->n_large, b->k_large, 0, &b->plan_l)) != NK_OK) return st;
+            if ((st = persistent_alloc(b->plan_l, b->p, scr, s)) != NK_OK) return st;
+        }
     }
     b->nv = nv;
     b->rowptr = rowptr_cat;
@@ -1433,7 +1593,8 @@ static nk_status batch_enqueue(const BatchSetup &b, hipStream_t s, hipEvent_t ev
         p.g_task = b.t_large;
         p.g_order = b.o_large;
         p.ntasks = b.k_large;
-        nk_status st = persistent_enqueue(b.plan_l, p, s, nullptr, nullptr);
+        nk_status st = b.ms_b > 1 ? ms_enqueue(b.mplan, p, s, nullptr, nullptr)
+                                  : persistent_enqueue(b.plan_l, p, s, nullptr, nullptr);
         if (st != NK_OK) return st;
     }
     if (ev1) NK_HIP(hipEventRecord(ev1, s));
@@ -1441,9 +1602,11 @@ static nk_status batch_enqueue(const BatchSetup &b, hipStream_t s, hipEvent_t ev
 }
 
 static void batch_stats(const BatchSetup &b, const DevStatus &h, float ms) {
-    const int where = b.g_large == 0 ? 2 : (b.g_small == 0 ? (b.plan_l.lds ? 1 : 0) : 3);
+    int where = b.g_large == 0 ? 2 : (b.g_small == 0 ? (b.plan_l.lds ? 1 : 0) : 3);
+    if (b.g_large > 0 && b.ms_b > 1) where = b.g_small == 0 ? 4 : 5;
     const LaunchPlan &shown = b.g_large == 0 ? b.plan_s : b.plan_l;
     stats_record(h, shown.grid, shown.block, where, ms);
+    if (b.g_large > 0) stats_set_batch(b.ms_b);
 }
 
 }  // namespace nk

@@ -112,6 +112,19 @@ struct Params {
     // per-vertex integer distance sums over the sources (sampled form)
     double *close_out;
     unsigned long long *close_acc;
+    // multi-source mode (nk_multi.hip): ms_b sources per task with their
+    // path counts interleaved (sigma[v * ms_b + b]); per slot the masks of
+    // sources newly reaching each vertex (nx), the union level lists' source
+    // masks (lm, ms_cap entries per slot, as lv/la/ld), and the visited
+    // masks of vertices ms_nl and up (visg; those below ms_nl sit in LDS)
+    int32_t ms_b;
+    int32_t ms_nl;
+    long long ms_cap;
+    long long nsources;        // sources of a single-graph task list (tasks = ceil(nsources / ms_b))
+    uint32_t *nx;
+    uint32_t *lm;
+    uint32_t *visg;
+    long long visg_words;      // per-slot words of visg
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.
@@ -126,6 +139,12 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds);
 // fit one workgroup's LDS (nk_lds.hip); lds_graph_bytes is its dynamic LDS
 // size for a graph of n vertices and m arcs.
 KernelRef brandes_lds_kernel(int block);
+
+// Multi-source kernel (nk_multi.hip) for `b` sources per task (4, 8 or
+// 16); its dynamic LDS holds the visited masks of the first vertices.
+KernelRef brandes_ms_kernel(int block, int b);
+// Bytes of visited mask per vertex for b sources per task.
+int ms_mask_bytes(int b);
 size_t lds_graph_bytes(int32_t n, int64_t m);
 hipError_t launch_validate_batched(const int32_t *rowptr_cat, const int32_t *colidx_cat, const long long *g_vtx,
                                    const long long *g_arc, int32_t G, DevStatus *st, hipStream_t s);

@@ -95,6 +95,28 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
 // when the tuning leaves it open.
 int auto_block(int32_t n_max);
 
+// Multi-source launch (nk_multi.hip): b sources per task.
+struct MsPlan {
+    LaunchPlan lp;
+    int b;
+    int32_t nl;            // vertices whose visited masks sit in LDS
+    long long stride;      // per-slot vertex capacity
+    long long cap;         // per-slot union-list capacity (stride * b)
+    long long visg_words;  // per-slot words of global masks
+    long long ntasks;      // tasks of the launch (set by plan_ms for a single graph)
+};
+// Sources per task for a graph of at most n_max vertices (the tuning's
+// batch, or the automatic choice); 1 means the one-source kernels.
+int ms_batch_for(int32_t n_max, long long nsources);
+// Plan for graphs of at most n_max vertices and `nsources` sources in all
+// (tasks = ceil(nsources / b)).
+nk_status plan_ms(int b, int32_t n_max, long long nsources, MsPlan *mp);
+nk_status ms_alloc(const MsPlan &mp, Params &p, Scratch &scr);
+// Clears the path counts, new-source masks and global visited masks, then
+// launches (p.ntasks is replaced by the plan's task count).
+nk_status ms_enqueue(const MsPlan &mp, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+void stats_set_batch(int b);
+
 // Grid-wide direction-optimising breadth-first search (nk_bfs.hip).
 struct BfsWork {
     int32_t *d;        // n distances from the source (-1 unreached)
