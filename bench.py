@@ -1,16 +1,33 @@
-"""Benchmark: source-sampled Brandes betweenness on one MI355X.
+"""Benchmark: Brandes betweenness on one MI355X.
 
-Workload (one step = one pass of the whole hot path over one batch):
-R-MAT scale 20, edge factor 16, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05),
-seed 2, symmetrised / deduplicated / self-loops removed (2^20 vertices,
-about 31.4M arcs); 4096 distinct uniform sources (seed 2); scores scaled by
-n / 4096.  A step is one nk_bc_sources call: CSR validation, the persistent
-Brandes kernel (forward path counting + FP64 dependency sweep) and scaling.
-Inputs are resident in HBM before the timed region.
+Headline (`value`): source-sampled betweenness on R-MAT scale 20, edge
+factor 16, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), seed 2, symmetrised /
+deduplicated / self-loops removed (2^20 vertices, about 31.4M arcs); 4096
+distinct uniform sources (seed 2); scores scaled by n / 4096.  A step is one
+nk_bc_sources call: CSR validation, the persistent Brandes kernel (forward
+path counting + FP64 dependency sweep) and scaling.  Inputs are resident in
+HBM before the timed region.
+
+The same JSON line also carries:
+  batched          exact betweenness of the 512-graph batch (n log-uniform
+                   in [1e3, 2e5], even graphs Erdos-Renyi m = 4n, odd ones
+                   Barabasi-Albert m0 = 4, seed 4) as ONE captured launch of
+                   the whole batch, progress read from the device while it
+                   runs; one timed pass;
+  pair_sampling    Riondato-Kornaropoulos pair sampling on the Chung-Lu graph
+                   (n = 4e6, exponent 2.5, mean degree 20, seed 3), eps 0.01,
+                   delta 0.1;
+  per_source_kernel  the plain per-source form (one launch, one workgroup,
+                   per source) on the headline graph and on the batch's
+                   largest graph, for comparison with the persistent forms;
+  serving          a short Poisson request stream through the server;
+  cpu_baseline     the CPU oracle on a bounded sample, on this GPU's share
+                   of the host's cores, with the host's CPU model.
 
 Prints one JSON line.  GTEPS = sources x undirected edges / time / 1e9.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                  [--no-batched] [--no-pairs] [--no-serving]
 """
 from __future__ import annotations
 
@@ -29,7 +46,8 @@ PEAK_HBM_GBS = 8000.0
 KERNEL = "k_brandes"
 # nk_last_stats "bitmap_lds" -> which kernel ran
 PLACEMENT = {0: "k_brandes (global bitmap)", 1: "k_brandes (LDS bitmap)", 2: "k_brandes_lds (all in LDS)",
-             3: "k_brandes_lds + k_brandes (LDS bitmap)"}
+             3: "k_brandes_lds + k_brandes (LDS bitmap)", 4: "k_brandes_ms (multi-source)",
+             5: "k_brandes_lds + k_brandes_ms (multi-source)"}
 
 
 def kernel_source_hash() -> str:
@@ -54,6 +72,41 @@ def counter_traffic(workload: str):
     return float(m_bytes.group(1))
 
 
+def cpu_threads() -> int:
+    """Oracle threads: the cores this process may run on, at most 16 (one
+    GPU's share of the host)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def machine_info() -> dict:
+    """The host CPU as lscpu reports it (model, sockets, cores, SMT)."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return info
+    keys = {"Model name": "cpu_model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU(s)": "logical_cpus"}
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keys:
+            v = v.strip()
+            info[keys[k.strip()]] = int(v) if v.isdigit() else v
+    if isinstance(info.get("sockets"), int) and isinstance(info.get("cores_per_socket"), int):
+        info["physical_cores"] = info["sockets"] * info["cores_per_socket"]
+    try:
+        info["cpus_available_to_process"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
+
+
 def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = "plain"):
     """The oracle (plain Brandes, the paper's per-thread-array parallel
     pattern; or its linear-scaling / bisection / edge form) on a bounded
@@ -74,7 +127,7 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = 
         else:
             oracle.bc_sources(g.rowptr, g.colidx, sources, 1.0, nthreads=threads)
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = cpu_threads()
     probe = 16
     t0 = time.perf_counter()
     run(src[:probe], 1)
@@ -89,6 +142,8 @@ def cpu_baseline(g, src, n_undirected: int, target_s: float = 15.0, kind: str = 
         "cores": threads,
         "kind": "oracle",
         "sample": f"first {k} of the {len(src)} sources, same graph, {dt:.1f} s wall",
+        "machine": machine_info(),
+        "note": "threads = this GPU's share of the host (16) or fewer if fewer cores are available",
     }
 
 
@@ -102,6 +157,172 @@ def _timed(fn, steps: int, warmup: int):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def alg_bytes(st: dict) -> int:
+    """Algorithmic bytes of Brandes' sweeps over the sources of a launch: per
+    source 68 per reached vertex, 16 per arc of a reached vertex, 24 per
+    shortest-path DAG arc (the counts come from the kernel's own counters,
+    equal to the oracle's)."""
+    return 68 * st["reached"] + 16 * st["arcs_reached"] + 24 * st["dag_arcs"]
+
+
+def roofline(bytes_: float, seconds: float, kernel: str, traffic=None) -> dict:
+    gbs = bytes_ / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": int(bytes_)}
+
+
+def per_source_kernel(g, sources, rp, ci, label: str) -> dict:
+    """The plain per-source form: one nk_bc_sources call, and so one launch
+    of one workgroup, per source; GTEPS and the HBM fraction of its kernel
+    time, for comparison with the persistent many-source launch."""
+    import numpy as np
+    import torch
+
+    import paper_1403_3005_amd as nk
+    dev = rp.device
+    bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+    one = torch.empty(1, dtype=torch.int32, device=dev)
+    # one untimed call loads the kernel
+    one.fill_(int(sources[0]))
+    nk.nk_bc_sources(rp, ci, one, 1.0, bc=bc)
+    torch.cuda.synchronize()
+    kern_s, byts = 0.0, 0
+    t0 = time.perf_counter()
+    for s_ in sources:
+        one.fill_(int(s_))
+        nk.nk_bc_sources(rp, ci, one, 1.0, bc=bc)
+        st = nk.nk_last_stats()
+        assert st["workgroups"] == 1
+        kern_s += st["kernel_us"] * 1e-6
+        byts += alg_bytes(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = len(sources)
+    return {"graph": label, "sources": k, "launches": k, "workgroups_per_launch": 1,
+            "gteps": round(k * g.m_undirected / wall / 1e9, 3),
+            "gteps_kernel_only": round(k * g.m_undirected / kern_s / 1e9, 3),
+            "ms_per_source": round(wall / k * 1e3, 3),
+            "roofline": roofline(byts, kern_s, "k_brandes (one workgroup per launch)")}
+
+
+def pair_record(args) -> dict:
+    """Pair sampling (eps 0.01, delta 0.1, seed 3) on the Chung-Lu graph with
+    n = 4e6: samples/s over `steps` calls, and the pair kernel's roofline.
+    Algorithmic bytes of a sample's bidirectional search: 16 per scanned arc
+    (its column index and the head's distance and path count) and 36 per
+    reached vertex (its list entry, its record written and reset)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_1403_3005_amd as nk
+    print("bench: generating Chung-Lu n=4e6 (seed 3)", file=sys.stderr, flush=True)
+    g = gg.workload_chung_lu4m(3)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.rowptr).to(dev)
+    ci = torch.from_numpy(g.colidx).to(dev)
+    box = {}
+
+    def run():
+        box["r"] = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
+        box["st"] = nk.nk_last_stats()
+
+    steps = max(1, min(args.steps, 10))
+    sec = _timed(run, steps, 1)
+    st = box["st"]
+    bc, cnt, r, vd = box["r"]
+    kern_s = st["kernel_us"] * 1e-6
+    byts = 16 * st["arcs_fwd"] + 36 * st["reached"]
+    print(f"bench: pair sampling {r} samples, {sec * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+    rec = {"metric": "pair samples per second (Riondato-Kornaropoulos, eps 0.01, delta 0.1)",
+           "workload": "chunglu4m_pairs", "value": round(r / sec, 1), "unit": "samples/s", "steps": steps,
+           "warmup": 1, "ms_per_step": round(sec * 1e3, 2), "n": g.n, "arcs": g.m, "r": r, "vd_bound": vd,
+           "r_times_edges_gteps": round(r * g.m_undirected / sec / 1e9, 3), "kernel_ms": round(kern_s * 1e3, 2),
+           "arcs_scanned": st["arcs_fwd"], "reached": st["reached"],
+           "roofline": roofline(byts, kern_s, "k_brandes (pair mode)")}
+    if not args.no_cpu_baseline:
+        threads = cpu_threads()
+        ns = 400 * threads
+        t0 = time.perf_counter()
+        oracle.pair_counts(g.rowptr, g.colidx, ns, 3, nthreads=threads)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": round(ns / dt, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
+                               "sample": f"first {ns} samples of the same sequence, {dt:.1f} s wall"}
+    return rec
+
+
+def batched_record(args) -> dict:
+    """Exact betweenness of the 512-graph batch as one captured launch
+    (nk_batch_plan_*): graphs whose CSR and one source's state fit a
+    workgroup's LDS run on the all-in-LDS kernel, the others on the
+    persistent kernel, in one replay of the plan's graph.  One timed pass;
+    progress lines come from the device's count of finished sources."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import oracle
+    import paper_1403_3005_amd as nk
+    print("bench: generating the 512-graph batch (seed 4)", file=sys.stderr, flush=True)
+    graphs = gg.workload_batched(512, 1000, 200_000, 4)
+    work = sum(g.n * g.m_undirected for g in graphs)
+    vtx = np.zeros(len(graphs) + 1, dtype=np.int64)
+    arc = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vtx[i + 1] = vtx[i] + g.n
+        arc[i + 1] = arc[i] + g.m
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(np.concatenate([g.rowptr for g in graphs]).astype(np.int32)).to(dev)
+    ci = torch.from_numpy(np.concatenate([g.colidx for g in graphs]).astype(np.int32)).to(dev)
+    stream = torch.cuda.Stream()
+    with nk.NkBatchPlan(vtx, arc, rp, ci) as plan:
+        torch.cuda.synchronize()
+        print(f"bench: batched: one launch over {len(graphs)} graphs, {int(vtx[-1])} sources", file=sys.stderr,
+              flush=True)
+        t0 = time.perf_counter()
+        plan.launch(stream)
+        next_report = 0.1
+        while True:
+            done, total, finished = plan.progress()
+            if finished:
+                break
+            if done >= next_report * total:
+                print(f"bench: batched: {100.0 * done / total:.0f}% of sources done after "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+                while next_report * total <= done:
+                    next_report += 0.1
+            time.sleep(0.5)
+        plan.finish(stream)
+        sec = time.perf_counter() - t0
+        st = nk.nk_last_stats()
+    kern_s = st["kernel_us"] * 1e-6
+    print(f"bench: batched: {sec:.1f} s ({work / sec / 1e9:.2f} GTEPS)", file=sys.stderr, flush=True)
+    rec = {"metric": "GTEPS, exact Brandes on a batch of 512 graphs in one launch", "workload": "batched512_exact",
+           "value": round(work / sec / 1e9, 3), "unit": "GTEPS", "steps": 1, "warmup": 0,
+           "ms_per_step": round(sec * 1e3, 1), "graphs": len(graphs), "n_total": int(vtx[-1]),
+           "arcs_total": int(arc[-1]), "source_edges": work, "n_range": [1000, 200_000], "launches": 1,
+           "kernel_ms": round(kern_s * 1e3, 1), "kernels": PLACEMENT.get(st["bitmap_lds"], st["bitmap_lds"]),
+           "block": st["block"], "workgroups": st["workgroups"], "sources_per_task": st["sources_per_task"],
+           "roofline": roofline(alg_bytes(st), kern_s, "k_brandes_lds + k_brandes (batched, whole run)")}
+    big = max(graphs, key=lambda g: g.n)
+    grp, gci = torch.from_numpy(big.rowptr).to(dev), torch.from_numpy(big.colidx).to(dev)
+    rec["per_source_kernel"] = per_source_kernel(big, list(range(0, big.n, big.n // 16))[:16], grp, gci,
+                                                 f"largest graph of the batch (n = {big.n})")
+    if not args.no_cpu_baseline:
+        threads = cpu_threads()
+        small = sorted(graphs, key=lambda g: g.n)[:16]
+        t0 = time.perf_counter()
+        for g in small:
+            oracle.bc_exact(g.rowptr, g.colidx, nthreads=threads)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": round(sum(g.n * g.m_undirected for g in small) / dt / 1e9, 4),
+                               "unit": "GTEPS", "cores": threads, "kind": "oracle",
+                               "sample": f"the 16 smallest graphs of the batch, exact, {dt:.1f} s wall"}
+    return rec
 
 
 def other_workload(args) -> dict:
@@ -274,69 +495,13 @@ def other_workload(args) -> dict:
                    {"value": round(1.0 / cpu, 2), "unit": "samples/s", "cores": 1, "kind": "oracle",
                     "sample": "first 200 pairs of the same sample sequence"})
     else:
-        count = 512 if args.workload == "batched512" else 64
-        hi = 200_000 if args.workload == "batched512" else 20_000
-        print(f"bench: generating {count} graphs", file=sys.stderr, flush=True)
-        graphs = []
-        for i, n in enumerate(gg.batched_sizes(count, 1000, hi, 4)):
-            gs = gg.draw(4, 61, i, 0)
-            graphs.append(gg.erdos_renyi(n, 4 * n, gs) if i % 2 == 0 else gg.barabasi_albert(n, 4, gs))
-            if (i + 1) % 64 == 0:
-                print(f"bench: {i + 1} graphs generated", file=sys.stderr, flush=True)
-        work = sum(g.n * g.m_undirected for g in graphs)
-        # the batch runs as launches of 64 graphs each (one persistent launch
-        # per group) so that a long batch reports progress between launches
-        groups = []
-        for c0 in range(0, count, 64):
-            part = graphs[c0:c0 + 64]
-            vtx = np.zeros(len(part) + 1, dtype=np.int64)
-            arc = np.zeros(len(part) + 1, dtype=np.int64)
-            for i, g in enumerate(part):
-                vtx[i + 1] = vtx[i] + g.n
-                arc[i + 1] = arc[i] + g.m
-            groups.append((vtx, arc, up(np.concatenate([g.rowptr for g in part]).astype(np.int32)),
-                           up(np.concatenate([g.colidx for g in part]).astype(np.int32))))
-
-        def run_all():
-            for gi, (vtx, arc, rp, ci) in enumerate(groups):
-                nk.nk_bc_exact_batched(vtx, arc, rp, ci)
-                if len(groups) > 1:
-                    print(f"bench: group {gi + 1}/{len(groups)} done", file=sys.stderr, flush=True)
-
-        sec = _timed(run_all, args.steps, args.warmup)
-        st = nk.nk_last_stats()
-        # the same batch as captured HIP graphs (one plan per launch group),
-        # replayed: the value stays the eager call's; this is reported beside it
-        plans = [nk.NkBatchPlan(*grp) for grp in groups]
-
-        def replay_all():
-            for gi, pl in enumerate(plans):
-                pl.run()
-                if len(plans) > 1:
-                    print(f"bench: replay of group {gi + 1}/{len(plans)} done", file=sys.stderr, flush=True)
-
-        sec_replay = _timed(replay_all, args.steps, 1)
-        for pl in plans:
-            pl.close()
-        vtx = np.array([0, sum(g.n for g in graphs)])
-        arc = np.array([0, sum(g.m for g in graphs)])
-        small = sorted(graphs, key=lambda g: g.n)[:4]
-        t0 = time.perf_counter()
-        for g in small:
-            oracle.bc_exact(g.rowptr, g.colidx)
-        cpu = time.perf_counter() - t0
-        rec.update(metric="GTEPS, exact Brandes on a batch of graphs in one launch", unit="GTEPS", dtype="f64",
-                   value=round(work / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 1),
-                   config={"workload": f"batched{count}", "graphs": count, "n_total": int(vtx[-1]),
-                           "arcs_total": int(arc[-1]), "n_range": [1000, hi], "launches": len(groups),
-                           "last_launch_kernel_ms": st["kernel_us"] / 1e3,
-                           "kernels": PLACEMENT[st["bitmap_lds"]],
-                           "block": st["block"], "workgroups": st["workgroups"],
-                           "graph_replay_ms_per_step": round(sec_replay * 1e3, 1),
-                           "graph_replay_gteps": round(work / sec_replay / 1e9, 3)},
-                   cpu_baseline={"value": round(sum(g.n * g.m_undirected for g in small) / cpu / 1e9, 4),
-                                 "unit": "GTEPS", "cores": 1, "kind": "oracle",
-                                 "sample": "the 4 smallest graphs of the batch, exact"})
+        b = batched_record(args)
+        rec.update(metric=b.pop("metric"), unit=b.pop("unit"), dtype="f64", value=b.pop("value"),
+                   ms_per_step=b.pop("ms_per_step"), steps=b.pop("steps"), warmup=b.pop("warmup"),
+                   roofline=b.pop("roofline"))
+        if "cpu_baseline" in b:
+            rec["cpu_baseline"] = b.pop("cpu_baseline")
+        rec["config"] = b
     return rec
 
 
@@ -432,12 +597,14 @@ def main():
                     help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-graph batch (about 5 minutes)")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the pair-sampling record")
     ap.add_argument("--serving-qps", type=float, default=8.0)
     ap.add_argument("--serving-requests", type=int, default=96,
                     help="requests of the default serving line; measured requests per point of --workload serving")
     ap.add_argument("--serving-warm", type=int, default=50, help="warm-up requests per point of --workload serving")
     ap.add_argument("--workload", default="rmat20",
-                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "batched64", "rmat20_linear", "rmat20_bisect", "rmat20_directed", "rmat20_weighted",
+                    choices=["rmat20", "er2000", "chunglu4m", "batched512", "rmat20_linear", "rmat20_bisect", "rmat20_directed", "rmat20_weighted",
                              "rmat20_edge", "rmat20_closeness", "er200k", "serving"],
                     help="rmat20 (default, the headline line); the others time the other configurations")
     args = ap.parse_args()
@@ -571,6 +738,13 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    print("bench: per-source kernel baseline", file=sys.stderr, flush=True)
+    out["per_source_kernel"] = per_source_kernel(g, [int(x) for x in src[:32]], rp, ci,
+                                                 "the headline graph, its first 32 sources")
+    if not args.no_pairs:
+        out["pair_sampling"] = pair_record(args)
+    if not args.no_batched:
+        out["batched"] = batched_record(args)
     if not args.no_serving:
         out["serving"] = serving_run(args.serving_qps, args.serving_requests)
     if not args.no_cpu_baseline:

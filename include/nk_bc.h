@@ -377,6 +377,23 @@ nk_status nk_batch_plan_run(nk_batch_plan *plan, void *stream);
 void nk_batch_plan_destroy(nk_batch_plan *plan);
 
 /*
+ * The same run in two halves, for long batches whose caller wants to see
+ * the run advance: nk_batch_plan_launch enqueues the graph on `stream` and
+ * returns at once; nk_batch_plan_progress reports *done = sources whose
+ * dependency sweep has finished so far (read from the device while the run
+ * goes on, on the plan's own stream), *total = all sources of the batch,
+ * and *finished = 1 once the launch has completed; nk_batch_plan_finish
+ * (same stream) waits, reads the status and records the statistics, as
+ * nk_batch_plan_run does.  A launched plan must be finished before it is
+ * launched again (NK_E_INVALID_ARG otherwise).  The progress read needs
+ * `stream` not to be the legacy default stream, which waits for every
+ * other stream.
+ */
+nk_status nk_batch_plan_launch(nk_batch_plan *plan, void *stream);
+nk_status nk_batch_plan_progress(nk_batch_plan *plan, int64_t *done, int64_t *total, int32_t *finished);
+nk_status nk_batch_plan_finish(nk_batch_plan *plan, void *stream);
+
+/*
  * Statistics of the calling thread's last nk_bc_exact / nk_bc_sources /
  * nk_bc_exact_batched / pair-sampling call (HOST out[32]):
  *   out[0] sources (or samples) processed     out[1] vertices reached

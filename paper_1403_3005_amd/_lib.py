@@ -36,6 +36,7 @@ EXPORTS = [
     "nk_bc_sources_linear", "nk_bc_sources_bisect", "nk_bc_directed", "nk_bc_weighted", "nk_transpose", "nk_edge_bc", "nk_closeness", "nk_closeness_sampled",
     "nk_sssp_counts", "nk_vd_bound", "nk_rk_sample_size", "nk_bc_pair_sample", "nk_pair_counts",
     "nk_sample_paths", "nk_bc_exact_batched", "nk_batch_plan_create", "nk_batch_plan_run", "nk_batch_plan_destroy",
+    "nk_batch_plan_launch", "nk_batch_plan_progress", "nk_batch_plan_finish",
     "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
     "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy", "nk_autotune", "nk_tuning_lookup",
@@ -90,6 +91,9 @@ def load():
         "nk_bc_exact_batched": (c.c_int32, [c.c_int32, i64p, i64p, vp, vp, vp, vp]),
         "nk_batch_plan_create": (c.c_int32, [c.c_int32, i64p, i64p, vp, vp, vp, c.POINTER(vp)]),
         "nk_batch_plan_run": (c.c_int32, [vp, vp]),
+        "nk_batch_plan_launch": (c.c_int32, [vp, vp]),
+        "nk_batch_plan_progress": (c.c_int32, [vp, i64p, i64p, i32p]),
+        "nk_batch_plan_finish": (c.c_int32, [vp, vp]),
         "nk_batch_plan_destroy": (None, [vp]),
         "nk_last_stats": (c.c_int32, [i64p]),
         "nk_set_tuning": (c.c_int32, [c.POINTER(NkTuning)]),
@@ -398,6 +402,21 @@ class NkBatchPlan:
 
     def run(self, stream=None):
         _check(load().nk_batch_plan_run(self._h, _stream(stream)))
+        return self.bc
+
+    def launch(self, stream=None):
+        """Enqueues a run and returns at once (see progress, finish)."""
+        _check(load().nk_batch_plan_launch(self._h, _stream(stream)))
+
+    def progress(self):
+        """(sources done, sources in all, finished) of the launched run."""
+        d, t, f = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(load().nk_batch_plan_progress(self._h, ctypes.byref(d), ctypes.byref(t), ctypes.byref(f)))
+        return int(d.value), int(t.value), bool(f.value)
+
+    def finish(self, stream=None):
+        """Waits for the launched run, checks its status; returns the scores."""
+        _check(load().nk_batch_plan_finish(self._h, _stream(stream)))
         return self.bc
 
     def close(self):

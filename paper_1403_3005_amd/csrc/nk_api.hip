@@ -1619,6 +1619,9 @@ struct nk_batch_plan {
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the last launch
+    unsigned long long *done_h = nullptr;      // pinned: progress counter read back
+    bool running = false;
 };
 
 extern "C" {
@@ -1675,32 +1678,83 @@ nk_status nk_batch_plan_create(int32_t G, const int64_t *vtx_off, const int64_t 
         if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess)
             return bail(fail(NK_E_HIP, "graph instantiation failed"));
     }
+    if (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess)
+        return bail(fail(NK_E_HIP, "event creation failed"));
+    if (hipHostMalloc((void **)&pl->done_h, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        pl->done_h = nullptr;
+        return bail(fail(NK_E_NO_MEMORY, "pinned progress buffer"));
+    }
     *out = pl;
     return NK_OK;
 }
 
-nk_status nk_batch_plan_run(nk_batch_plan *plan, void *stream) {
-    clear_error();
-    stats_clear();
+static nk_status plan_check(nk_batch_plan *plan) {
     if (!plan) return fail(NK_E_INVALID_ARG, "plan is NULL");
-    if (plan->b.nv == 0) return NK_OK;
     int dev = 0;
     NK_HIP(hipGetDevice(&dev));
     if (dev != plan->device) return fail(NK_E_INVALID_ARG, "plan was made on device %d, current is %d", plan->device, dev);
+    return NK_OK;
+}
+
+nk_status nk_batch_plan_launch(nk_batch_plan *plan, void *stream) {
+    clear_error();
+    nk_status st = plan_check(plan);
+    if (st != NK_OK) return st;
+    if (plan->running) return fail(NK_E_INVALID_ARG, "the plan's previous run has not been finished");
+    if (plan->b.nv == 0) return NK_OK;
+    hipStream_t s = (hipStream_t)stream;
+    NK_HIP(hipEventRecord(plan->ev0, s));
+    NK_HIP(hipGraphLaunch(plan->exec, s));
+    NK_HIP(hipEventRecord(plan->ev1, s));
+    plan->running = true;
+    return NK_OK;
+}
+
+nk_status nk_batch_plan_progress(nk_batch_plan *plan, int64_t *done, int64_t *total, int32_t *finished) {
+    clear_error();
+    nk_status st = plan_check(plan);
+    if (st != NK_OK) return st;
+    if (!done || !total || !finished) return fail(NK_E_INVALID_ARG, "NULL output");
+    *total = plan->b.nv;
+    if (!plan->running || plan->b.nv == 0) {
+        *done = plan->running ? 0 : plan->b.nv;
+        *finished = 1;
+        return NK_OK;
+    }
+    // the counter is read on the plan's own (non-blocking) stream while the
+    // run goes on on the caller's
+    NK_HIP(hipMemcpyAsync(plan->done_h, &plan->b.dst->stat[kStDone], sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, plan->cs));
+    NK_HIP(hipStreamSynchronize(plan->cs));
+    const hipError_t q = hipEventQuery(plan->ev1);
+    if (q != hipSuccess && q != hipErrorNotReady) return fail(NK_E_HIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+    *finished = q == hipSuccess;
+    *done = (int64_t)*plan->done_h;
+    return NK_OK;
+}
+
+nk_status nk_batch_plan_finish(nk_batch_plan *plan, void *stream) {
+    clear_error();
+    stats_clear();
+    nk_status st = plan_check(plan);
+    if (st != NK_OK) return st;
+    if (plan->b.nv == 0) return NK_OK;
+    if (!plan->running) return fail(NK_E_INVALID_ARG, "the plan has no run to finish");
+    plan->running = false;
     hipStream_t s = (hipStream_t)stream;
     DevStatus *h = host_status();
     if (!h) return fail(NK_E_NO_MEMORY, "pinned status buffer");
-    hipEvent_t ev0, ev1;
-    nk_status st;
-    if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
-    NK_HIP(hipEventRecord(ev0, s));
-    NK_HIP(hipGraphLaunch(plan->exec, s));
-    NK_HIP(hipEventRecord(ev1, s));
     st = finish(plan->b.dst, h, s);
     float ms = 0.0f;
-    NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    NK_HIP(hipEventElapsedTime(&ms, plan->ev0, plan->ev1));
     batch_stats(plan->b, *h, ms);
     return st;
+}
+
+nk_status nk_batch_plan_run(nk_batch_plan *plan, void *stream) {
+    nk_status st = nk_batch_plan_launch(plan, stream);
+    if (st != NK_OK) return st;
+    return nk_batch_plan_finish(plan, stream);
 }
 
 void nk_batch_plan_destroy(nk_batch_plan *plan) {
@@ -1708,7 +1762,11 @@ void nk_batch_plan_destroy(nk_batch_plan *plan) {
     if (plan->cs) (void)hipStreamSynchronize(plan->cs);
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->running && plan->ev1) (void)hipEventSynchronize(plan->ev1);
     if (plan->cs) (void)hipStreamDestroy(plan->cs);
+    if (plan->ev0) (void)hipEventDestroy(plan->ev0);
+    if (plan->ev1) (void)hipEventDestroy(plan->ev1);
+    if (plan->done_h) (void)hipHostFree(plan->done_h);
     delete plan->scr;
     delete plan;
 }

@@ -42,6 +42,7 @@ enum PairSubIdx { kSbPairSearch = 0, kSbPairSelect, kSbPairWalk, kSbPairClear };
 
 enum StatIdx {
     kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached, kStBwPush,
+    kStDone,   // sources (or samples) finished so far, added as each task ends (progress of a long run)
     kNumStats = 12
 };
 

@@ -1737,12 +1737,18 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             // an isolated endpoint leaves the pair unreachable
             if (g.rp[target + 1] == g.rp[target] || g.rp[src + 1] == g.rp[src]) {
                 if (tid == 0 && p.p_len) p.p_len[task] = -1;
-                if (tid == 0) c.tasks++;
+                if (tid == 0) {
+                    c.tasks++;
+                    atomicAdd(&p.st->stat[kStDone], 1ULL);
+                }
                 continue;
             }
             phase_start<BLOCK>(sm);
             bidir_sample<BLOCK>(p, sm, bs, rec, s, s2, g, src, target, j, task, c);
-            if (tid == 0) c.tasks++;
+            if (tid == 0) {
+                c.tasks++;
+                atomicAdd(&p.st->stat[kStDone], 1ULL);
+            }
             phase_end<BLOCK>(sm, kPhTd);
             continue;
         } else if constexpr (MODE == kModeWeighted) {
@@ -1776,6 +1782,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             if (tid == 0) {
                 c.reached += (unsigned long long)nreach;
                 c.tasks++;
+                atomicAdd(&p.st->stat[kStDone], 1ULL);
             }
             __syncthreads();
             phase_end<BLOCK>(sm, kPhReset);
@@ -1819,6 +1826,7 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
         __syncthreads();
         phase_start<BLOCK>(sm);
         for (int32_t i = tid; i < nreached; i += BLOCK) s.sigma[s.lv[i]] = 0ULL;
+        if (tid == 0) atomicAdd(&p.st->stat[kStDone], 1ULL);
         __syncthreads();
         phase_end<BLOCK>(sm, kPhReset);
         }  // non-pair modes

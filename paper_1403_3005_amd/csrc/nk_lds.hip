@@ -197,6 +197,7 @@ __device__ void lds_source(const Params &p, Tile<BLOCK> &sm, const LdsGraph &L, 
     if (tid == 0) {
         c.reached += (unsigned long long)f1;
         c.tasks++;
+        atomicAdd(&p.st->stat[kStDone], 1ULL);
     }
     const int32_t Ld = lvl;
     if (Ld == 0) return;

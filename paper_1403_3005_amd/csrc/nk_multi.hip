@@ -725,7 +725,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes_ms(Params p) {
             if (v >= S.nl) vis_clear<B>(S, v, MsVis<B>::kField);
         }
         __syncthreads();
-        if (tid == 0) sm.cyc[kPhReset] += (unsigned long long)(clock64() - sm.t0);
+        if (tid == 0) {
+            sm.cyc[kPhReset] += (unsigned long long)(clock64() - sm.t0);
+            atomicAdd(&p.st->stat[kStDone], (unsigned long long)nsrc);
+        }
     }
 
     // counters: wave sums of the DAG arcs, one atomic per wave; the rest

@@ -79,3 +79,35 @@ def test_batch_plan_empty_and_bad_arguments():
         assert plan.run().numel() == 0
     with pytest.raises(nk.NkError):
         nk.NkBatchPlan(np.array([1, 2], dtype=np.int64), np.array([0, 0], dtype=np.int64), rp, ci)
+
+
+def test_batch_plan_launch_progress_finish():
+    """The run in halves on a stream of its own: progress is read while the
+    run goes on (never decreasing, never above the total), reaches every
+    source once the launch has completed, and finish returns the eager
+    scores; a second launch before finishing is refused."""
+    nk.nk_set_tuning()
+    graphs = _graphs() + [gg.erdos_renyi(60000, 240000, 148)]
+    vtx, arc, rp, ci = _batch(graphs)
+    eager = nk.nk_bc_exact_batched(vtx, arc, rp, ci).cpu().numpy()
+    stream = torch.cuda.Stream()
+    with nk.NkBatchPlan(vtx, arc, rp, ci) as plan:
+        for r in range(2):
+            plan.launch(stream)
+            with pytest.raises(nk.NkError):
+                plan.launch(stream)
+            seen = []
+            for _ in range(200000):
+                done, total, finished = plan.progress()
+                assert total == int(vtx[-1]) and 0 <= done <= total
+                seen.append(done)
+                if finished:
+                    break
+            assert finished and seen == sorted(seen)
+            done, total, _ = plan.progress()
+            assert done == total
+            got = plan.finish(stream).cpu().numpy()
+            assert nk.nk_last_stats()["sources"] == total
+            assert_scores_close(got, eager, f"launched run {r}")
+        with pytest.raises(nk.NkError):
+            plan.finish(stream)
