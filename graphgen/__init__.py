@@ -26,7 +26,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
-_LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
+# NK_SANITIZE=1 selects a build instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the host process must preload the ASan runtime)
+_SANITIZE = os.environ.get("NK_SANITIZE") == "1"
+_LIB_PATH = os.path.join(_HERE, "libgraphgen_san.so" if _SANITIZE else "libgraphgen.so")
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 _lib = None
 
 
@@ -34,7 +38,8 @@ def build(force: bool = True) -> str:
     """Compile gen.c into libgraphgen.so next to it."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc"] + opt + ["-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

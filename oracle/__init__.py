@@ -21,7 +21,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "brandes.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# NK_SANITIZE=1 selects a build instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the host process must preload the ASan runtime)
+_SANITIZE = os.environ.get("NK_SANITIZE") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 _lib = None
 
 OK, E_INVALID_ARG, E_INVALID_GRAPH, E_SIGMA_OVERFLOW, E_NO_MEMORY = 0, -1, -2, -3, -4
@@ -37,7 +41,8 @@ def build(force: bool = True) -> str:
     """Compile brandes.c into liboracle.so (plain C, -O2)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
+        opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc"] + opt + ["-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
