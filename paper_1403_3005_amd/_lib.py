@@ -40,6 +40,7 @@ EXPORTS = [
     "nk_last_stats", "nk_set_tuning", "nk_get_tuning",
     "nk_server_create", "nk_server_add_graph", "nk_server_submit", "nk_server_wait", "nk_server_poll",
     "nk_server_stats", "nk_server_reset_stats", "nk_server_destroy", "nk_autotune", "nk_tuning_lookup",
+    "nk_set_tuning_cache",
 ]
 
 
@@ -109,6 +110,7 @@ def load():
         "nk_server_destroy": (None, [vp]),
         "nk_autotune": (c.c_int32, g + [vp, c.c_int32, c.c_char_p, c.POINTER(NkTuning), vp]),
         "nk_tuning_lookup": (c.c_int32, [c.c_char_p, c.c_int32, c.c_int64, c.c_int64, c.POINTER(NkTuning)]),
+        "nk_set_tuning_cache": (c.c_int32, [c.c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -465,6 +467,12 @@ def nk_get_tuning() -> dict:
 def _tuning_dict(t) -> dict:
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
             "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib, "batch": t.batch}
+
+
+def nk_set_tuning_cache(cache_path: str | None) -> None:
+    """Registers an autotuner cache (None unregisters): later calls on graphs
+    whose shape has an entry run under it (see include/nk_bc.h)."""
+    _check(load().nk_set_tuning_cache(cache_path.encode() if cache_path else None))
 
 
 def nk_autotune(rowptr, colidx, sources, cache_path: str | None = None, stream=None) -> dict:

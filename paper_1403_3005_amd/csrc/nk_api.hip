@@ -221,10 +221,20 @@ size_t pool_bytes_in_use() {
 static std::mutex g_tune_mu;
 static nk_tuning g_tune = {0, 16.0f, 0, 0, 0.1f, 0, 0, 0};
 
+// A call running under a cached per-graph-shape tuning sees it instead of
+// the global one (thread-local, set for the duration of the call).
+static thread_local const nk_tuning *t_override = nullptr;
+
 nk_tuning tuning_get() {
+    if (t_override) return *t_override;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     return g_tune;
 }
+
+TuningOverride::TuningOverride(const nk_tuning *t) : prev_(t_override) {
+    if (t) t_override = t;
+}
+TuningOverride::~TuningOverride() { t_override = prev_; }
 
 void tuning_set(const nk_tuning &t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -779,6 +789,15 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
     if (k < 0) return fail(NK_E_INVALID_ARG, "k is negative");
     if (k > 0 && !sources && k != n) return fail(NK_E_INVALID_ARG, "sources is NULL");
     hipStream_t s = (hipStream_t)stream;
+    // a registered autotuner cache supplies the tuning for this graph's shape
+    nk_tuning cached;
+    bool use_cached = false;
+    if (tuning_cache_active()) {
+        int64_t dmax = 0;
+        if ((st = graph_max_degree(rowptr, n, s, &dmax)) != NK_OK) return st;
+        use_cached = cached_tuning(n, m, dmax, &cached);
+    }
+    TuningOverride cached_scope(use_cached ? &cached : nullptr);
     Scratch scr;
     DevStatus *dst;
     uint32_t *iso;
@@ -1546,6 +1565,20 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
         if ((st = tables(small, &b->t_small, &b->o_small, &b->k_small, 1)) != NK_OK) return st;
         if (!plan_lds(dyn_max, n_small, b->k_small, &b->plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
     }
+    // the large graphs' launch runs under the registered autotuner cache's
+    // tuning for the largest of them, if it has one
+    nk_tuning cached;
+    bool use_cached = false;
+    if (!large.empty() && tuning_cache_active()) {
+        int32_t gbig = large[0];
+        for (int32_t g : large)
+            if (vtx_off[g + 1] - vtx_off[g] > vtx_off[gbig + 1] - vtx_off[gbig]) gbig = g;
+        int64_t dmax = 0;
+        const int32_t nb = (int32_t)(vtx_off[gbig + 1] - vtx_off[gbig]);
+        if ((st = graph_max_degree(rowptr_cat + vtx_off[gbig] + gbig, nb, s, &dmax)) != NK_OK) return st;
+        use_cached = cached_tuning(nb, arc_off[gbig + 1] - arc_off[gbig], dmax, &cached);
+    }
+    TuningOverride cached_scope(use_cached ? &cached : nullptr);
     if (!large.empty()) {
         long long nsrc_large = 0;
         for (int32_t g : large) nsrc_large += vtx_off[g + 1] - vtx_off[g];

@@ -67,6 +67,28 @@ size_t pool_bytes_idle();   // idle pooled bytes on the current device
 nk_tuning tuning_get();
 void tuning_set(const nk_tuning &t);
 
+// While alive, tuning_get() on this thread returns *t (nothing changes when
+// t is NULL); scopes nest.
+class TuningOverride {
+public:
+    explicit TuningOverride(const nk_tuning *t);
+    ~TuningOverride();
+    TuningOverride(const TuningOverride &) = delete;
+    TuningOverride &operator=(const TuningOverride &) = delete;
+
+private:
+    const nk_tuning *prev_;
+};
+
+// Autotuner cache (nk_tune.hip): the tuning registered for graphs shaped
+// like (n, m, max degree), merged into the global tuning (flags and
+// scratch cap stay global); false when no cache is registered or it has no
+// entry for the shape.
+bool cached_tuning(int32_t n, int64_t m, int64_t max_deg, nk_tuning *out);
+bool tuning_cache_active();
+// Maximum degree of a CSR (one reduction kernel; synchronises s).
+nk_status graph_max_degree(const int32_t *rowptr, int32_t n, hipStream_t s, int64_t *out);
+
 // Per-thread statistics of the last call (nk_last_stats).
 // lds: 0 global bitmap, 1 bitmap in LDS, 2 whole graph in LDS
 void stats_record(const DevStatus &st, int grid, int block, int lds, float kernel_ms);

@@ -43,6 +43,8 @@ struct ServerGraph {
     uint32_t *iso = nullptr;
     int32_t vd = 0;              // vertex-diameter bound of the original graph
     size_t bytes = 0;
+    bool tuned = false;          // an autotuner cache entry matched the graph's shape
+    nk_tuning tuning = {};
 };
 
 struct Request {
@@ -156,6 +158,8 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
     if (launch_status_init(sl.dst, s) != hipSuccess) return bail(NK_E_HIP);
     const bool pair = rq->sources.empty();
     if (!pair) {
+        // source requests run under the graph's cached tuning, if any
+        TuningOverride tuned(g.tuned ? &g.tuning : nullptr);
         const long long k = (long long)rq->sources.size();
         int32_t *src_host_dev, *src_int;
         double *acc, *outd;
@@ -265,6 +269,7 @@ static void widen_grid(nk_server *sv, Request *rq, int busy) {
     if (div >= sv->n_share) return;
     const ServerGraph &g = *rq->g;
     const bool pair = rq->sources.empty();
+    TuningOverride tuned(g.tuned && !pair ? &g.tuning : nullptr);
     LaunchPlan pl;
     if (plan_launch(pair ? kModePair : kModeBC, g.n, std::max<long long>(rq->tasks, 1), -div, &pl) != NK_OK) {
         clear_error();
@@ -419,6 +424,12 @@ nk_status nk_server_add_graph(nk_server *sv, const int32_t *rowptr, const int32_
     int32_t info[8];
     if ((st = vd_bound_impl(rowptr, colidx, n, m, info, s)) != NK_OK) return cleanup(st);
     g.vd = info[4];
+    // the autotuner cache's tuning for this graph's shape, if one is registered
+    if (tuning_cache_active()) {
+        int64_t dmax = 0;
+        if ((st = graph_max_degree(g.rowptr, n, s, &dmax)) != NK_OK) return cleanup(st);
+        g.tuned = cached_tuning(n, m, dmax, &g.tuning);
+    }
     (void)hipStreamDestroy(s);
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->pool_bytes += g.bytes;
@@ -458,6 +469,7 @@ nk_status nk_server_submit(nk_server *sv, int32_t graph_id, const int32_t *sourc
     // once for this kernel (block size and occupancy depend on the graph),
     // so that n_slots requests together fill the GPU
     {
+        TuningOverride tuned(g.tuned && k > 0 ? &g.tuning : nullptr);
         LaunchPlan pl;
         const nk_status ps = plan_launch(k > 0 ? kModeBC : kModePair, g.n, std::max<long long>(tasks, 1),
                                          -sv->n_share, &pl);

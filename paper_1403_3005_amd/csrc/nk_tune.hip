@@ -1,12 +1,15 @@
-// Autotuner for the per-source Brandes kernel.
+// Autotuner for the source-set Brandes kernels.
 //
-// For a graph and a sample of its sources, times every candidate setting of
-// the workgroup size and the two direction thresholds (forward bottom-up
-// switch, backward push switch) with the source-set entry point, and keeps
-// the fastest.  Winners are stored per graph-shape bucket -- (floor log2 n,
+// For a graph and a sample of its sources, times with the source-set entry
+// point every setting of the workgroup size and the two direction
+// thresholds (forward bottom-up switch, backward push switch), then, from
+// the fastest of those, the resident workgroups per compute unit and the
+// sources per workgroup task (the multi-source kernel), and keeps the
+// fastest.  Winners are stored per graph-shape bucket -- (floor log2 n,
 // round log2 mean degree, round log2 of max degree / mean degree) -- in a
-// flat JSON object, so later runs on graphs of the same shape can reuse
-// them without timing.
+// flat JSON object.  Once a cache file is registered (nk_set_tuning_cache),
+// single-graph calls, batched plans and the server run every graph whose
+// bucket has an entry under that entry's tuning.
 #include <stdio.h>
 #include <string.h>
 
@@ -33,7 +36,10 @@ static std::string bucket_key(int32_t n, int64_t m, int64_t maxdeg) {
     return buf;
 }
 
-// The cache file is a flat JSON object: {"key": [block, bu_ratio, bw_ratio, ms], ...}.
+// The cache file is a flat JSON object:
+// {"key": [block, bu_ratio, bw_ratio, wg_per_cu, batch, ms], ...}; entries
+// of four values [block, bu_ratio, bw_ratio, ms] (older files) read as
+// wg_per_cu = 0, batch = 0.
 static std::map<std::string, std::vector<double>> read_cache(const char *path) {
     std::map<std::string, std::vector<double>> out;
     if (!path) return out;
@@ -64,7 +70,8 @@ static std::map<std::string, std::vector<double>> read_cache(const char *path) {
             vals.push_back(v);
             p = q;
         }
-        if (vals.size() == 4) out[key] = vals;
+        if (vals.size() == 4) vals = {vals[0], vals[1], vals[2], 0.0, 0.0, vals[3]};
+        if (vals.size() == 6) out[key] = vals;
         i = b + 1;
     }
     return out;
@@ -77,15 +84,18 @@ static bool write_cache(const char *path, const std::map<std::string, std::vecto
     fprintf(f, "{\n");
     size_t k = 0;
     for (const auto &kv : c) {
-        fprintf(f, "  \"%s\": [%d, %.6g, %.6g, %.6g]%s\n", kv.first.c_str(), (int)kv.second[0], kv.second[1],
-                kv.second[2], kv.second[3], ++k < c.size() ? "," : "");
+        fprintf(f, "  \"%s\": [%d, %.6g, %.6g, %d, %d, %.6g]%s\n", kv.first.c_str(), (int)kv.second[0],
+                kv.second[1], kv.second[2], (int)kv.second[3], (int)kv.second[4], kv.second[5],
+                ++k < c.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
     return rename(tmp.c_str(), path) == 0;
 }
 
-static nk_status max_degree(const int32_t *rowptr, int32_t n, hipStream_t s, int64_t *out) {
+nk_status graph_max_degree(const int32_t *rowptr, int32_t n, hipStream_t s, int64_t *out) {
+    *out = 0;
+    if (n <= 0) return NK_OK;
     Scratch scr;
     unsigned long long *key;
     nk_status st;
@@ -97,6 +107,39 @@ static nk_status max_degree(const int32_t *rowptr, int32_t n, hipStream_t s, int
     NK_HIP(hipStreamSynchronize(s));
     *out = (int64_t)(k >> 32);
     return NK_OK;
+}
+
+// The registered cache: its path and parsed entries (read once per
+// registration, refreshed when the autotuner writes to the same file).
+static std::string g_active_path;
+static std::map<std::string, std::vector<double>> g_active;
+// set while the autotuner times its candidates: they must run as given
+static thread_local bool t_trials = false;
+
+static void merge_entry(const std::vector<double> &e, nk_tuning *t) {
+    t->block = (int32_t)e[0];
+    t->bu_ratio = (float)e[1];
+    t->bw_ratio = (float)e[2];
+    t->wg_per_cu = (int32_t)e[3];
+    t->batch = (int32_t)e[4];
+}
+
+bool tuning_cache_active() {
+    if (t_trials) return false;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return !g_active_path.empty();
+}
+
+bool cached_tuning(int32_t n, int64_t m, int64_t max_deg, nk_tuning *out) {
+    if (t_trials) return false;
+    const nk_tuning base = tuning_get();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_active_path.empty()) return false;
+    auto it = g_active.find(bucket_key(n, m, max_deg));
+    if (it == g_active.end()) return false;
+    *out = base;
+    merge_entry(it->second, out);
+    return true;
 }
 
 }  // namespace nk
@@ -113,10 +156,24 @@ nk_status nk_tuning_lookup(const char *cache_path, int32_t n, int64_t m, int64_t
     auto it = c.find(bucket_key(n, m, max_deg));
     if (it == c.end()) return fail(NK_E_INVALID_ARG, "no cached tuning for this graph shape");
     nk_tuning t = tuning_get();
-    t.block = (int32_t)it->second[0];
-    t.bu_ratio = (float)it->second[1];
-    t.bw_ratio = (float)it->second[2];
+    merge_entry(it->second, &t);
     *out = t;
+    return NK_OK;
+}
+
+nk_status nk_set_tuning_cache(const char *cache_path) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!cache_path || !cache_path[0]) {
+        g_active_path.clear();
+        g_active.clear();
+        return NK_OK;
+    }
+    FILE *f = fopen(cache_path, "r");
+    if (!f) return fail(NK_E_INVALID_ARG, "cannot read %s", cache_path);
+    fclose(f);
+    g_active_path = cache_path;
+    g_active = read_cache(cache_path);
     return NK_OK;
 }
 
@@ -128,46 +185,66 @@ nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, i
     if (n == 0 || k <= 0 || !sources || !best) return fail(NK_E_INVALID_ARG, "need n > 0, k > 0, sources, best");
     hipStream_t s = (hipStream_t)stream;
     int64_t dmax = 0;
-    if ((st = max_degree(rowptr, n, s, &dmax)) != NK_OK) return st;
+    if ((st = graph_max_degree(rowptr, n, s, &dmax)) != NK_OK) return st;
     double *bc = nullptr;
     NK_HIP(hipMalloc((void **)&bc, sizeof(double) * (size_t)n));
     const nk_tuning saved = tuning_get();
-    const int blocks[] = {256, 512, 1024};
-    const float bus[] = {0.0f, 2.0f, 8.0f, 16.0f, 64.0f};
-    const float bws[] = {0.0f, 0.1f, 0.25f, 1.0f};
     nk_tuning win = saved;
     double best_ms = 1e300;
     nk_status result = NK_OK;
-    for (int b : blocks) {
-        for (float bu : bus) {
+    struct TrialScope {
+        TrialScope() { t_trials = true; }
+        ~TrialScope() { t_trials = false; }
+    } trials;
+    // times one setting: an untimed run (allocation, caches), then the timed one
+    auto trial = [&](const nk_tuning &t) -> bool {
+        tuning_set(t);
+        st = nk_bc_sources(rowptr, colidx, n, m, sources, k, 1.0, bc, stream);
+        if (st != NK_OK) {
+            result = st;
+            return false;
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        st = nk_bc_sources(rowptr, colidx, n, m, sources, k, 1.0, bc, stream);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (st != NK_OK) {
+            result = st;
+            return false;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            win = t;
+        }
+        return true;
+    };
+    // stage 1: block size x the two direction thresholds, one source per task
+    const int blocks[] = {256, 512, 1024};
+    const float bus[] = {0.0f, 2.0f, 8.0f, 16.0f, 64.0f};
+    const float bws[] = {0.0f, 0.1f, 0.25f, 1.0f};
+    for (int b : blocks)
+        for (float bu : bus)
             for (float bw : bws) {
                 nk_tuning t = saved;
                 t.block = b;
                 t.bu_ratio = bu;
                 t.bw_ratio = bw;
-                tuning_set(t);
-                // one untimed run (allocation, caches), then the timed one
-                st = nk_bc_sources(rowptr, colidx, n, m, sources, k, 1.0, bc, stream);
-                if (st != NK_OK) {
-                    result = st;
-                    break;
-                }
-                const auto t0 = std::chrono::steady_clock::now();
-                st = nk_bc_sources(rowptr, colidx, n, m, sources, k, 1.0, bc, stream);
-                const double ms =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                if (st != NK_OK) {
-                    result = st;
-                    break;
-                }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    win = t;
-                }
+                t.wg_per_cu = 0;
+                t.batch = 1;
+                if (result == NK_OK) trial(t);
             }
-            if (result != NK_OK) break;
+    // stage 2: from the stage-1 winner, one resident workgroup per compute
+    // unit, then the multi-source kernel with 4, 8 and 16 sources per task
+    if (result == NK_OK) {
+        const nk_tuning base = win;
+        nk_tuning t = base;
+        t.wg_per_cu = 1;
+        trial(t);
+        for (int b : {4, 8, 16}) {
+            t = base;
+            t.batch = b;
+            t.block = 1024;
+            if (result == NK_OK) trial(t);
         }
-        if (result != NK_OK) break;
     }
     tuning_set(saved);
     (void)hipFree(bc);
@@ -176,8 +253,10 @@ nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, i
     if (cache_path) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto c = read_cache(cache_path);
-        c[bucket_key(n, m, dmax)] = {(double)win.block, (double)win.bu_ratio, (double)win.bw_ratio, best_ms};
+        c[bucket_key(n, m, dmax)] = {(double)win.block, (double)win.bu_ratio, (double)win.bw_ratio,
+                                     (double)win.wg_per_cu, (double)win.batch, best_ms};
         if (!write_cache(cache_path, c)) return fail(NK_E_INVALID_ARG, "cannot write %s", cache_path);
+        if (g_active_path == cache_path) g_active = c;
     }
     clear_error();
     return NK_OK;

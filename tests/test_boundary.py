@@ -93,3 +93,24 @@ def test_tuning_cache_lookup(tmp_path):
     assert t["block"] == 256 and t["bu_ratio"] == 2.0 and t["bw_ratio"] == 0.0
     with pytest.raises(nk.NkError):
         nk.nk_tuning_lookup(str(path), 100, 300, 10)
+
+
+def test_tuning_cache_formats_and_registration(tmp_path):
+    """Cache entries of six values and of the older four read back (host
+    only); registering a missing file is refused, None unregisters."""
+    import json
+
+    import paper_1403_3005_amd as nk
+    path = tmp_path / "c.json"
+    # n = 1000 (floor log2 = 9), m = 8000 (mean 8: log2 3), max degree 64 (ratio 8: log2 3)
+    path.write_text(json.dumps({"n9_d3_s3": [256, 2, 0.25, 1, 8, 1.5], "n10_d3_s3": [512, 8, 0.1, 3.5]}))
+    t = nk.nk_tuning_lookup(str(path), 1000, 8000, 64)
+    assert (t["block"], t["bu_ratio"], t["bw_ratio"], t["wg_per_cu"], t["batch"]) == (256, 2.0, 0.25, 1, 8)
+    t = nk.nk_tuning_lookup(str(path), 1500, 12000, 64)
+    assert (t["block"], t["bu_ratio"], t["wg_per_cu"], t["batch"]) == (512, 8.0, 0, 0)
+    with pytest.raises(nk.NkError):
+        nk.nk_tuning_lookup(str(path), 100000, 800000, 64)
+    with pytest.raises(nk.NkError):
+        nk.nk_set_tuning_cache(str(tmp_path / "missing.json"))
+    nk.nk_set_tuning_cache(str(path))
+    nk.nk_set_tuning_cache(None)

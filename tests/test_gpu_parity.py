@@ -508,3 +508,64 @@ def test_autotune_picks_a_valid_tuning(tmp_path):
     nk.nk_set_tuning(**best)
     got = nk.nk_bc_sources(rp, ci, src, 1.0).cpu().numpy()
     assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src.cpu().numpy()), "tuned")
+
+
+def _retune_cache(path, **fields):
+    """Rewrites every entry of an autotuner cache with the given fields."""
+    order = ["block", "bu_ratio", "bw_ratio", "wg_per_cu", "batch"]
+    with open(path) as f:
+        c = json.load(f)
+    for k, v in c.items():
+        for name, val in fields.items():
+            v[order.index(name)] = val
+    with open(path, "w") as f:
+        json.dump(c, f)
+
+
+def test_cached_tuning_applies_without_set_tuning(tmp_path):
+    """A registered cache entry is picked up by nk_bc_sources, the batched
+    plan and the server for graphs of its shape (no nk_set_tuning), results
+    match the oracle; graphs of other shapes, and all graphs once the cache
+    is unregistered, run under the global tuning."""
+    g = gg.barabasi_albert(20000, 4, 123)
+    rp, ci = upload(g)
+    src = gg.sample_sources(g.n, 96, 124)
+    cache = str(tmp_path / "tune.json")
+    nk.nk_autotune(rp, ci, ivec(src[:32]), cache)
+    # a distinctive entry: 256-thread workgroups, the multi-source kernel with 8 sources per task
+    _retune_cache(cache, block=256, batch=8, bu_ratio=0.0)
+    nk.nk_set_tuning(flags=4)
+    try:
+        nk.nk_set_tuning_cache(cache)
+        got = nk.nk_bc_sources(rp, ci, ivec(src), 2.0).cpu().numpy()
+        st = nk.nk_last_stats()
+        assert st["block"] == 256 and st["sources_per_task"] == 8 and st["bitmap_lds"] == 4 and st["levels_bu"] == 0
+        assert_scores_close(got, oracle.bc_sources(g.rowptr, g.colidx, src, 2.0, nthreads=8), "cached tuning")
+        # another shape: the global tuning
+        other = gg.erdos_renyi(3000, 6000, 125)
+        orp, oci = upload(other)
+        nk.nk_bc_sources(orp, oci, ivec([1, 2, 3]), 1.0)
+        assert nk.nk_last_stats()["sources_per_task"] == 1
+        # the batched plan: its large graph has the cached shape
+        vtx = np.array([0, other.n, other.n + g.n], dtype=np.int64)
+        arc = np.array([0, other.m, other.m + g.m], dtype=np.int64)
+        brp = torch.from_numpy(np.concatenate([other.rowptr, g.rowptr]).astype(np.int32)).cuda()
+        bci = torch.from_numpy(np.concatenate([other.colidx, g.colidx]).astype(np.int32)).cuda()
+        with nk.NkBatchPlan(vtx, arc, brp, bci) as plan:
+            out = plan.run().cpu().numpy()
+            st = nk.nk_last_stats()
+            assert st["sources_per_task"] == 8 and st["block"] == 256
+        assert_scores_close(out[other.n:], oracle.bc_exact(g.rowptr, g.colidx, nthreads=16), "batched, cached")
+        assert_scores_close(out[:other.n], oracle.bc_exact(other.rowptr, other.colidx), "batched, other")
+        # the server: a graph added while the cache is registered
+        with nk.NkServer(16 << 30, slots=2) as sv:
+            gid = sv.add_graph(rp, ci)
+            t = sv.submit(gid, sources=src)
+            scores, _ = sv.wait(t)
+        assert_scores_close(scores, oracle.bc_sources(g.rowptr, g.colidx, src, g.n / len(src), nthreads=8), "server")
+        nk.nk_set_tuning_cache(None)
+        nk.nk_bc_sources(rp, ci, ivec(src), 2.0)
+        assert nk.nk_last_stats()["sources_per_task"] == 1
+    finally:
+        nk.nk_set_tuning_cache(None)
+        nk.nk_set_tuning()
