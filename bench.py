@@ -308,10 +308,11 @@ def batched_record(args) -> dict:
            "kernel_ms": round(kern_s * 1e3, 1), "kernels": PLACEMENT.get(st["bitmap_lds"], st["bitmap_lds"]),
            "block": st["block"], "workgroups": st["workgroups"], "sources_per_task": st["sources_per_task"],
            "roofline": roofline(alg_bytes(st), kern_s, "k_brandes_lds + k_brandes (batched, whole run)")}
-    big = max(graphs, key=lambda g: g.n)
-    grp, gci = torch.from_numpy(big.rowptr).to(dev), torch.from_numpy(big.colidx).to(dev)
-    rec["per_source_kernel"] = per_source_kernel(big, list(range(0, big.n, big.n // 16))[:16], grp, gci,
-                                                 f"largest graph of the batch (n = {big.n})")
+    if not args.no_per_source:
+        big = max(graphs, key=lambda g: g.n)
+        grp, gci = torch.from_numpy(big.rowptr).to(dev), torch.from_numpy(big.colidx).to(dev)
+        rec["per_source_kernel"] = per_source_kernel(big, list(range(0, big.n, big.n // 16))[:16], grp, gci,
+                                                     f"largest graph of the batch (n = {big.n})")
     if not args.no_cpu_baseline:
         threads = cpu_threads()
         small = sorted(graphs, key=lambda g: g.n)[:16]
@@ -438,6 +439,8 @@ def other_workload(args) -> dict:
         src = np.arange(4096, dtype=np.int32)
         rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
         bc = torch.empty(g.n, dtype=torch.float64, device=dev)
+        if args.batch:
+            nk.nk_set_tuning(batch=args.batch)
         sec = _timed(lambda: nk.nk_bc_sources(rp, ci, sv, g.n / 4096, bc=bc), args.steps, args.warmup)
         st = nk.nk_last_stats()
         alg = 68 * st["reached"] + 16 * st["arcs_reached"] + 24 * st["dag_arcs"]
@@ -446,7 +449,9 @@ def other_workload(args) -> dict:
                    value=round(4096 * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
                    config={"workload": "er200k_sources4096", "graph": "Erdos-Renyi G(2e5, 8e5), seed 7",
                            "n": g.n, "arcs": g.m, "sources": 4096, "kernel_ms": kern_s * 1e3,
-                           "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"]},
+                           "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"],
+                           "sources_per_task": st["sources_per_task"], "reached": st["reached"],
+                           "arcs_reached": st["arcs_reached"], "dag_arcs": st["dag_arcs"]},
                    roofline={"bound": "hbm", "achieved": round(alg / kern_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / PEAK_HBM_GBS, 4),
                              "traffic": counter_traffic("er200k_sources4096"), "kernel": KERNEL,
@@ -572,8 +577,9 @@ def serving_sweep(warm: int, measured: int) -> dict:
         lat = latency_summary(res)
         out["saturation_rps"] = round(sat, 2)
         out["saturation_gteps"] = round(server.stats()["gteps"], 3)
-        out["points"].append({"fraction": "all at once", "qps": None, "p50_ms": round(lat["p50_ms"], 2),
-                              "p99_ms": round(lat["p99_ms"], 2), "achieved_rps": round(sat, 2)})
+        out["points"].append({"fraction": "all at once", "qps": None, "requests": measured,
+                              "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),
+                              "achieved_rps": round(sat, 2)})
         for i, f in enumerate((0.25, 0.5, 0.75, 0.9)):
             qps = f * sat
             reqs = gg.request_stream(warm + measured, qps, sizes, seed=57 + i)
@@ -581,9 +587,15 @@ def serving_sweep(warm: int, measured: int) -> dict:
                   flush=True)
             res, wall = replay(server, ids, reqs)
             lat = latency_summary(res[warm:])
-            out["points"].append({"fraction": f, "qps": round(qps, 2), "p50_ms": round(lat["p50_ms"], 2),
-                                  "p99_ms": round(lat["p99_ms"], 2), "mean_ms": round(lat["mean_ms"], 2),
-                                  "achieved_rps": round(len(reqs) / wall, 2)})
+            out["points"].append({"fraction": f, "qps": round(qps, 2), "requests": measured, "warmup": warm,
+                                  "p50_ms": round(lat["p50_ms"], 2), "p99_ms": round(lat["p99_ms"], 2),
+                                  "mean_ms": round(lat["mean_ms"], 2), "achieved_rps": round(len(reqs) / wall, 2)})
+    # the plain per-source kernel on the pool's largest graph, for comparison
+    big = max(pool, key=lambda g: g.m)
+    brp, bci = torch.from_numpy(big.rowptr).to(dev), torch.from_numpy(big.colidx).to(dev)
+    nz = [v for v in range(big.n) if big.rowptr[v + 1] > big.rowptr[v]]
+    out["per_source_kernel"] = per_source_kernel(big, nz[::max(1, len(nz) // 16)][:16], brp, bci,
+                                                 f"the pool's largest graph (n = {big.n}, {big.m} arcs)")
     return out
 
 
@@ -599,6 +611,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-graph batch (about 5 minutes)")
     ap.add_argument("--no-pairs", action="store_true", help="skip the pair-sampling record")
+    ap.add_argument("--no-per-source", action="store_true", help="skip the per-source kernel baseline")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="sources per workgroup task for the er200k workload (tuning field batch; 0 = automatic)")
     ap.add_argument("--serving-qps", type=float, default=8.0)
     ap.add_argument("--serving-requests", type=int, default=96,
                     help="requests of the default serving line; measured requests per point of --workload serving")
@@ -738,9 +753,10 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
-    print("bench: per-source kernel baseline", file=sys.stderr, flush=True)
-    out["per_source_kernel"] = per_source_kernel(g, [int(x) for x in src[:32]], rp, ci,
-                                                 "the headline graph, its first 32 sources")
+    if not args.no_per_source:
+        print("bench: per-source kernel baseline", file=sys.stderr, flush=True)
+        out["per_source_kernel"] = per_source_kernel(g, [int(x) for x in src[:32]], rp, ci,
+                                                     "the headline graph, its first 32 sources")
     if not args.no_pairs:
         out["pair_sampling"] = pair_record(args)
     if not args.no_batched:
