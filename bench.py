@@ -47,7 +47,8 @@ KERNEL = "k_brandes"
 # nk_last_stats "bitmap_lds" -> which kernel ran
 PLACEMENT = {0: "k_brandes (global bitmap)", 1: "k_brandes (LDS bitmap)", 2: "k_brandes_lds (all in LDS)",
              3: "k_brandes_lds + k_brandes (LDS bitmap)", 4: "k_brandes_ms (multi-source)",
-             5: "k_brandes_lds + k_brandes_ms (multi-source)"}
+             5: "k_brandes_lds + k_brandes_ms (multi-source)", 6: "k_brandes_group (XCD groups)",
+             7: "k_brandes_lds + k_brandes + k_brandes_group"}
 
 
 def kernel_source_hash() -> str:

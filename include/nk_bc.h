@@ -404,9 +404,15 @@ nk_status nk_batch_plan_finish(nk_batch_plan *plan, void *stream);
  *   out[9] threads per workgroup
  *   out[10] kernel placement: 0 visited bitmap in global memory, 1 bitmap in
  *           LDS, 2 whole graph in LDS (all-in-LDS kernel), 3 a batch split
- *           between the all-in-LDS kernel and the LDS-bitmap kernel
+ *           between the all-in-LDS kernel and the LDS-bitmap kernel, 4 the
+ *           multi-source kernel, 5 a batch split between the all-in-LDS and
+ *           multi-source kernels, 6 the group kernel (the workgroups of one
+ *           XCD share a source), 7 a batch split between the all-in-LDS and
+ *           group kernels
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
- *   out[12] dependency-sweep levels run by push   out[13..15] reserved
+ *   out[12] dependency-sweep levels run by push
+ *   out[13] sources per workgroup task (multi-source kernel; else 1)
+ *   out[14..15] reserved
  *   (nk_bc_weighted: out[2] arcs relaxed in the distance rounds, out[5]
  *   distance rounds, out[6] shortest-path DAG layers, out[4] DAG arcs)
  *   out[16..23] shader-clock cycles per phase, summed over workgroups:
@@ -434,6 +440,12 @@ nk_status nk_last_stats(int64_t *out);
  *              bit 2: never use the all-in-LDS kernel (which otherwise runs
  *              betweenness on every graph whose CSR plus one source's state,
  *              about 16 n + 4 m bytes, fits one workgroup's LDS);
+ *              bit 3: run exact and source-set betweenness (plain and linear
+ *              scaling) of undirected graphs that the all-in-LDS kernel does
+ *              not take on the group kernel, where the workgroups of one XCD
+ *              run one source together with its path counts in that XCD's
+ *              L2 (graphs whose visited bitmap fits LDS: up to about 1.1
+ *              million vertices); block 512 makes two groups per XCD;
  *   bw_ratio   in the dependency sweep, handle level l by pushing from level
  *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
  *              of level l (0 = always pull; default 0.1);
@@ -451,6 +463,12 @@ nk_status nk_last_stats(int64_t *out);
  *              reading each adjacency row once per union level and keeping
  *              the sources' path counts of a vertex side by side; 0 =
  *              chosen by graph size.
+ *   group      workgroups per group in the group kernel (flags bit 3): 1,
+ *              2, 4, 8, 16, 32 or 64, capped at the workgroups of one XCD
+ *              (0 = chosen by graph size).  Each group runs one source at a
+ *              time; fewer workgroups per group means more sources in
+ *              flight, more workgroups per group keeps fewer sources'
+ *              path counts in the caches.
  * nk_set_tuning applies to later calls from every thread.
  */
 typedef struct {
@@ -461,7 +479,7 @@ typedef struct {
     float bw_ratio;
     int32_t scratch_mib;
     int32_t batch;
-    int32_t reserved;
+    int32_t group;
 } nk_tuning;
 
 nk_status nk_set_tuning(const nk_tuning *t);

@@ -53,7 +53,7 @@ class NkError(RuntimeError):
 class NkTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("bu_ratio", ctypes.c_float), ("wg_per_cu", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("bw_ratio", ctypes.c_float), ("scratch_mib", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("group", ctypes.c_int32)]
 
 
 def load():
@@ -453,8 +453,8 @@ def nk_last_stats() -> dict:
 
 
 def nk_set_tuning(block: int = 0, bu_ratio: float = 16.0, wg_per_cu: int = 0, flags: int = 0, bw_ratio: float = 0.1,
-                  scratch_mib: int = 0, batch: int = 0):
-    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio, scratch_mib, batch)
+                  scratch_mib: int = 0, batch: int = 0, group: int = 0):
+    t = NkTuning(block, bu_ratio, wg_per_cu, flags, bw_ratio, scratch_mib, batch, group)
     _check(load().nk_set_tuning(ctypes.byref(t)))
 
 
@@ -466,7 +466,7 @@ def nk_get_tuning() -> dict:
 
 def _tuning_dict(t) -> dict:
     return {"block": t.block, "bu_ratio": t.bu_ratio, "wg_per_cu": t.wg_per_cu, "flags": t.flags,
-            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib, "batch": t.batch}
+            "bw_ratio": t.bw_ratio, "scratch_mib": t.scratch_mib, "batch": t.batch, "group": t.group}
 
 
 def nk_set_tuning_cache(cache_path: str | None) -> None:

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnkbc.so")
 SOURCES = ["nk_kernels.hip", "nk_lds.hip", "nk_bfs.hip", "nk_relabel.hip", "nk_directed.hip", "nk_api.hip",
-           "nk_server.hip", "nk_tune.hip", "nk_multi.hip", "nk_noalloc.hip"]
+           "nk_server.hip", "nk_tune.hip", "nk_multi.hip", "nk_group.hip", "nk_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -553,6 +553,126 @@ nk_status ms_enqueue(const MsPlan &mp, const Params &p, hipStream_t s, hipEvent_
     return NK_OK;
 }
 
+// ------------------------------------------------------------- group plan --
+
+bool group_wanted(int32_t n_max, int64_t m_arcs) {
+    const nk_tuning t = tuning_get();
+    if ((t.flags & 16) || n_max < 1 || t.batch > 1) return false;
+    // automatic: sparse graphs of 10^5 to 3 * 10^5 vertices, where sharing
+    // a source between a few workgroups measured faster than one source per
+    // workgroup (mean-degree-8 random and preferential-attachment graphs);
+    // flag bit 3 asks for the group kernel on every graph it can take
+    const bool autosel = n_max >= 100000 && n_max <= 300000 && m_arcs <= 12LL * n_max;
+    if (!(t.flags & 8) && !autosel) return false;
+    DevInfo di;
+    if (dev_info(&di) != NK_OK) return false;
+    const int block = t.block == 512 ? 512 : 1024;
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, brandes_group_kernel(block).fn) != hipSuccess) return false;
+    const size_t bm = (size_t)(((long long)n_max + 31) / 32) * 4;
+    return attr.sharedSizeBytes + bm <= di.lds_per_block;
+}
+
+nk_status plan_group(int32_t n_max, GroupPlan *gp) {
+    DevInfo di;
+    nk_status st = dev_info(&di);
+    if (st != NK_OK) return st;
+    const nk_tuning t = tuning_get();
+    const int block = t.block == 512 ? 512 : 1024;
+    KernelRef kr = brandes_group_kernel(block);
+    hipFuncAttributes attr;
+    NK_HIP(hipFuncGetAttributes(&attr, kr.fn));
+    const size_t dyn = (size_t)(((long long)n_max + 31) / 32) * 4;
+    if (attr.sharedSizeBytes + dyn > di.lds_per_block)
+        return fail(NK_E_INTERNAL, "group kernel: a bitmap of %d vertices does not fit LDS", n_max);
+    NK_HIP(hipFuncSetAttribute(kr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    int occ = 0;
+    NK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kr.fn, block, dyn));
+    if (occ < 1) return fail(NK_E_INTERNAL, "group kernel does not fit a compute unit (block %d)", block);
+    // one 1024-thread workgroup per compute unit, or two of 512 (one per
+    // group of each XCD's two groups)
+    const int per_cu = block == 512 ? std::min(occ, 2) : 1;
+    int nxcc = 0;
+    if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, di.device) != hipSuccess || nxcc < 1) nxcc = 1;
+    (void)hipGetLastError();
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, di.device) != hipSuccess || rate_khz < 1)
+        rate_khz = 100000;
+    (void)hipGetLastError();
+    // workgroups per group: the tuning's, else 4 (measured fastest on the
+    // mid-size graphs; whole-XCD groups leave each workgroup too few tiles
+    // per level)
+    const int per_xcd = std::max(1, di.cus * per_cu / nxcc);
+    int gsz = t.group > 0 ? t.group : 4;
+    if (gsz > per_xcd) gsz = per_xcd;
+    gp->gpx = std::max(1, per_xcd / gsz);
+    gp->groups = nxcc * gp->gpx;
+    gp->stride = (((long long)n_max + 2) + 63) / 64 * 64;
+    gp->timeout = (long long)rate_khz * 1000LL * 20LL;   // 20 s
+    gp->lp.mode = kModeBC;
+    gp->lp.block = block;
+    gp->lp.lds = true;
+    gp->lp.grid = di.cus * per_cu;
+    gp->lp.dyn_lds = dyn;
+    gp->lp.stride = gp->stride;
+    gp->lp.bm_words = 0;
+    gp->lp.kernel = kr;
+    gp->lp.pair_rec = nullptr;
+    gp->lp.dag_words = 0;
+    return NK_OK;
+}
+
+nk_status group_alloc(const GroupPlan &gp, Params &p, Scratch &scr) {
+    const long long cells = (long long)gp.groups * gp.stride;
+    nk_status st;
+    if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.lv)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.la)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.ld)) != NK_OK) return st;
+    if ((st = scr.get(cells, &p.lvl)) != NK_OK) return st;
+    // bottom-up candidates: each member's segment holds the vertices of
+    // every G-th bitmap word (G <= 64 members)
+    const long long cstride = gp.stride + 64 * 32 + 64;
+    if ((st = scr.get((long long)gp.groups * cstride, &p.cand)) != NK_OK) return st;
+    p.xg_cand_stride = cstride;
+    unsigned long long *ctl;
+    if ((st = scr.get((long long)(gp.groups * group_ctl_bytes() / 8), &ctl)) != NK_OK) return st;
+    if ((st = scr.get(32, &p.xg_reg)) != NK_OK) return st;
+    p.xg_ctl = ctl;
+    p.stride = gp.stride;
+    p.xg_gpx = gp.gpx;
+    p.xg_groups = gp.groups;
+    p.xg_timeout = gp.timeout;
+    p.bu_ratio = tuning_get().bu_ratio;
+    p.bw_ratio = tuning_get().bw_ratio;
+    return NK_OK;
+}
+
+nk_status group_enqueue(const GroupPlan &gp, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    NK_HIP(launch_fill_u64(p.sigma, 0ULL, (long long)gp.groups * gp.stride, s));
+    NK_HIP(launch_fill_u64(static_cast<unsigned long long *>(p.xg_ctl), 0ULL,
+                           (long long)(gp.groups * group_ctl_bytes() / 8), s));
+    NK_HIP(launch_fill_u32(p.xg_reg, 0u, 32, s));
+    if (ev0) NK_HIP(hipEventRecord(ev0, s));
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    NK_HIP(hipStreamIsCapturing(s, &cap));
+    if (cap == hipStreamCaptureStatusNone) {
+        // the runtime checks that the whole grid can be resident at once
+        Params arg = p;
+        void *args[] = {&arg};
+        NK_HIP(hipLaunchCooperativeKernel(gp.lp.kernel.fn, dim3(gp.lp.grid), dim3(gp.lp.block), args,
+                                          (unsigned int)gp.lp.dyn_lds, s));
+    } else {
+        // a captured plan runs alone on its stream, after the launches
+        // before it, with the device otherwise idle; the registration
+        // count inside the kernel still checks residency
+        gp.lp.kernel.launch(dim3(gp.lp.grid), dim3(gp.lp.block), gp.lp.dyn_lds, s, p);
+        NK_HIP(hipGetLastError());
+    }
+    if (ev1) NK_HIP(hipEventRecord(ev1, s));
+    return NK_OK;
+}
+
 nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipStream_t s) {
     const long long slots = plan.grid;
     const long long cells = slots * plan.stride;
@@ -727,6 +847,8 @@ nk_status nk_set_tuning(const nk_tuning *t) {
         return fail(NK_E_INVALID_ARG, "bad tuning values");
     if (t->batch != 0 && t->batch != 1 && t->batch != 4 && t->batch != 8 && t->batch != 16)
         return fail(NK_E_INVALID_ARG, "batch must be 0, 1, 4, 8 or 16");
+    if (t->group < 0 || t->group > 64 || (t->group & (t->group - 1)) != 0)
+        return fail(NK_E_INVALID_ARG, "group must be 0 or a power of two up to 64");
     tuning_set(*t);
     return NK_OK;
 }
@@ -884,7 +1006,36 @@ static nk_status bc_sources_impl(const int32_t *rowptr, const int32_t *colidx, i
             NK_HIP(launch_fill_f64(acc, 0.0, n, s));
         }
         // plain and linear-scaling sweeps of undirected graphs without edge
-        // scores may run several sources per task
+        // scores may run one source per XCD group of workgroups
+        if (!ebc && !dir && est != kEstBisect && group_wanted(n, m)) {
+            GroupPlan gp;
+            if ((st = plan_group(n, &gp)) != NK_OK) return st;
+            Params p;
+            memset(&p, 0, sizeof(p));
+            p.rowptr = g.rowptr;
+            p.colidx = g.colidx;
+            p.n = n;
+            p.m = (int32_t)m;
+            p.sources = src;
+            p.ntasks = k;
+            p.bc = acc;
+            p.iso = iso;
+            p.st = dst;
+            p.linear = est == kEstLinear;
+            if ((st = group_alloc(gp, p, scr)) != NK_OK) return st;
+            hipEvent_t ev0, ev1;
+            if ((st = thread_events(&ev0, &ev1)) != NK_OK) return st;
+            if ((st = group_enqueue(gp, p, s, ev0, ev1)) != NK_OK) return st;
+            if (g.perm)
+                NK_HIP(launch_gather_scale(acc, g.perm, n, scale, bc, s));
+            else if (scale != 1.0)
+                NK_HIP(launch_scale_f64(bc, scale, n, s));
+            st = finish(dst, h, s);
+            NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            stats_record(*h, gp.lp.grid, gp.lp.block, 6, ms);
+            return st;
+        }
+        // or several sources per task
         const int msb = (!ebc && !dir && est != kEstBisect) ? ms_batch_for(n, k) : 1;
         if (msb > 1) {
             MsPlan mp;
@@ -1463,10 +1614,12 @@ struct BatchSetup {
     LaunchPlan plan_s = {}, plan_l = {};
     int ms_b = 1;              // sources per task of the large graphs' launch
     MsPlan mplan = {};
-    long long *t_small = nullptr, *t_large = nullptr;
-    int32_t *o_small = nullptr, *o_large = nullptr;
-    long long k_small = 0, k_large = 0;
-    int32_t g_small = 0, g_large = 0, n_large = 0;
+    GroupPlan gplan = {};      // the group kernel's launch
+    Params pg;                 // its parameters (own scratch)
+    long long *t_small = nullptr, *t_large = nullptr, *t_group = nullptr;
+    int32_t *o_small = nullptr, *o_large = nullptr, *o_group = nullptr;
+    long long k_small = 0, k_large = 0, k_group = 0;
+    int32_t g_small = 0, g_large = 0, n_large = 0, g_group = 0, n_group = 0;
     long long *d_vtx = nullptr, *d_arc = nullptr;
     int32_t G = 0;
     long long nv = 0;
@@ -1517,7 +1670,9 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
         if ((st = dev_info(&di)) != NK_OK) return st;
         budget = di.lds_per_block > attr.sharedSizeBytes ? di.lds_per_block - attr.sharedSizeBytes : 0;
     }
-    std::vector<int32_t> small, large;
+    // Graphs the group kernel takes (by size, or all large ones under flag
+    // bit 3) form a third part with a launch of its own.
+    std::vector<int32_t> small, large, grp;
     int32_t n_small = 0;
     for (int32_t g = 0; g < G; ++g) {
         const long long ng = vtx_off[g + 1] - vtx_off[g], mg = arc_off[g + 1] - arc_off[g];
@@ -1527,6 +1682,9 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
             small.push_back(g);
             dyn_max = std::max(dyn_max, by);
             n_small = std::max<int32_t>(n_small, (int32_t)ng);
+        } else if (group_wanted((int32_t)ng, mg)) {
+            grp.push_back(g);
+            b->n_group = std::max<int32_t>(b->n_group, (int32_t)ng);
         } else {
             large.push_back(g);
             b->n_large = std::max<int32_t>(b->n_large, (int32_t)ng);
@@ -1535,6 +1693,7 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
     auto by_work = [&](int32_t x, int32_t y) { return work[x] > work[y]; };
     std::stable_sort(small.begin(), small.end(), by_work);
     std::stable_sort(large.begin(), large.end(), by_work);
+    std::stable_sort(grp.begin(), grp.end(), by_work);
     // task prefix over the graphs in processing order: one task per source,
     // or per group of `per` sources
     auto tables = [&](const std::vector<int32_t> &ids, long long **d_task, int32_t **d_order, long long *ntasks,
@@ -1561,6 +1720,7 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
     b->p.st = b->dst;
     b->g_small = (int32_t)small.size();
     b->g_large = (int32_t)large.size();
+    b->g_group = (int32_t)grp.size();
     if (!small.empty()) {
         if ((st = tables(small, &b->t_small, &b->o_small, &b->k_small, 1)) != NK_OK) return st;
         if (!plan_lds(dyn_max, n_small, b->k_small, &b->plan_s)) return fail(NK_E_INTERNAL, "all-in-LDS plan failed");
@@ -1593,6 +1753,15 @@ static nk_status batch_prepare(int32_t G, const int64_t *vtx_off, const int64_t 
             if ((st = plan_launch(kModeBC, b->n_large, b->k_large, 0, &b->plan_l)) != NK_OK) return st;
             if ((st = persistent_alloc(b->plan_l, b->p, scr, s)) != NK_OK) return st;
         }
+    }
+    if (!grp.empty()) {
+        if ((st = tables(grp, &b->t_group, &b->o_group, &b->k_group, 1)) != NK_OK) return st;
+        if ((st = plan_group(b->n_group, &b->gplan)) != NK_OK) return st;
+        // the group launch has its own scratch; the one-source launch's
+        // pointers in b->p stay as they are
+        Params gp_params = b->p;
+        if ((st = group_alloc(b->gplan, gp_params, scr)) != NK_OK) return st;
+        b->pg = gp_params;
     }
     b->nv = nv;
     b->rowptr = rowptr_cat;
@@ -1630,6 +1799,17 @@ static nk_status batch_enqueue(const BatchSetup &b, hipStream_t s, hipEvent_t ev
                                   : persistent_enqueue(b.plan_l, p, s, nullptr, nullptr);
         if (st != NK_OK) return st;
     }
+    if (b.g_group > 0) {
+        if (b.g_small > 0 || b.g_large > 0) NK_HIP(launch_reset_head(b.dst, s));
+        Params q = b.pg;
+        q.n = b.n_group;
+        q.G = b.g_group;
+        q.g_task = b.t_group;
+        q.g_order = b.o_group;
+        q.ntasks = b.k_group;
+        nk_status st = group_enqueue(b.gplan, q, s, nullptr, nullptr);
+        if (st != NK_OK) return st;
+    }
     if (ev1) NK_HIP(hipEventRecord(ev1, s));
     return NK_OK;
 }
@@ -1637,7 +1817,8 @@ static nk_status batch_enqueue(const BatchSetup &b, hipStream_t s, hipEvent_t ev
 static void batch_stats(const BatchSetup &b, const DevStatus &h, float ms) {
     int where = b.g_large == 0 ? 2 : (b.g_small == 0 ? (b.plan_l.lds ? 1 : 0) : 3);
     if (b.g_large > 0 && b.ms_b > 1) where = b.g_small == 0 ? 4 : 5;
-    const LaunchPlan &shown = b.g_large == 0 ? b.plan_s : b.plan_l;
+    if (b.g_group > 0) where = (b.g_small == 0 && b.g_large == 0) ? 6 : 7;
+    const LaunchPlan &shown = b.g_large > 0 ? b.plan_l : (b.g_group > 0 ? b.gplan.lp : b.plan_s);
     stats_record(h, shown.grid, shown.block, where, ms);
     if (b.g_large > 0) stats_set_batch(b.ms_b);
 }

@@ -125,6 +125,18 @@ struct Params {
     uint32_t *lm;
     uint32_t *visg;
     long long visg_words;      // per-slot words of visg
+    // group mode (nk_group.hip): the workgroups of one XCD share a source;
+    // per group (not per slot) `stride` elements of sigma, lv, la, ld, lvl;
+    // xg_gpx groups per XCD, xg_groups groups allocated, their control
+    // blocks (group_ctl_bytes() each, zeroed before the launch), 17
+    // registration counters (zeroed), and the longest wait allowed, in
+    // wall-clock ticks
+    int32_t xg_gpx;
+    int32_t xg_groups;
+    void *xg_ctl;
+    unsigned int *xg_reg;
+    long long xg_timeout;
+    long long xg_cand_stride;  // per-group entries of the bottom-up candidate array (cand)
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.
@@ -145,6 +157,11 @@ KernelRef brandes_lds_kernel(int block);
 KernelRef brandes_ms_kernel(int block, int b);
 // Bytes of visited mask per vertex for b sources per task.
 int ms_mask_bytes(int b);
+// Group kernel (nk_group.hip): the workgroups of one XCD run one source
+// together; its dynamic LDS holds the visited bitmap (4 * ceil(n / 32)
+// bytes).  Every workgroup of the launch must be resident at once.
+KernelRef brandes_group_kernel(int block);
+size_t group_ctl_bytes();
 size_t lds_graph_bytes(int32_t n, int64_t m);
 hipError_t launch_validate_batched(const int32_t *rowptr_cat, const int32_t *colidx_cat, const long long *g_vtx,
                                    const long long *g_arc, int32_t G, DevStatus *st, hipStream_t s);

@@ -139,6 +139,26 @@ nk_status ms_alloc(const MsPlan &mp, Params &p, Scratch &scr);
 nk_status ms_enqueue(const MsPlan &mp, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 void stats_set_batch(int b);
 
+// Group launch (nk_group.hip): one source per group of workgroups sharing
+// an XCD's L2.
+struct GroupPlan {
+    LaunchPlan lp;
+    int gpx;               // groups per XCD
+    int groups;            // groups allocated (XCDs x gpx)
+    long long stride;      // per-group vertex capacity
+    long long timeout;     // wall-clock ticks a wait may last
+};
+// Whether the group kernel takes a graph of n_max vertices and m_arcs arcs:
+// automatically for sparse graphs of 10^5 to 3 * 10^5 vertices, for every
+// graph under tuning flag bit 3, never under bit 4 or an explicit
+// multi-source batch; and only if its visited bitmap fits LDS.
+bool group_wanted(int32_t n_max, int64_t m_arcs);
+nk_status plan_group(int32_t n_max, GroupPlan *gp);
+nk_status group_alloc(const GroupPlan &gp, Params &p, Scratch &scr);
+// Clears the path counts, control blocks and registration counters, then
+// launches (cooperatively unless the stream is being captured).
+nk_status group_enqueue(const GroupPlan &gp, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+
 // Grid-wide direction-optimising breadth-first search (nk_bfs.hip).
 struct BfsWork {
     int32_t *d;        // n distances from the source (-1 unreached)

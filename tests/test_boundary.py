@@ -60,15 +60,17 @@ def test_host_argument_checks():
 def test_tuning_roundtrip():
     import paper_1403_3005_amd as nk
     old = nk.nk_get_tuning()
-    nk.nk_set_tuning(block=512, bu_ratio=2.0, wg_per_cu=1, flags=1, bw_ratio=0.5, scratch_mib=64, batch=8)
+    nk.nk_set_tuning(block=512, bu_ratio=2.0, wg_per_cu=1, flags=1, bw_ratio=0.5, scratch_mib=64, batch=8, group=4)
     assert nk.nk_get_tuning() == {"block": 512, "bu_ratio": 2.0, "wg_per_cu": 1, "flags": 1, "bw_ratio": 0.5,
-                                  "scratch_mib": 64, "batch": 8}
+                                  "scratch_mib": 64, "batch": 8, "group": 4}
     with pytest.raises(nk.NkError):
         nk.nk_set_tuning(block=300)
     with pytest.raises(nk.NkError):
         nk.nk_set_tuning(batch=3)
     with pytest.raises(nk.NkError):
         nk.nk_set_tuning(scratch_mib=-1)
+    with pytest.raises(nk.NkError):
+        nk.nk_set_tuning(group=3)
     nk.nk_set_tuning(**old)
 
 
