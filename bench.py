@@ -51,24 +51,30 @@ PLACEMENT = {0: "k_brandes (global bitmap)", 1: "k_brandes (LDS bitmap)", 2: "k_
              7: "k_brandes_lds + k_brandes + k_brandes_group"}
 
 
-def kernel_source_hash() -> str:
+# sources of each kernel that counter summaries are tied to
+KERNEL_SOURCES = {"k_brandes": ["nk_device.h", "nk_kernels.h", "nk_kernels.hip"],
+                  "k_brandes_ms": ["nk_device.h", "nk_kernels.h", "nk_multi.hip"],
+                  "k_brandes_group": ["nk_device.h", "nk_kernels.h", "nk_group.hip"]}
+
+
+def kernel_source_hash(kernel: str = KERNEL) -> str:
     h = hashlib.sha256()
-    for name in ["nk_device.h", "nk_kernels.h", "nk_kernels.hip"]:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1403_3005_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload: str):
+def counter_traffic(workload: str, kernel: str = KERNEL):
     """HBM bytes per launch of the main kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_counters.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", text)
     m_bytes = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(kernel):
         return None
     return float(m_bytes.group(1))
 
@@ -314,7 +320,8 @@ def batched_record(args) -> dict:
            "arcs_total": int(arc[-1]), "source_edges": work, "n_range": [1000, 200_000], "launches": 1,
            "kernel_ms": round(kern_s * 1e3, 1), "kernels": PLACEMENT.get(st["bitmap_lds"], st["bitmap_lds"]),
            "block": st["block"], "workgroups": st["workgroups"], "sources_per_task": st["sources_per_task"],
-           "roofline": roofline(alg_bytes(st), kern_s, "k_brandes_lds + k_brandes (batched, whole run)")}
+           "roofline": roofline(alg_bytes(st), kern_s,
+                                PLACEMENT.get(st["bitmap_lds"], "batched") + " (batched, whole run)")}
     if not args.no_per_source:
         big = max(graphs, key=lambda g: g.n)
         grp, gci = torch.from_numpy(big.rowptr).to(dev), torch.from_numpy(big.colidx).to(dev)
@@ -446,12 +453,13 @@ def other_workload(args) -> dict:
         src = np.arange(4096, dtype=np.int32)
         rp, ci, sv = up(g.rowptr), up(g.colidx), up(src)
         bc = torch.empty(g.n, dtype=torch.float64, device=dev)
-        if args.batch:
-            nk.nk_set_tuning(batch=args.batch)
+        if args.batch or args.tuning_flags:
+            nk.nk_set_tuning(batch=args.batch, flags=args.tuning_flags)
         sec = _timed(lambda: nk.nk_bc_sources(rp, ci, sv, g.n / 4096, bc=bc), args.steps, args.warmup)
         st = nk.nk_last_stats()
         alg = alg_bytes(st)
         kern_s = st["kernel_us"] * 1e-6
+        kname = {4: "k_brandes_ms", 6: "k_brandes_group"}.get(st["bitmap_lds"], KERNEL)
         rec.update(metric="GTEPS, source-sampled Brandes", unit="GTEPS", dtype="f64",
                    value=round(4096 * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
                    config={"workload": "er200k_sources4096", "graph": "Erdos-Renyi G(2e5, 8e5), seed 7",
@@ -461,7 +469,7 @@ def other_workload(args) -> dict:
                            "arcs_reached": st["arcs_reached"], "dag_arcs": st["dag_arcs"]},
                    roofline={"bound": "hbm", "achieved": round(alg / kern_s / 1e9, 1), "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / PEAK_HBM_GBS, 4),
-                             "traffic": counter_traffic("er200k_sources4096"), "kernel": KERNEL,
+                             "traffic": counter_traffic("er200k_sources4096", kname), "kernel": kname,
                              "algorithmic_bytes_per_launch": alg})
     elif args.workload == "er2000":
         g = gg.workload_er2000(1)
@@ -621,6 +629,8 @@ def main():
     ap.add_argument("--no-per-source", action="store_true", help="skip the per-source kernel baseline")
     ap.add_argument("--batch", type=int, default=0,
                     help="sources per workgroup task for the er200k workload (tuning field batch; 0 = automatic)")
+    ap.add_argument("--tuning-flags", type=int, default=0,
+                    help="tuning flags for the er200k workload (16 = one source per workgroup, no group kernel)")
     ap.add_argument("--serving-qps", type=float, default=8.0)
     ap.add_argument("--serving-requests", type=int, default=96,
                     help="requests of the default serving line; measured requests per point of --workload serving")

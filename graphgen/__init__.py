@@ -354,17 +354,6 @@ def workload_chung_lu4m(seed: int = 3) -> Graph:
     return chung_lu(4_000_000, 2.5, 20.0, seed)
 
 
-def workload_batched(count: int = 512, lo: int = 1000, hi: int = 200_000, seed: int = 4):
-    """The batched workload: `count` graphs with n log-uniform in [lo, hi];
-    graph i is Erdos-Renyi with m = 4n edges when i is even, else
-    Barabasi-Albert with m0 = 4; graph i draws its seed from (seed, 61, i)."""
-    graphs = []
-    for i, n in enumerate(batched_sizes(count, lo, hi, seed)):
-        gs = draw(seed, 61, i, 0)
-        graphs.append(erdos_renyi(n, 4 * n, gs) if i % 2 == 0 else barabasi_albert(n, 4, gs))
-    return graphs
-
-
 def batched_sizes(count: int, lo: int, hi: int, seed: int):
     """Vertex counts log-uniform in [lo, hi] for a batch of graphs."""
     out = []

@@ -602,7 +602,7 @@ nk_status plan_group(int32_t n_max, GroupPlan *gp) {
     // workgroups per group: the tuning's, else 4 (measured fastest on the
     // mid-size graphs; whole-XCD groups leave each workgroup too few tiles
     // per level)
-    const int per_xcd = std::max(1, di.cus * per_cu / nxcc);
+    const int per_xcd = std::max(1, di.cus * per_cu / nxcc);   // (one XCD has per_cu fewer)
     int gsz = t.group > 0 ? t.group : 4;
     if (gsz > per_xcd) gsz = per_xcd;
     gp->gpx = std::max(1, per_xcd / gsz);
@@ -612,7 +612,10 @@ nk_status plan_group(int32_t n_max, GroupPlan *gp) {
     gp->lp.mode = kModeBC;
     gp->lp.block = block;
     gp->lp.lds = true;
-    gp->lp.grid = di.cus * per_cu;
+    // one compute unit stays free: a workgroup fills its compute unit's
+    // vector registers, and the runtime's copy kernels (a progress read
+    // while the launch runs) need a place to run
+    gp->lp.grid = std::max(1, di.cus - 1) * per_cu;
     gp->lp.dyn_lds = dyn;
     gp->lp.stride = gp->stride;
     gp->lp.bm_words = 0;

@@ -17,8 +17,11 @@
 // Group membership comes from the XCC_ID hardware register, read by each
 // workgroup at start, so it does not depend on how workgroups are
 // dispatched.  Every workgroup of the launch must be resident at once (the
-// launch is sized to one workgroup per compute unit and made cooperative
-// where the runtime allows); a registration count checks this.
+// launch is sized to one workgroup per compute unit, all but one compute
+// unit, and made cooperative where the runtime allows); a registration
+// count checks this.  A 1024-thread workgroup holds all of its compute
+// unit's vector registers, so the compute unit left free is where the
+// runtime's copy kernels run meanwhile (a progress read during the launch).
 //
 // Data exchange inside a group relies on the XCD's L2 being the point of
 // coherence for all its compute units: a workgroup's stores reach L2 before
