@@ -489,13 +489,18 @@ nk_status nk_get_tuning(nk_tuning *t);
  * Autotuner: times with nk_bc_sources on the given sample of sources
  * (DEVICE int32[k]) every setting of block in {256, 512, 1024}, bu_ratio in
  * {0, 2, 8, 16, 64} and bw_ratio in {0, 0.1, 0.25, 1} (one source per task),
- * then from the fastest of those one resident workgroup per compute unit
- * and batch = 4, 8 and 16 sources per task (block 1024), and returns the
- * fastest in *best (HOST).  The current tuning is left unchanged.  If cache_path is not
- * NULL the winner is stored there under the graph's shape bucket
- * (floor log2 n, round log2 mean degree, round log2 max degree / mean
- * degree) in a flat JSON object
- * {"bucket": [block, bu_ratio, bw_ratio, wg_per_cu, batch, ms]}.
+ * on the one-source kernel (flags bit 4), then from the fastest of those
+ * one resident workgroup per compute unit, batch = 4, 8 and 16 sources per
+ * task (block 1024) and, where its bitmap fits LDS, the group kernel
+ * (flags bit 3) with group = 2, 4 and 8 workgroups per source, and returns
+ * the fastest in *best (HOST).  The current tuning is left unchanged.  If
+ * cache_path is not NULL the winner is stored there under the graph's
+ * shape bucket (floor log2 n, round log2 mean degree, round log2 max
+ * degree / mean degree) in a flat JSON object
+ * {"bucket": [block, bu_ratio, bw_ratio, wg_per_cu, batch, ms,
+ * kernel_flags, group]}, kernel_flags being the winner's flag bits 3 and 4
+ * (8 or 16).  Entries of six values (no kernel choice) and of four
+ * ([block, bu_ratio, bw_ratio, ms]) are read as well.
  */
 nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, const int32_t *sources,
                       int32_t k, const char *cache_path, nk_tuning *best, void *stream);
@@ -511,8 +516,9 @@ nk_status nk_tuning_lookup(const char *cache_path, int32_t n, int64_t m, int64_t
  * call, every batched call or plan (for the launch of its graphs
  * too large for the all-in-LDS kernel, by the largest of them) and every
  * server graph added later (for its source requests) whose shape bucket has
- * an entry runs under that entry's block, bu_ratio, bw_ratio, wg_per_cu and
- * batch (flags and scratch_mib stay those of nk_set_tuning), found by one
+ * an entry runs under that entry's block, bu_ratio, bw_ratio, wg_per_cu,
+ * batch and, for eight-value entries, group and flag bits 3 and 4 (the
+ * other flags and scratch_mib stay those of nk_set_tuning), found by one
  * maximum-degree reduction per call; other graphs run under the global
  * tuning.  The file is read when registered and re-read when nk_autotune
  * writes it.  NK_E_INVALID_ARG if it cannot be read.

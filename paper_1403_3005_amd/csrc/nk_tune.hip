@@ -2,10 +2,11 @@
 //
 // For a graph and a sample of its sources, times with the source-set entry
 // point every setting of the workgroup size and the two direction
-// thresholds (forward bottom-up switch, backward push switch), then, from
-// the fastest of those, the resident workgroups per compute unit and the
-// sources per workgroup task (the multi-source kernel), and keeps the
-// fastest.  Winners are stored per graph-shape bucket -- (floor log2 n,
+// thresholds (forward bottom-up switch, backward push switch) on the
+// one-source kernel, then, from the fastest of those, the resident
+// workgroups per compute unit, the sources per workgroup task (the
+// multi-source kernel) and the workgroups per source (the group kernel),
+// and keeps the fastest.  Winners are stored per graph-shape bucket -- (floor log2 n,
 // round log2 mean degree, round log2 of max degree / mean degree) -- in a
 // flat JSON object.  Once a cache file is registered (nk_set_tuning_cache),
 // single-graph calls, batched plans and the server run every graph whose
@@ -37,9 +38,12 @@ static std::string bucket_key(int32_t n, int64_t m, int64_t maxdeg) {
 }
 
 // The cache file is a flat JSON object:
-// {"key": [block, bu_ratio, bw_ratio, wg_per_cu, batch, ms], ...}; entries
-// of four values [block, bu_ratio, bw_ratio, ms] (older files) read as
-// wg_per_cu = 0, batch = 0.
+// {"key": [block, bu_ratio, bw_ratio, wg_per_cu, batch, ms, kernel_flags,
+// group], ...}, kernel_flags being the winner's tuning flag bits 3 and 4
+// (group kernel forced or forbidden); entries of six values (no kernel
+// choice: the flags stay the caller's, group 0) and of four values
+// [block, bu_ratio, bw_ratio, ms] (also wg_per_cu = 0, batch = 0) are read
+// too.
 static std::map<std::string, std::vector<double>> read_cache(const char *path) {
     std::map<std::string, std::vector<double>> out;
     if (!path) return out;
@@ -71,7 +75,8 @@ static std::map<std::string, std::vector<double>> read_cache(const char *path) {
             p = q;
         }
         if (vals.size() == 4) vals = {vals[0], vals[1], vals[2], 0.0, 0.0, vals[3]};
-        if (vals.size() == 6) out[key] = vals;
+        if (vals.size() == 6) vals.insert(vals.end(), {-1.0, 0.0});
+        if (vals.size() == 8) out[key] = vals;
         i = b + 1;
     }
     return out;
@@ -84,9 +89,9 @@ static bool write_cache(const char *path, const std::map<std::string, std::vecto
     fprintf(f, "{\n");
     size_t k = 0;
     for (const auto &kv : c) {
-        fprintf(f, "  \"%s\": [%d, %.6g, %.6g, %d, %d, %.6g]%s\n", kv.first.c_str(), (int)kv.second[0],
+        fprintf(f, "  \"%s\": [%d, %.6g, %.6g, %d, %d, %.6g, %d, %d]%s\n", kv.first.c_str(), (int)kv.second[0],
                 kv.second[1], kv.second[2], (int)kv.second[3], (int)kv.second[4], kv.second[5],
-                ++k < c.size() ? "," : "");
+                (int)kv.second[6], (int)kv.second[7], ++k < c.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -122,6 +127,10 @@ static void merge_entry(const std::vector<double> &e, nk_tuning *t) {
     t->bw_ratio = (float)e[2];
     t->wg_per_cu = (int32_t)e[3];
     t->batch = (int32_t)e[4];
+    if (e[6] >= 0.0) {
+        t->flags = (t->flags & ~24) | ((int32_t)e[6] & 24);
+        t->group = (int32_t)e[7];
+    }
 }
 
 bool tuning_cache_active() {
@@ -230,6 +239,8 @@ nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, i
                 t.bw_ratio = bw;
                 t.wg_per_cu = 0;
                 t.batch = 1;
+                t.flags = (saved.flags & ~24) | 16;   // the one-source kernel
+                t.group = 0;
                 if (result == NK_OK) trial(t);
             }
     // stage 2: from the stage-1 winner, one resident workgroup per compute
@@ -245,6 +256,18 @@ nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, i
             t.block = 1024;
             if (result == NK_OK) trial(t);
         }
+        // the group kernel with 2, 4 and 8 workgroups per source, where its
+        // visited bitmap fits LDS
+        for (int g : {2, 4, 8}) {
+            t = base;
+            t.flags = (saved.flags & ~24) | 8;
+            t.group = g;
+            t.block = 1024;
+            t.wg_per_cu = 0;
+            tuning_set(t);
+            const bool fits = group_wanted(n, m);
+            if (fits && result == NK_OK) trial(t);
+        }
     }
     tuning_set(saved);
     (void)hipFree(bc);
@@ -254,7 +277,8 @@ nk_status nk_autotune(const int32_t *rowptr, const int32_t *colidx, int32_t n, i
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto c = read_cache(cache_path);
         c[bucket_key(n, m, dmax)] = {(double)win.block, (double)win.bu_ratio, (double)win.bw_ratio,
-                                     (double)win.wg_per_cu, (double)win.batch, best_ms};
+                                     (double)win.wg_per_cu, (double)win.batch, best_ms,
+                                     (double)(win.flags & 24), (double)win.group};
         if (!write_cache(cache_path, c)) return fail(NK_E_INVALID_ARG, "cannot write %s", cache_path);
         if (g_active_path == cache_path) g_active = c;
     }

@@ -110,6 +110,21 @@ def test_tuning_cache_formats_and_registration(tmp_path):
     assert (t["block"], t["bu_ratio"], t["bw_ratio"], t["wg_per_cu"], t["batch"]) == (256, 2.0, 0.25, 1, 8)
     t = nk.nk_tuning_lookup(str(path), 1500, 12000, 64)
     assert (t["block"], t["bu_ratio"], t["wg_per_cu"], t["batch"]) == (512, 8.0, 0, 0)
+    # eight values: the kernel choice (flag bits 3 and 4) and workgroups per
+    # source; other flag bits stay the caller's
+    path8 = tmp_path / "c8.json"
+    path8.write_text(json.dumps({"n17_d3_s3": [1024, 16, 0.1, 0, 1, 120.5, 8, 4],
+                                 "n16_d3_s3": [1024, 16, 0.1, 0, 1, 80.0, 16, 0]}))
+    old = nk.nk_get_tuning()
+    try:
+        nk.nk_set_tuning(flags=2 | 16)
+        t = nk.nk_tuning_lookup(str(path8), 200_000, 1_600_000, 64)
+        assert (t["flags"], t["group"], t["batch"]) == (2 | 8, 4, 1)
+        nk.nk_set_tuning(flags=2 | 8)
+        t = nk.nk_tuning_lookup(str(path8), 100_000, 800_000, 64)
+        assert (t["flags"], t["group"]) == (2 | 16, 0)
+    finally:
+        nk.nk_set_tuning(**old)
     with pytest.raises(nk.NkError):
         nk.nk_tuning_lookup(str(path), 100000, 800000, 64)
     with pytest.raises(nk.NkError):
