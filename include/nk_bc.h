@@ -412,7 +412,9 @@ nk_status nk_batch_plan_finish(nk_batch_plan *plan, void *stream);
  *   out[11] arcs of reached vertices (sum of their degrees, over sources)
  *   out[12] dependency-sweep levels run by push
  *   out[13] sources per workgroup task (multi-source kernel; else 1)
- *   out[14..15] reserved
+ *   out[14] pair samples that could outgrow their slot's hashed records
+ *           and ran again with one record per vertex (flags bit 6)
+ *   out[15] reserved
  *   (nk_bc_weighted: out[2] arcs relaxed in the distance rounds, out[5]
  *   distance rounds, out[6] shortest-path DAG layers, out[4] DAG arcs)
  *   out[16..23] shader-clock cycles per phase, summed over workgroups:
@@ -446,6 +448,16 @@ nk_status nk_last_stats(int64_t *out);
  *              run one source together with its path counts in that XCD's
  *              L2 (graphs whose visited bitmap fits LDS: up to about 1.1
  *              million vertices); block 512 makes two groups per XCD;
+ *              bit 4: never use the group kernel (the automatic choice runs
+ *              it on sparse graphs of 10^5 to 3 * 10^5 vertices);
+ *              bit 5: pair sampling always keeps one record per vertex per
+ *              workgroup slot; bit 6: it keeps a hash table of the reached
+ *              vertices per slot instead (n/16 entries, rounded up to a
+ *              power of two in [2^14, 2^18]; graphs above 4x that) and runs
+ *              the samples that could fill more than half of it again with
+ *              one record per vertex -- which it does by itself when records
+ *              per vertex (68 bytes per vertex per slot) would leave fewer
+ *              than two slots per compute unit in half the device memory;
  *   bw_ratio   in the dependency sweep, handle level l by pushing from level
  *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
  *              of level l (0 = always pull; default 0.1);

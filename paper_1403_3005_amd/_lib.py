@@ -440,7 +440,7 @@ class NkBatchPlan:
 
 
 STAT_KEYS = ["sources", "reached", "arcs_fwd", "arcs_bwd", "dag_arcs", "levels_td", "levels_bu", "workgroups",
-             "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "sources_per_task", "reserved14",
+             "kernel_us", "block", "bitmap_lds", "arcs_reached", "levels_bw_push", "sources_per_task", "pair_deferred",
              "reserved15", "cyc_init", "cyc_topdown", "cyc_bottomup", "cyc_mark", "cyc_pull", "cyc_push",
              "cyc_reset", "cyc_other", "sub_bu_stage", "sub_bu_arcs", "sub_bu_finalize", "sub_pull_stage",
              "sub_pull_arcs", "sub_pull_finalize", "reserved30", "reserved31"]

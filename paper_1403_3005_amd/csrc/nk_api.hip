@@ -262,7 +262,8 @@ void stats_record(const DevStatus &st, int grid, int block, int lds, float kerne
     t_stats[11] = (int64_t)st.stat[kStArcsReached];
     t_stats[12] = (int64_t)st.stat[kStBwPush];
     t_stats[13] = 1;
-    t_stats[14] = t_stats[15] = 0;
+    t_stats[14] = (int64_t)st.stat[kStDeferred];
+    t_stats[15] = 0;
     for (int i = 0; i < kNumPhases; ++i) t_stats[16 + i] = (int64_t)st.cycles[i];
     for (int i = 0; i < 8; ++i) t_stats[24 + i] = (int64_t)st.sub[i];
 }
@@ -331,7 +332,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         block = auto_block(n_max);
         // a pair sample's search levels are small: more concurrent samples
         // of 256 threads hide more memory latency than fewer wide ones
-        if (mode == kModePair) block = 256;
+        if (mode == kModePair || mode == kModePairHash) block = 256;
     }
     const long long words = ((long long)n_max + 31) / 32;
     const size_t bm_bytes = (size_t)words * 4;
@@ -345,7 +346,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         NK_HIP(hipFuncGetAttributes(&attr, probe.fn));
         // pair mode keeps two visited bitmaps (one per search side) in global memory
         lds = attr.sharedSizeBytes + std::max(bm_bytes, hist_bytes) <= di.lds_per_block && !(t.flags & 1) &&
-              mode != kModePair;
+              mode != kModePair && mode != kModePairHash;
     }
     KernelRef kr = brandes_kernel(mode, block, lds);
     size_t dyn = std::max(lds ? bm_bytes : 0, hist_bytes);
@@ -369,11 +370,13 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
         // bitmap when it does not sit in LDS
         // weighted: + u64 distances, round marks, two worklists and the far pile (24)
         // bisection: + kBisK cutoff coefficients per vertex
+        // hashed pair records: + the two sides' table slots (8)
         size_t per_slot = (size_t)stride * (mode == kModePair       ? 68
+                                            : mode == kModePairHash ? 76
                                             : mode == kModeWeighted ? 68
                                             : mode == kModeBisect   ? 44 + 8 * kBisK
                                                                     : 44);
-        if (mode != kModePair && !lds) per_slot += (size_t)wordsr * 4;
+        if (mode != kModePair && mode != kModePairHash && !lds) per_slot += (size_t)wordsr * 4;
         // weighted: one bit per arc marks the shortest-path DAG
         if (mode == kModeWeighted) per_slot += (size_t)dag_words_of(m_arcs) * 4;
         size_t avail;
@@ -386,7 +389,7 @@ nk_status plan_launch(int mode, int32_t n_max, long long ntasks, int max_slots, 
             // pair samples touch their slots' records at random: beyond
             // about half the device's memory, more slots add address-
             // translation misses faster than they hide latency
-            if (mode == kModePair && avail > tot / 2) avail = tot / 2;
+            if ((mode == kModePair || mode == kModePairHash) && avail > tot / 2) avail = tot / 2;
         }
         const long long fit = (long long)(avail / per_slot);
         if (fit < 1)
@@ -680,8 +683,9 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
     const long long slots = plan.grid;
     const long long cells = slots * plan.stride;
     nk_status st;
-    const bool pair = plan.mode == kModePair;
+    const bool pair = plan.mode == kModePair || plan.mode == kModePairHash;
     p.sigma = nullptr;
+    p.ls = p.ls2 = nullptr;
     p.ldeg = nullptr;
     p.d = nullptr;
     p.lvl = nullptr;
@@ -710,6 +714,10 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
         if ((st = scr.get(cells, &p.lv2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.la2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ld2)) != NK_OK) return st;
+        if (plan.mode == kModePairHash) {
+            if ((st = scr.get(cells, &p.ls)) != NK_OK) return st;
+            if ((st = scr.get(cells, &p.ls2)) != NK_OK) return st;
+        }
         if (!clean) NK_HIP(launch_pair_rec_init(p.pair_rec, (long long)(rec_bytes / 32), s));
     } else {
         if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
@@ -738,7 +746,7 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
 }
 
 nk_status persistent_enqueue(const LaunchPlan &plan, const Params &p, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (plan.mode != kModePair) {
+    if (plan.mode != kModePair && plan.mode != kModePairHash) {
         const long long cells = (long long)plan.grid * plan.stride;
         if (plan.mode == kModeWeighted) {
             NK_HIP(launch_fill_u64(p.dist, ~0ULL, cells, s));
@@ -1467,8 +1475,29 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
         if ((st = scr.get(n, &cnt)) != NK_OK) return st;
         NK_HIP(launch_fill_u32(cnt, 0u, n, s));
     }
+    // Records: one per vertex per slot, unless that leaves fewer than two
+    // slots per compute unit (68 bytes per vertex per slot against half the
+    // device memory) -- then each slot keeps a hash table of the vertices
+    // its sample reaches (n / 16 entries rounded up to a power of two, in
+    // [2^14, 2^18]; a sample lists a few thousand), and samples that could
+    // fill more than half of it run afterwards with one record per vertex.
+    // Hashing costs a probe per access: on a 4 * 10^6-vertex graph, where
+    // 512 slots of records fit, 768 hashed slots were slower.  Tuning flag
+    // bit 6 forces the tables, bit 5 forbids them.
+    int32_t hlog = kPairHashMinLog2;
+    while (hlog < kPairHashMaxLog2 && (1LL << hlog) < (long long)n / 16) ++hlog;
+    const long long hcap = 1LL << hlog;
+    const int32_t tflags = tuning_get().flags;
     LaunchPlan plan;
-    if ((st = plan_launch(kModePair, n, count, 0, &plan)) != NK_OK) return st;
+    if ((st = plan_launch(kModePair, n, count, 0, &plan)) != NK_OK && st != NK_E_NO_MEMORY) return st;
+    DevInfo di;
+    if (dev_info(&di) != NK_OK) return NK_E_HIP;
+    const bool short_of_slots = st == NK_E_NO_MEMORY || (plan.grid < 2LL * di.cus && plan.grid < count);
+    clear_error();
+    const bool hashed = !(tflags & 32) && (long long)n > 4 * hcap && ((tflags & 64) || short_of_slots);
+    if (hashed && (st = plan_launch(kModePairHash, (int32_t)(hcap - 2), count, 0, &plan)) != NK_OK) return st;
+    if (!hashed && st == NK_E_NO_MEMORY)
+        return fail(NK_E_NO_MEMORY, "one pair-sampling slot with a record per vertex (n = %d) does not fit", n);
     Params p;
     memset(&p, 0, sizeof(p));
     p.rowptr = g.rowptr;
@@ -1487,9 +1516,36 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     p.inv = g.inv;
     p.iso = iso;
     p.st = dst;
-    if ((st = launch_persistent(plan, p, scr, s, ev0, ev1)) != NK_OK) return st;
-    if (counts && g.perm) NK_HIP(launch_gather_u32(cnt, g.perm, n, counts, s));
+    unsigned long long *dcount = nullptr;
+    if (hashed) {
+        p.ph_log2 = hlog;
+        if ((st = scr.get(count, &p.defer)) != NK_OK) return st;
+        if ((st = scr.get(1, &dcount)) != NK_OK) return st;
+        NK_HIP(launch_fill_u64(dcount, 0ULL, 1, s));
+        p.defer_count = dcount;
+    }
+    if ((st = launch_persistent(plan, p, scr, s, ev0, hashed ? nullptr : ev1)) != NK_OK) return st;
     plan.pair_rec = p.pair_rec;
+    if (hashed) {
+        unsigned long long nd = 0;
+        NK_HIP(hipMemcpyAsync(&nd, dcount, sizeof(nd), hipMemcpyDeviceToHost, s));
+        NK_HIP(hipStreamSynchronize(s));
+        if (nd > 0) {
+            // the deferred samples, one record per vertex, outputs by sample
+            LaunchPlan full;
+            if ((st = plan_launch(kModePair, n, (long long)nd, 0, &full)) != NK_OK) return st;
+            Params q = p;
+            q.ntasks = (long long)nd;
+            q.task_list = p.defer;
+            q.defer = nullptr;
+            q.defer_count = nullptr;
+            NK_HIP(launch_reset_head(dst, s));
+            if ((st = launch_persistent(full, q, scr, s, nullptr, nullptr)) != NK_OK) return st;
+            // (its records end all-unreached too, but stay untagged)
+        }
+        if (ev1) NK_HIP(hipEventRecord(ev1, s));
+    }
+    if (counts && g.perm) NK_HIP(launch_gather_u32(cnt, g.perm, n, counts, s));
     *plan_out = plan;
     return NK_OK;
 }

@@ -43,6 +43,7 @@ enum PairSubIdx { kSbPairSearch = 0, kSbPairSelect, kSbPairWalk, kSbPairClear };
 enum StatIdx {
     kStSources = 0, kStReached, kStArcsFwd, kStArcsBwd, kStDag, kStTd, kStBu, kStArcsReached, kStBwPush,
     kStDone,   // sources (or samples) finished so far, added as each task ends (progress of a long run)
+    kStDeferred,   // pair samples left by the hashed-record launch to one with a record per vertex
     kNumStats = 12
 };
 

@@ -16,8 +16,18 @@ enum Mode : int {
     kModePair = 2,  // one sampled pair: bidirectional search and path walk
     kModeClose = 3,  // forward with unit path counts; distance sums for closeness
     kModeBisect = 4,  // betweenness with the bisection estimator
-    kModeWeighted = 5  // betweenness over positive integer arc weights
+    kModeWeighted = 5,  // betweenness over positive integer arc weights
+    kModePairHash = 6   // pair mode with each slot's records in a hash table keyed by vertex
 };
+
+// Pair mode with hashed records: a table of 2^ph_log2 entries per slot,
+// ph_log2 in [kPairHashMinLog2, kPairHashMaxLog2] chosen from the graph's
+// size; a sample that could list more than half of it is left to a later
+// launch with one record per vertex, and no probe passes kPairHashProbes
+// entries.
+constexpr int kPairHashMinLog2 = 14;
+constexpr int kPairHashMaxLog2 = 18;
+constexpr int kPairHashProbes = 128;
 
 // Weighted mode: distinct distances the bucket layering handles; its
 // histogram takes kDistBuckets ints of dynamic LDS.
@@ -137,6 +147,18 @@ struct Params {
     unsigned int *xg_reg;
     long long xg_timeout;
     long long xg_cand_stride;  // per-group entries of the bottom-up candidate array (cand)
+    // pair modes: task_list (if not NULL) maps launch task t to sample
+    // task_list[t] (outputs indexed by the sample); hashed records: each
+    // listed vertex's table slot for both sides (ls, ls2, `stride` entries
+    // per slot) and the samples left for a launch with one record per vertex
+    // (defer, *defer_count)
+    const long long *task_list;
+    int32_t ph_log2;           // hashed records: log2 of the entries per slot (stride = 2^ph_log2)
+    int32_t pad3;
+    int32_t *ls;
+    int32_t *ls2;
+    long long *defer;
+    unsigned long long *defer_count;
 };
 
 // Kernel handle for one (mode, block, bitmap placement) instantiation.

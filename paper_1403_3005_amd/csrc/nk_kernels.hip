@@ -85,6 +85,7 @@ struct Scr {
     int32_t *ld;                // degree
     int32_t *lvl;               // level offsets
     int32_t *cand;
+    int32_t *ls;                // hashed pair records: table slot of each listed vertex
 };
 
 struct Counters {
@@ -1264,6 +1265,7 @@ struct BiState {
     int32_t result;                  // 0 searching, 1 met, -1 unreachable, -3 overflow
     int32_t pad;
     int32_t pickw, pickv;            // block walk: first crossing wave, chosen vertex
+    int32_t full;                    // hashed records: a claim found the table full
     unsigned long long part_lo[16], part_hi[16];
     unsigned long long total, r0;
 };
@@ -1304,7 +1306,60 @@ __device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long 
 struct PairRec {
     unsigned long long sig[2];   // path counts from u (side 0) and from v (side 1)
     int32_t d[2];                // distances from u and from v
-    int32_t pad[2];
+    int32_t key;                 // hashed records: vertex + 1 (0 = free entry)
+    int32_t pad;
+};
+
+// Record access: one record per vertex (DirectRecs), or a per-slot table of
+// 2^ph_log2 entries keyed by vertex with linear probing (HashRecs), whose
+// free entries hold the unreached state, so a claimed entry needs no set-up.
+// A sample claims an entry the first time a search side reaches its vertex,
+// lists the vertex with the entry's slot, and frees every listed slot at
+// the end.  Within a sample keys are only added, so a probe that meets a
+// free entry has seen all of the vertex's chain.  The table stays at most
+// half full (a level that could pass that is not run), and a probe gives
+// up after kPairHashProbes entries (the sample is then deferred as well).
+struct DirectRecs {
+    static constexpr bool kHashed = false;
+    PairRec *R;
+    __device__ PairRec *find(int32_t v) const { return R + v; }
+    __device__ PairRec *claim(int32_t v) const { return R + v; }
+    __device__ int32_t slot(const PairRec *e) const { return (int32_t)(e - R); }
+    __device__ PairRec *listed(const Scr &s, int32_t i) const { return R + s.lv[i]; }
+};
+
+struct HashRecs {
+    static constexpr bool kHashed = true;
+    PairRec *T;
+    uint32_t mask;     // entries - 1
+    int32_t shift;     // 32 - log2 entries
+    __device__ uint32_t home(int32_t v) const { return ((uint32_t)v * 0x9E3779B1u) >> shift; }
+    // the entry of v, or NULL when no side has reached v (or, past the
+    // probe limit, when the sample is being deferred anyway)
+    __device__ PairRec *find(int32_t v) const {
+        uint32_t h = home(v);
+        for (int i = 0; i < kPairHashProbes; ++i) {
+            const int32_t k = T[h].key;
+            if (k == v + 1) return T + h;
+            if (k == 0) return nullptr;
+            h = (h + 1u) & mask;
+        }
+        return nullptr;
+    }
+    // the entry of v, claimed if v has none; NULL past the probe limit
+    __device__ PairRec *claim(int32_t v) const {
+        uint32_t h = home(v);
+        for (int i = 0; i < kPairHashProbes; ++i) {
+            int32_t k = T[h].key;
+            // the compare-and-swap's old value settles a stale read
+            if (k == 0) k = atomicCAS(&T[h].key, 0, v + 1);
+            if (k == 0 || k == v + 1) return T + h;
+            h = (h + 1u) & mask;
+        }
+        return nullptr;
+    }
+    __device__ int32_t slot(const PairRec *e) const { return (int32_t)(e - T); }
+    __device__ PairRec *listed(const Scr &s, int32_t i) const { return T + s.ls[i]; }
 };
 
 // Top-down growth of side X by one level (list[f0, f1) at distance dep)
@@ -1312,15 +1367,15 @@ struct PairRec {
 // level adds sigma_X(y) to sigma_X(z).  The first adder appends z with its
 // first arc and degree, adds the degree to *newcost, and, when the other
 // side has reached z, appends z to the meeting list (meet, *nm).
-template <int BLOCK>
-__device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, const Scr &s, const GView &g,
+template <int BLOCK, class Recs>
+__device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int X, const Scr &s, const GView &g,
                            int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
-                           unsigned long long *newcost, Counters &c) {
+                           unsigned long long *newcost, int32_t lcap, int32_t *full, Counters &c) {
     const int tid = threadIdx.x;
     unsigned long long dsum = 0;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
-        if (tid < cnt) sm.val.u[tid] = R[s.lv[tb + tid]].sig[X];
+        if (tid < cnt) sm.val.u[tid] = R.listed(s, tb + tid)->sig[X];
         const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
@@ -1329,15 +1384,18 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, 
             load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
             bool act[kChunk];
             unsigned long long add[kChunk], old[kChunk];
+            PairRec *e[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
+                e[j] = kk[j] >= 0 ? R.claim(w[j]) : nullptr;
+                if (Recs::kHashed && kk[j] >= 0 && !e[j]) *full = 1;
                 // unreached, or reached on this very level by another adder
-                const int32_t dz = kk[j] >= 0 ? R[w[j]].d[X] : 0;
-                act[j] = kk[j] >= 0 && (dz < 0 || dz == dep + 1);
+                const int32_t dz = e[j] ? e[j]->d[X] : 0;
+                act[j] = e[j] != nullptr && (dz < 0 || dz == dep + 1);
                 add[j] = act[j] ? sm.val.u[kk[j]] : 0ULL;
             }
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) old[j] = act[j] ? atomicAdd(&R[w[j]].sig[X], add[j]) : 1ULL;
+            for (int j = 0; j < kChunk; ++j) old[j] = act[j] ? atomicAdd(&e[j]->sig[X], add[j]) : 1ULL;
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 const bool fresh = act[j] && old[j] == 0ULL;
@@ -1348,19 +1406,20 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, 
                     if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
                 }
                 if (fresh) {
-                    R[w[j]].d[X] = dep + 1;
+                    e[j]->d[X] = dep + 1;
                     a0 = g.rp[w[j]];
                     dg = g.rp[w[j] + 1] - a0;
-                    met = R[w[j]].d[1 - X] >= 0;
+                    met = e[j]->d[1 - X] >= 0;
                     dsum += (unsigned long long)dg;
                 }
-                const int32_t pos = wave_append_pos(fresh, w[j], s.lv + f1, &sm.count, g.n - f1, &p.st->err);
+                const int32_t pos = wave_append_pos(fresh, w[j], s.lv + f1, &sm.count, lcap - f1, &p.st->err);
                 if (pos >= 0) {
                     s.la[f1 + pos] = a0;
                     s.ld[f1 + pos] = dg;
+                    if (Recs::kHashed) s.ls[f1 + pos] = R.slot(e[j]);
                 }
                 // meeting vertices: new on side X and already reached by the other side
-                wave_append(met, w[j], meet, nm, g.n, &p.st->err);
+                wave_append(met, w[j], meet, nm, lcap, &p.st->err);
             }
         }
         __syncthreads();
@@ -1379,20 +1438,22 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, PairRec *R, int X, 
 // root as its only predecessor.  Thread 0 calls emit(i, vertex) for step
 // i = 1, 2, ..., the root included.  Returns false if no predecessor is
 // found (only after a reported overflow).
-template <int BLOCK, typename Emit>
-__device__ bool walk_block(const Params &p, BiState &bs, const PairRec *R, int X, const GView &g, int32_t from,
+template <int BLOCK, class Recs, typename Emit>
+__device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, const GView &g, int32_t from,
                            int32_t rootv, unsigned long long stream, long long j, Emit emit) {
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = lane_id(), wid = wave_id();
     int32_t x = from;
     for (unsigned long long tt = 0;; ++tt) {
-        const int32_t dx = R[x].d[X];
+        const PairRec *ex = R.find(x);
+        if (!ex) return false;
+        const int32_t dx = ex->d[X];
         if (dx <= 0) return true;
         if (dx == 1) {
             if (tid == 0) emit((int32_t)tt + 1, rootv);
             return true;
         }
-        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), R[x].sig[X]);
+        const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), ex->sig[X]);
         const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         unsigned long long carry = 0ULL;
         int32_t pick = -1;
@@ -1402,7 +1463,8 @@ __device__ bool walk_block(const Params &p, BiState &bs, const PairRec *R, int X
             unsigned long long sp = 0ULL;
             if (e < a1) {
                 pp = g.ci[e];
-                if (R[pp].d[X] == dx - 1) sp = R[pp].sig[X];
+                const PairRec *ep = R.find(pp);
+                if (ep && ep->d[X] == dx - 1) sp = ep->sig[X];
             }
             const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
             if (lane == kWave - 1) bs.part_lo[wid] = incl;
@@ -1448,20 +1510,24 @@ __device__ bool walk_block(const Params &p, BiState &bs, const PairRec *R, int X
 // A (stream 3).  Interior vertices are counted and, for inspection, written
 // from v's side towards u.  The records of every listed vertex are reset at
 // the end, so the next sample starts from unreached records.
-template <int BLOCK>
-__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, PairRec *R, const Scr &sa,
+template <int BLOCK, class Recs>
+__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Recs &R, const Scr &sa,
                              const Scr &sb, const GView &g, int32_t u, int32_t v, long long j, long long task,
-                             Counters &c) {
+                             int32_t lcap, Counters &c) {
     const int tid = threadIdx.x;
+    if (tid == 0) bs.full = 0;
     if (tid < 2) {
+        // (one thread claims each root: u != v, and an empty table has room)
         const Scr &x = tid == 0 ? sa : sb;
         const int32_t r = tid == 0 ? u : v;
         const int32_t a0 = g.rp[r], dg = g.rp[r + 1] - a0;
-        R[r].sig[tid] = 1ULL;
-        R[r].d[tid] = 0;
+        PairRec *er = R.claim(r);
+        er->sig[tid] = 1ULL;
+        er->d[tid] = 0;
         x.lv[0] = r;
         x.la[0] = a0;
         x.ld[0] = dg;
+        if (Recs::kHashed) x.ls[0] = R.slot(er);
         bs.lo[tid] = 0;
         bs.hi[tid] = 1;
         bs.depth[tid] = 0;
@@ -1480,6 +1546,14 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
         const int X = bs.cost[0] <= bs.cost[1] ? 0 : 1;
         const Scr &sx = X == 0 ? sa : sb;
         const int32_t lo = bs.lo[X], hi = bs.hi[X], dep = bs.depth[X];
+        // hashed records: a level that could take the table past half full
+        // (each arc leaving the frontier may add a vertex) is not run
+        if (Recs::kHashed && (long long)bs.hi[0] + bs.hi[1] + bs.cost[X] > (long long)(lcap >> 1)) {
+            __syncthreads();
+            if (tid == 0) bs.result = -4;
+            __syncthreads();
+            break;
+        }
         __syncthreads();
         if (tid == 0) {
             sm.count = 0;
@@ -1488,15 +1562,19 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
         }
         __syncthreads();
         pair_level<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm,
-                          reinterpret_cast<unsigned long long *>(&bs.newcost), c);
+                          reinterpret_cast<unsigned long long *>(&bs.newcost), lcap, &bs.full, c);
         __syncthreads();
-        const int32_t nnew = sm.count < g.n - hi ? sm.count : g.n - hi;
+        const int32_t nnew = sm.count < lcap - hi ? sm.count : lcap - hi;
         if (tid == 0) {
             bs.lo[X] = hi;
             bs.hi[X] = hi + nnew;
             bs.depth[X] = dep + 1;
             bs.cost[X] = bs.newcost;
-            if (nnew == 0)
+            // hashed records: a full table, or one past half full (long
+            // probes), leaves the sample to the one-record-per-vertex launch
+            if (Recs::kHashed && (bs.full || bs.hi[0] + bs.hi[1] > (lcap >> 1)))
+                bs.result = -4;
+            else if (nnew == 0)
                 bs.result = -1;
             else if (bs.nm > 0)
                 bs.result = 1;
@@ -1515,7 +1593,8 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
         int32_t idlo = 0x7fffffff, idhi = -1;
         for (int32_t i = tid; i < nm; i += BLOCK) {
             const int32_t z = sa.cand[i];
-            const unsigned long long a = R[z].sig[0], b = R[z].sig[1];
+            const PairRec *ez = R.find(z);
+            const unsigned long long a = ez->sig[0], b = ez->sig[1];
             const unsigned long long w = a * b;
             if (__umul64hi(a, b) != 0ULL) wrap = true;
             wt[i] = w;
@@ -1580,13 +1659,16 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
     }
     sub_mark<BLOCK>(sm, kSbPairSelect);
     // ---- walks (all threads; thread 0 records)
-    if (bs.result == -1) {
+    if (bs.result == -4) {
+        // left for the launch with one record per vertex
+    } else if (bs.result == -1) {
         if (tid == 0 && p.p_len) p.p_len[task] = -1;
     } else if (bs.result == -3) {
         if (tid == 0 && p.p_len) p.p_len[task] = -3;
     } else {
         const int32_t z = bs.z;
-        const int32_t kb = R[z].d[1], ha = R[z].d[0];
+        const PairRec *ez = R.find(z);
+        const int32_t kb = ez->d[1], ha = ez->d[0];
         const int32_t nb = kb >= 1 ? kb - 1 : 0;
         const int32_t zc = (kb >= 1 && ha >= 1) ? 1 : 0;
         const int32_t len = nb + zc + (ha >= 1 ? ha - 1 : 0);
@@ -1609,15 +1691,17 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, Pair
     __syncthreads();
     sub_mark<BLOCK>(sm, kSbPairWalk);
 
-    // ---- reset the records of every listed vertex (both sides)
+    // ---- reset the records of every listed vertex (both sides); hashed
+    // records also free their entries (no probe runs any more)
     for (int k = 0; k < 2; ++k) {
         const Scr &x = k == 0 ? sa : sb;
         for (int32_t i = tid; i < bs.hi[k]; i += BLOCK) {
-            PairRec &rc = R[x.lv[i]];
+            PairRec &rc = *R.listed(x, i);
             rc.sig[0] = 0ULL;
             rc.sig[1] = 0ULL;
             rc.d[0] = -1;
             rc.d[1] = -1;
+            if (Recs::kHashed) rc.key = 0;
         }
     }
     __syncthreads();
@@ -1639,16 +1723,17 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
 
     const long long slot = blockIdx.x;
     const long long off = slot * p.stride;
+    constexpr bool PAIR = MODE == kModePair || MODE == kModePairHash;
     Scr s;
     // pair mode keeps its path counts and distances in records instead
-    s.sigma = MODE == kModePair ? nullptr : p.sigma + off;
+    s.sigma = PAIR ? nullptr : p.sigma + off;
     s.dacc = p.dacc + off;
-    s.ldeg = MODE == kModePair ? nullptr : p.ldeg + off;
-    s.d = MODE == kModePair ? nullptr : p.d + off;
+    s.ldeg = PAIR ? nullptr : p.ldeg + off;
+    s.d = PAIR ? nullptr : p.d + off;
     s.lv = p.lv + off;
     s.la = p.la + off;
     s.ld = p.ld + off;
-    s.lvl = MODE == kModePair ? nullptr : p.lvl + off;
+    s.lvl = PAIR ? nullptr : p.lvl + off;
     s.cand = p.cand + off;
     s.dist = p.dist ? p.dist + off : nullptr;
     s.mark = p.mark ? p.mark + off : nullptr;
@@ -1657,16 +1742,18 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     s.wl2 = p.wl2 ? p.wl2 + off : nullptr;
     s.dagm = p.dagm ? p.dagm + slot * p.dag_words : nullptr;
     s.bvec = p.bvec ? p.bvec + off * kBisK : nullptr;
-    uint32_t *bm = (BMLDS || MODE == kModePair) ? lds_bm : p.bmg + slot * p.bm_words;
+    uint32_t *bm = (BMLDS || PAIR) ? lds_bm : p.bmg + slot * p.bm_words;
     // pair mode: per-vertex records of both search sides, and the target
     // side's level lists
+    s.ls = MODE == kModePairHash ? p.ls + off : nullptr;
     Scr s2 = s;
     PairRec *rec = nullptr;
-    if (MODE == kModePair) {
+    if (PAIR) {
         rec = reinterpret_cast<PairRec *>(p.pair_rec) + slot * p.stride;
         s2.lv = p.lv2 + slot * p.stride;
         s2.la = p.la2 + slot * p.stride;
         s2.ld = p.ld2 + slot * p.stride;
+        s2.ls = MODE == kModePairHash ? p.ls2 + slot * p.stride : nullptr;
     }
 
     Counters c = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1714,14 +1801,16 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             g.vbase = 0;
             g.trp = p.trowptr ? p.trowptr : p.rowptr;
             g.tci = p.trowptr ? p.tcolidx : p.colidx;
-            if (MODE == kModePair) {
-                j = p.j0 + task;
+            if (PAIR) {
+                // the sample this task runs (a task list maps tasks to samples)
+                const long long tt = p.task_list ? p.task_list[task] : task;
+                j = p.j0 + tt;
                 const int32_t a = (int32_t)bounded(draw(p.seed, 1, (unsigned long long)j, 0), (unsigned long long)p.n);
                 int32_t b = (int32_t)bounded(draw(p.seed, 2, (unsigned long long)j, 0), (unsigned long long)(p.n - 1));
                 if (b >= a) b += 1;
                 if (tid == 0 && p.p_uv) {
-                    p.p_uv[2 * task] = a;
-                    p.p_uv[2 * task + 1] = b;
+                    p.p_uv[2 * tt] = a;
+                    p.p_uv[2 * tt + 1] = b;
                 }
                 src = p.perm ? p.perm[a] : a;
                 target = p.perm ? p.perm[b] : b;
@@ -1733,10 +1822,11 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             if (tid == 0) atomicOr(&p.st->err, kErrArg);
             continue;
         }
-        if constexpr (MODE == kModePair) {
+        if constexpr (PAIR) {
+            const long long tt = j - p.j0;
             // an isolated endpoint leaves the pair unreachable
             if (g.rp[target + 1] == g.rp[target] || g.rp[src + 1] == g.rp[src]) {
-                if (tid == 0 && p.p_len) p.p_len[task] = -1;
+                if (tid == 0 && p.p_len) p.p_len[tt] = -1;
                 if (tid == 0) {
                     c.tasks++;
                     atomicAdd(&p.st->stat[kStDone], 1ULL);
@@ -1744,10 +1834,28 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
                 continue;
             }
             phase_start<BLOCK>(sm);
-            bidir_sample<BLOCK>(p, sm, bs, rec, s, s2, g, src, target, j, task, c);
+            // work counters count finished samples only (a deferred one is
+            // counted by the launch that runs it)
+            const Counters c0 = c;
+            if constexpr (MODE == kModePairHash) {
+                const HashRecs hr{rec, (1u << p.ph_log2) - 1u, 32 - p.ph_log2};
+                bidir_sample<BLOCK>(p, sm, bs, hr, s, s2, g, src, target, j, tt,
+                                    (int32_t)min<long long>(p.stride, g.n), c);
+            } else {
+                bidir_sample<BLOCK>(p, sm, bs, DirectRecs{rec}, s, s2, g, src, target, j, tt, g.n, c);
+            }
+            if (bs.result == -4) c = c0;
             if (tid == 0) {
-                c.tasks++;
-                atomicAdd(&p.st->stat[kStDone], 1ULL);
+                if (bs.result == -4) {
+                    // too many vertices for the table: a later launch with one
+                    // record per vertex runs this sample
+                    const unsigned long long q = atomicAdd(p.defer_count, 1ULL);
+                    p.defer[q] = tt;
+                    atomicAdd(&p.st->stat[kStDeferred], 1ULL);
+                } else {
+                    c.tasks++;
+                    atomicAdd(&p.st->stat[kStDone], 1ULL);
+                }
             }
             phase_end<BLOCK>(sm, kPhTd);
             continue;
@@ -1881,6 +1989,7 @@ KernelRef brandes_kernel(int mode, int block, bool bitmap_in_lds) {
         case kModeBC: return ref_mode<kModeBC>(block, bitmap_in_lds);
         case kModeSSSP: return ref_mode<kModeSSSP>(block, bitmap_in_lds);
         case kModePair: return ref_mode<kModePair>(block, bitmap_in_lds);
+        case kModePairHash: return ref_mode<kModePairHash>(block, bitmap_in_lds);
         case kModeClose: return ref_mode<kModeClose>(block, bitmap_in_lds);
         case kModeBisect: return ref_mode<kModeBisect>(block, bitmap_in_lds);
         case kModeWeighted: return ref_mode<kModeWeighted>(block, bitmap_in_lds);
@@ -2019,8 +2128,8 @@ __global__ void k_pair_rec_init(PairRec *rec, long long count) {
         rec[i].sig[1] = 0ULL;
         rec[i].d[0] = -1;
         rec[i].d[1] = -1;
-        rec[i].pad[0] = 0;
-        rec[i].pad[1] = 0;
+        rec[i].key = 0;
+        rec[i].pad = 0;
     }
 }
 

@@ -110,9 +110,11 @@ def test_chunglu4m_sampled_pairs_bit_exact(chunglu4m):
 
 def test_chunglu4m_full_sample_bit_exact(chunglu4m):
     """The benchmark call itself (eps 0.01, delta 0.1, seed 3: r = 31,513
-    samples on 512 slots of 256 threads), twice, so the second call runs on
-    the per-vertex records the first left (reused without a fill): all
-    counts identical to the oracle's over the whole sample."""
+    samples on 512 slots of 256 threads with one record per vertex), twice,
+    so the second call runs on the per-vertex records the first left (reused
+    without a fill); then with hashed records per slot (the samples that
+    could outgrow them rerun with one record per vertex): all counts
+    identical to the oracle's over the whole sample."""
     g, rp, ci = chunglu4m
     nk.nk_set_tuning()
     _, cnt0, r, vd = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
@@ -121,6 +123,12 @@ def test_chunglu4m_full_sample_bit_exact(chunglu4m):
     assert np.array_equal(cnt0.cpu().numpy().view(np.uint32), ref)
     _, cnt1, r1, _ = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
     assert r1 == r and np.array_equal(cnt1.cpu().numpy().view(np.uint32), ref)
+    nk.nk_set_tuning(flags=64)
+    try:
+        _, cnt2, r2, _ = nk.nk_bc_pair_sample(rp, ci, 0.01, 0.1, 3)
+    finally:
+        nk.nk_set_tuning()
+    assert r2 == r and np.array_equal(cnt2.cpu().numpy().view(np.uint32), ref)
 
 
 def test_batched_with_50k_vertex_graphs():
