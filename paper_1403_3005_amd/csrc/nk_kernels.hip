@@ -1432,12 +1432,15 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
 // the block together (the same choice as the oracle's walk: at w, step t,
 // r = bounded(draw(seed, stream, j, t), sigma[w]) and the first neighbour
 // in adjacency order one level closer to the root whose running sigma sum
-// exceeds r).  Each iteration covers BLOCK arcs of w: a wave scan per 64
-// arcs, the wave totals in LDS, and the first wave whose running sum
-// crosses r names the vertex.  A vertex one level from the root has the
-// root as its only predecessor.  Thread 0 calls emit(i, vertex) for step
-// i = 1, 2, ..., the root included.  Returns false if no predecessor is
-// found (only after a reported overflow).
+// exceeds r).  Each iteration covers kWalkArcs * BLOCK consecutive arcs of
+// w, kWalkArcs per thread in order: per-thread sums, a wave scan, the wave
+// totals in LDS; the first thread whose running sum crosses r finds the
+// arc among its own.  A vertex one level from the root has the root as its
+// only predecessor.  Thread 0 calls emit(i, vertex) for step i = 1, 2, ...,
+// the root included.  Returns false if no predecessor is found (only after
+// a reported overflow).
+constexpr int kWalkArcs = 4;
+
 template <int BLOCK, class Recs, typename Emit>
 __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, const GView &g, int32_t from,
                            int32_t rootv, unsigned long long stream, long long j, Emit emit) {
@@ -1457,16 +1460,24 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
         const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         unsigned long long carry = 0ULL;
         int32_t pick = -1;
-        for (int32_t base = a0; base < a1; base += BLOCK) {
-            const int32_t e = base + tid;
-            int32_t pp = -1;
-            unsigned long long sp = 0ULL;
-            if (e < a1) {
-                pp = g.ci[e];
-                const PairRec *ep = R.find(pp);
-                if (ep && ep->d[X] == dx - 1) sp = ep->sig[X];
+        for (int32_t base = a0; base < a1; base += BLOCK * kWalkArcs) {
+            const int32_t e0 = base + tid * kWalkArcs;
+            int32_t pp[kWalkArcs];
+            unsigned long long sp[kWalkArcs];
+#pragma unroll
+            for (int q = 0; q < kWalkArcs; ++q) pp[q] = e0 + q < a1 ? g.ci[e0 + q] : -1;
+#pragma unroll
+            for (int q = 0; q < kWalkArcs; ++q) {
+                sp[q] = 0ULL;
+                if (pp[q] >= 0) {
+                    const PairRec *ep = R.find(pp[q]);
+                    if (ep && ep->d[X] == dx - 1) sp[q] = ep->sig[X];
+                }
             }
-            const unsigned long long incl = wave_incl_scan<unsigned long long>(sp);
+            unsigned long long tsum = 0ULL;
+#pragma unroll
+            for (int q = 0; q < kWalkArcs; ++q) tsum += sp[q];
+            const unsigned long long incl = wave_incl_scan<unsigned long long>(tsum);
             if (lane == kWave - 1) bs.part_lo[wid] = incl;
             if (tid == 0) bs.pickw = NW;
             __syncthreads();
@@ -1477,14 +1488,22 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
                 if (w < wid) before += ws;
                 total += ws;
             }
-            const unsigned long long mask = __ballot(e < a1 && before + incl > r);
+            // running sums are non-decreasing: the first thread whose
+            // inclusive sum passes r holds the chosen arc
+            const unsigned long long mask = __ballot(before + incl > r);
             if (lane == 0 && mask) atomicMin(&bs.pickw, wid);
             __syncthreads();
             const int pw = bs.pickw;
             if (pw < NW) {
-                if (wid == pw) {
-                    const int32_t chosen = __shfl(pp, __ffsll((long long)mask) - 1, kWave);
-                    if (lane == 0) bs.pickv = chosen;
+                if (wid == pw && lane == __ffsll((long long)mask) - 1) {
+                    unsigned long long run = before + incl - tsum;
+                    int32_t chosen = -1;
+#pragma unroll
+                    for (int q = 0; q < kWalkArcs; ++q) {
+                        run += sp[q];
+                        if (chosen < 0 && run > r) chosen = pp[q];
+                    }
+                    bs.pickv = chosen;
                 }
                 __syncthreads();
                 pick = bs.pickv;
@@ -1693,15 +1712,24 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
 
     // ---- reset the records of every listed vertex (both sides); hashed
     // records also free their entries (no probe runs any more)
+    // (four list entries per thread at a time, their loads issued together)
     for (int k = 0; k < 2; ++k) {
         const Scr &x = k == 0 ? sa : sb;
-        for (int32_t i = tid; i < bs.hi[k]; i += BLOCK) {
-            PairRec &rc = *R.listed(x, i);
-            rc.sig[0] = 0ULL;
-            rc.sig[1] = 0ULL;
-            rc.d[0] = -1;
-            rc.d[1] = -1;
-            if (Recs::kHashed) rc.key = 0;
+        const int32_t hk = bs.hi[k];
+        for (int32_t i0 = tid; i0 < hk; i0 += 4 * BLOCK) {
+            PairRec *rc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rc[q] = i0 + q * BLOCK < hk ? R.listed(x, i0 + q * BLOCK) : nullptr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (rc[q]) {
+                    rc[q]->sig[0] = 0ULL;
+                    rc[q]->sig[1] = 0ULL;
+                    rc[q]->d[0] = -1;
+                    rc[q]->d[1] = -1;
+                    if (Recs::kHashed) rc[q]->key = 0;
+                }
+            }
         }
     }
     __syncthreads();
