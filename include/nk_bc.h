@@ -457,7 +457,7 @@ nk_status nk_last_stats(int64_t *out);
  *              the samples that could fill more than half of it again with
  *              one record per vertex -- which it does by itself when records
  *              per vertex (68 bytes per vertex per slot) would leave fewer
- *              than two slots per compute unit in half the device memory;
+ *              slots than compute units in half the device memory;
  *   bw_ratio   in the dependency sweep, handle level l by pushing from level
  *              l+1 when the arcs of level l+1 are below bw_ratio x the arcs
  *              of level l (0 = always pull; default 0.1);

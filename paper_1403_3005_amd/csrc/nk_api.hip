@@ -1475,8 +1475,8 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
         if ((st = scr.get(n, &cnt)) != NK_OK) return st;
         NK_HIP(launch_fill_u32(cnt, 0u, n, s));
     }
-    // Records: one per vertex per slot, unless that leaves fewer than two
-    // slots per compute unit (68 bytes per vertex per slot against half the
+    // Records: one per vertex per slot, unless memory leaves fewer slots
+    // than compute units (68 bytes per vertex per slot against half the
     // device memory) -- then each slot keeps a hash table of the vertices
     // its sample reaches (n / 16 entries rounded up to a power of two, in
     // [2^14, 2^18]; a sample lists a few thousand), and samples that could
@@ -1492,7 +1492,7 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     if ((st = plan_launch(kModePair, n, count, 0, &plan)) != NK_OK && st != NK_E_NO_MEMORY) return st;
     DevInfo di;
     if (dev_info(&di) != NK_OK) return NK_E_HIP;
-    const bool short_of_slots = st == NK_E_NO_MEMORY || (plan.grid < 2LL * di.cus && plan.grid < count);
+    const bool short_of_slots = st == NK_E_NO_MEMORY || (plan.grid < (long long)di.cus && plan.grid < count);
     clear_error();
     const bool hashed = !(tflags & 32) && (long long)n > 4 * hcap && ((tflags & 64) || short_of_slots);
     if (hashed && (st = plan_launch(kModePairHash, (int32_t)(hcap - 2), count, 0, &plan)) != NK_OK) return st;
