@@ -198,21 +198,28 @@ def per_source_kernel(g, sources, rp, ci, label: str) -> dict:
     dev = rp.device
     bc = torch.empty(g.n, dtype=torch.float64, device=dev)
     one = torch.empty(1, dtype=torch.int32, device=dev)
-    # one untimed call loads the kernel
-    one.fill_(int(sources[0]))
-    nk.nk_bc_sources(rp, ci, one, 1.0, bc=bc)
-    torch.cuda.synchronize()
-    kern_s, byts = 0.0, 0
-    t0 = time.perf_counter()
-    for s_ in sources:
-        one.fill_(int(s_))
+    # one workgroup on one source per launch: the group kernel (which takes
+    # mid-size graphs by itself) is ruled out with tuning flag bit 4
+    saved = nk.nk_get_tuning()
+    nk.nk_set_tuning(**dict(saved, flags=saved["flags"] | 16))
+    try:
+        # one untimed call loads the kernel
+        one.fill_(int(sources[0]))
         nk.nk_bc_sources(rp, ci, one, 1.0, bc=bc)
-        st = nk.nk_last_stats()
-        assert st["workgroups"] == 1
-        kern_s += st["kernel_us"] * 1e-6
-        byts += alg_bytes(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        kern_s, byts = 0.0, 0
+        t0 = time.perf_counter()
+        for s_ in sources:
+            one.fill_(int(s_))
+            nk.nk_bc_sources(rp, ci, one, 1.0, bc=bc)
+            st = nk.nk_last_stats()
+            assert st["workgroups"] == 1
+            kern_s += st["kernel_us"] * 1e-6
+            byts += alg_bytes(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        nk.nk_set_tuning(**saved)
     k = len(sources)
     return {"graph": label, "sources": k, "launches": k, "workgroups_per_launch": 1,
             "gteps": round(k * g.m_undirected / wall / 1e9, 3),
