@@ -44,6 +44,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNEL = "k_brandes"
+# LDS: 256 compute units x 128 bytes per clock x 2.4 GHz
+PEAK_LDS_GBS = 256 * 128 * 2.4
 # nk_last_stats "bitmap_lds" -> which kernel ran
 PLACEMENT = {0: "k_brandes (global bitmap)", 1: "k_brandes (LDS bitmap)", 2: "k_brandes_lds (all in LDS)",
              3: "k_brandes_lds + k_brandes (LDS bitmap)", 4: "k_brandes_ms (multi-source)",
@@ -491,11 +493,19 @@ def other_workload(args) -> dict:
         t0 = time.perf_counter()
         oracle.bc_exact(g.rowptr, g.colidx)
         cpu = time.perf_counter() - t0
+        # the whole graph and every per-source array sit in LDS: the sweep's
+        # bytes (the same per-unit model as the HBM kernels) move through LDS
+        alg = alg_bytes(st)
+        kern_s = st["kernel_us"] * 1e-6
         rec.update(metric="GTEPS, exact Brandes, all sources", unit="GTEPS", dtype="f64",
                    value=round(g.n * g.m_undirected / sec / 1e9, 3), ms_per_step=round(sec * 1e3, 3),
                    config={"workload": "er2000_exact", "n": g.n, "arcs": g.m, "kernel_ms": st["kernel_us"] / 1e3,
                            "kernel": PLACEMENT[st["bitmap_lds"]], "block": st["block"],
-                           "workgroups": st["workgroups"]},
+                           "workgroups": st["workgroups"], "reached": st["reached"],
+                           "arcs_reached": st["arcs_reached"], "dag_arcs": st["dag_arcs"]},
+                   roofline={"bound": "lds", "achieved": round(alg / kern_s / 1e9, 1), "peak": PEAK_LDS_GBS,
+                             "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / PEAK_LDS_GBS, 4), "traffic": None,
+                             "kernel": "k_brandes_lds", "algorithmic_bytes_per_launch": alg},
                    cpu_baseline={"value": round(g.n * g.m_undirected / cpu / 1e9, 4), "unit": "GTEPS", "cores": 1,
                                  "kind": "oracle", "sample": f"all 2000 sources, {cpu:.2f} s"})
     elif args.workload == "chunglu4m":
