@@ -336,7 +336,9 @@ nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t 
  * Exact betweenness of G independent graphs (the paper's recommended use on
  * large batches of smaller networks): one persistent launch of the
  * all-in-LDS kernel for the graphs that fit one workgroup's LDS, one of the
- * global-memory kernel for the rest, each draining (graph, source) tasks.
+ * global-memory kernel for the rest, and one of the group kernel for the
+ * sparse graphs of 10^5 to 3 * 10^5 vertices (see nk_tuning flags bits 3
+ * and 4), each draining (graph, source) tasks, largest graphs first.
  *   vtx_off  HOST int64[G+1]: graph g has vertices vtx_off[g] .. vtx_off[g+1]-1
  *            of the concatenated vertex space;
  *   arc_off  HOST int64[G+1]: its arcs are colidx_cat[arc_off[g] .. arc_off[g+1]);
