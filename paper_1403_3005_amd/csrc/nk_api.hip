@@ -610,6 +610,7 @@ nk_status plan_group(int32_t n_max, GroupPlan *gp) {
     if (gsz > per_xcd) gsz = per_xcd;
     gp->gpx = std::max(1, per_xcd / gsz);
     gp->groups = nxcc * gp->gpx;
+    gp->nxcc = nxcc;
     gp->stride = (((long long)n_max + 2) + 63) / 64 * 64;
     gp->timeout = (long long)rate_khz * 1000LL * 20LL;   // 20 s
     gp->lp.mode = kModeBC;
@@ -648,6 +649,7 @@ nk_status group_alloc(const GroupPlan &gp, Params &p, Scratch &scr) {
     p.stride = gp.stride;
     p.xg_gpx = gp.gpx;
     p.xg_groups = gp.groups;
+    p.xg_nxcc = gp.nxcc;
     p.xg_timeout = gp.timeout;
     p.bu_ratio = tuning_get().bu_ratio;
     p.bw_ratio = tuning_get().bw_ratio;

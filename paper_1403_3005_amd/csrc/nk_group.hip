@@ -263,16 +263,21 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        int32_t xd = 0;
-        for (int32_t i = 0; i < x; ++i) xd += ldg_u32(&reg[i]) > 0u ? 1 : 0;
+        int32_t xd = 0, distinct = 0;
+        for (int32_t i = 0; i < 16; ++i) {
+            const bool used = ldg_u32(&reg[i]) > 0u;
+            if (i < x) xd += used ? 1 : 0;
+            distinct += used ? 1 : 0;
+        }
         const int32_t cnt = (int32_t)ldg_u32(&reg[x]);
         const int32_t gpx = p.xg_gpx;
         const int32_t sub = r % gpx;
         gs.group = xd * gpx + sub;
         gs.rank = r / gpx;
         gs.gsize = (cnt - sub + gpx - 1) / gpx;
-        // (candidate segments are sized for at most 64 members)
-        if (gs.group >= p.xg_groups || gs.gsize > 64) {
+        // (candidate segments are sized for at most 64 members; a group must
+        // not span XCDs, so every XCD the device has must report its own id)
+        if (gs.group >= p.xg_groups || gs.gsize > 64 || distinct != p.xg_nxcc) {
             atomicOr(&p.st->err, kErrInternal);
             gs.flag = 0;
         }

@@ -143,6 +143,8 @@ struct Params {
     // wall-clock ticks
     int32_t xg_gpx;
     int32_t xg_groups;
+    int32_t xg_nxcc;           // XCDs of the device (each must hold workgroups of the launch)
+    int32_t pad4;
     void *xg_ctl;
     unsigned int *xg_reg;
     long long xg_timeout;

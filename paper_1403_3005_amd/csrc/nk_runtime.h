@@ -145,6 +145,7 @@ struct GroupPlan {
     LaunchPlan lp;
     int gpx;               // groups per XCD
     int groups;            // groups allocated (XCDs x gpx)
+    int nxcc;              // XCDs of the device
     long long stride;      // per-group vertex capacity
     long long timeout;     // wall-clock ticks a wait may last
 };
