@@ -4,10 +4,13 @@
 // A source's path counts and coefficients (8 bytes per vertex) are read at
 // random positions once per DAG arc.  When every workgroup runs a source of
 // its own, 32 workgroups of an XCD keep 32 such arrays live against one
-// 4 MB L2, and almost every access leaves the XCD.  Here the workgroups of
-// an XCD form a group that shares one source's arrays, so for graphs up to
-// a few hundred thousand vertices the arrays stay in that XCD's L2 and the
-// random accesses are L2 hits.  The algorithm per source is the same as the
+// 4 MB L2 (and 256 of them against the 256 MB Infinity Cache), and almost
+// every access leaves the XCD.  Here the workgroups of an XCD split into
+// groups of S (a tuning value, 4 by default), each group sharing one
+// source's arrays: S = 32 keeps a graph of a few hundred thousand vertices
+// in the XCD's L2, smaller groups keep all sources in flight within the
+// Infinity Cache while leaving each member enough of a level to overlap
+// its memory round trips.  The algorithm per source is the same as the
 // one-workgroup kernel's (nk_kernels.hip): level-synchronous forward search
 // counting shortest paths (top-down with 64-bit atomics, or bottom-up),
 // then the dependency pull level by level from the deepest (Brandes 2001,
@@ -82,15 +85,11 @@ __device__ __forceinline__ int32_t xcc_id() {
     return (int32_t)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u);
 }
 
-template <int BLOCK>
+// Workgroup-wide scalars (LDS).
 struct GState {
     int32_t group, rank, gsize, flag;
     unsigned long long epoch;       // group barriers passed
     long long task;
-    int32_t src, n, m, nw;
-    long long vbase;
-    double mf, mu;
-    int32_t f0, f1, levels;
     int32_t count;                  // bottom-up candidates of this workgroup
     unsigned long long dsum;        // degree sum of the vertices this workgroup appended this level
 };
@@ -101,8 +100,7 @@ struct GCount {
 
 // Group barrier.  Contains block barriers: every thread calls it.  Returns
 // false when the group has aborted.
-template <int BLOCK>
-__device__ bool group_sync(GState<BLOCK> &gs, GroupCtl *ctl, const Params &p) {
+__device__ bool group_sync(GState &gs, GroupCtl *ctl, const Params &p) {
     // this wave's stores and atomics have reached L2
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -241,7 +239,7 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(Params p) {
     extern __shared__ uint32_t lbm[];     // visited bitmap of the current source
     __shared__ Tile<BLOCK> sm;
-    __shared__ GState<BLOCK> gs;
+    __shared__ GState gs;
     const int tid = threadIdx.x;
     GroupCtl *ctls = reinterpret_cast<GroupCtl *>(p.xg_ctl);
     unsigned int *reg = p.xg_reg;   // [0, 16): workgroups per XCC id; [16]: total
@@ -302,7 +300,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
             const long long t = (long long)atomicAdd(&p.st->head, 1ULL);
             ctl->task[it & 1].v = (unsigned long long)t;
         }
-        if (!group_sync<BLOCK>(gs, ctl, p)) break;
+        if (!group_sync(gs, ctl, p)) break;
         if (tid == 0) gs.task = (long long)ldg_u64(&ctl->task[it & 1].v);
         __syncthreads();
         const long long task = gs.task;
@@ -371,7 +369,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
         int32_t f0 = 0, f1 = 1;
         if (lead && tid == 0) c.arcs_reached += (unsigned long long)d_src;
         // sigma[src] and the source entry are visible to the group
-        if (!group_sync<BLOCK>(gs, ctl, p)) break;
+        if (!group_sync(gs, ctl, p)) break;
 
         // ------------------------------------------------------- forward --
         int32_t d = 0;
@@ -515,7 +513,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
             }
             __syncthreads();
             if (tid == 0 && gs.dsum) atomicAdd(&acc->w, gs.dsum);
-            if (!group_sync<BLOCK>(gs, ctl, p)) {
+            if (!group_sync(gs, ctl, p)) {
                 ok = false;
                 break;
             }
@@ -561,7 +559,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
                 const int32_t w = ldg_i32(lv + i);
                 atomicAnd(&lbm[w >> 5], ~(1u << (w & 31)));
             }
-            if (!group_sync<BLOCK>(gs, ctl, p)) break;
+            if (!group_sync(gs, ctl, p)) break;
             for (int32_t l = Ld - 1; l >= 1; --l) {
                 const int32_t lo = ldg_i32(lvl + l), hi = ldg_i32(lvl + l + 1);
                 const double wfac = p.linear ? (double)l / (double)(l + 1) : 1.0;
@@ -612,7 +610,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_brandes_group(P
                     atomicAnd(&lbm[w >> 5], ~(1u << (w & 31)));
                 }
                 // level l's coefficients are visible before level l - 1 pulls
-                if (!group_sync<BLOCK>(gs, ctl, p)) {
+                if (!group_sync(gs, ctl, p)) {
                     ok = false;
                     break;
                 }
