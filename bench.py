@@ -12,8 +12,9 @@ The same JSON line also carries:
   batched          exact betweenness of the 512-graph batch (n log-uniform
                    in [1e3, 2e5], even graphs Erdos-Renyi m = 4n, odd ones
                    Barabasi-Albert m0 = 4, seed 4) as ONE captured launch of
-                   the whole batch, progress read from the device while it
-                   runs; one timed pass;
+                   the whole batch (all-in-LDS, one-source and XCD-group
+                   kernels by graph size), progress read from the device
+                   while it runs; one timed pass;
   pair_sampling    Riondato-Kornaropoulos pair sampling on the Chung-Lu graph
                    (n = 4e6, exponent 2.5, mean degree 20, seed 3), eps 0.01,
                    delta 0.1;
@@ -23,11 +24,14 @@ The same JSON line also carries:
   serving          a short Poisson request stream through the server;
   cpu_baseline     the CPU oracle on a bounded sample, on this GPU's share
                    of the host's cores, with the host's CPU model.
+The headline step runs under the autotuner's choice for its graph; every
+other record under the library's default tuning.
 
 Prints one JSON line.  GTEPS = sources x undirected edges / time / 1e9.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-batched] [--no-pairs] [--no-serving]
+                  [--no-batched] [--no-pairs] [--no-serving] [--no-per-source]
+  python bench.py --workload {er2000,chunglu4m,batched512,er200k,serving,...}
 """
 from __future__ import annotations
 
