@@ -245,3 +245,30 @@ def test_batch_three_way_split():
         again = plan.run().cpu().numpy()
         assert nk.nk_last_stats()["bitmap_lds"] == 7
         assert_scores_close(again, got, "replay")
+
+
+def test_cached_kernel_choice(tmp_path):
+    """A registered autotuner cache entry carries the kernel choice: an
+    eight-value entry with flag bit 3 runs a graph of its shape on the group
+    kernel, one with bit 4 keeps the same graph on the one-source kernel,
+    whatever the automatic choice would be; scores agree with the oracle."""
+    import json
+
+    g = gg.erdos_renyi(60_000, 240_000, 79)          # below the automatic range
+    src = gg.sample_sources(g.n, 48, 80)
+    rp, ci = upload(g)
+    ref = oracle.bc_sources(g.rowptr, g.colidx, src, 1.0, nthreads=16)
+    deg = g.degrees()
+    mean = g.m / g.n
+    key = "n%d_d%d_s%d" % (int(np.floor(np.log2(g.n))), int(np.round(np.log2(mean))),
+                           int(np.round(np.log2(deg.max() / mean))))
+    cache = tmp_path / "tune.json"
+    try:
+        for kflags, where in ((8, 6), (16, 1)):
+            cache.write_text(json.dumps({key: [1024, 16, 0.1, 0, 1, 10.0, kflags, 2]}))
+            nk.nk_set_tuning_cache(str(cache))
+            got = nk.nk_bc_sources(rp, ci, ivec(src), 1.0).cpu().numpy()
+            assert nk.nk_last_stats()["bitmap_lds"] == where, kflags
+            assert_scores_close(got, ref, f"cached flags {kflags}")
+    finally:
+        nk.nk_set_tuning_cache(None)
