@@ -73,7 +73,7 @@ struct PoolBlock {
     size_t bytes;
     int device;
     bool busy;
-    int tag;    // meaning of the contents kept across calls (0 = none)
+    uint64_t tag;   // meaning of the contents kept across calls (0 = none)
 };
 static std::mutex g_pool_mu;
 static std::vector<PoolBlock> g_pool;
@@ -131,7 +131,7 @@ nk_status Scratch::get(size_t bytes, void **out) {
     return NK_OK;
 }
 
-nk_status Scratch::get_tagged(size_t bytes, int tag, void **out, bool *clean, size_t *block_bytes) {
+nk_status Scratch::get_tagged(size_t bytes, uint64_t tag, void **out, bool *clean, size_t *block_bytes) {
     int dev = 0;
     NK_HIP(hipGetDevice(&dev));
     const size_t need = (bytes + 255) & ~(size_t)255;
@@ -166,7 +166,7 @@ nk_status Scratch::get_tagged(size_t bytes, int tag, void **out, bool *clean, si
     return NK_OK;
 }
 
-void Scratch::mark(void *p, int tag) {
+void Scratch::mark(void *p, uint64_t tag) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &b : g_pool)
         if (b.ptr == p) b.tag = tag;
@@ -692,7 +692,7 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
     p.d = nullptr;
     p.lvl = nullptr;
     p.bmg = nullptr;
-    p.pair_rec = nullptr;
+    p.pair_rec = p.pair_blk = nullptr;
     p.lv2 = p.la2 = p.ld2 = nullptr;
     p.dist = nullptr;
     p.mark = nullptr;
@@ -706,21 +706,34 @@ nk_status persistent_alloc(const LaunchPlan &plan, Params &p, Scratch &scr, hipS
     if ((st = scr.get(cells, &p.ld)) != NK_OK) return st;
     if ((st = scr.get(cells, &p.cand)) != NK_OK) return st;
     if (pair) {
-        // 32-byte records of both search sides (every sample resets the
-        // records it touched, so a block left by a successful pair launch is
-        // still all-unreached and needs no fill), the target side's lists
+        // 32-byte records of both search sides, the target side's lists.
+        // Every sample resets the records it touched, so a block left by a
+        // successful pair launch is still all-unreached and needs no fill;
+        // one record per vertex also holds the vertex's degree, refreshed
+        // on the device when the graph's row pointers differ from the ones
+        // the block was filled from (tables hold no degree).
+        const bool hashed = plan.mode == kModePairHash;
+        const long long head = hashed ? 0 : pair_block_head_bytes(plan.stride);
         bool clean = false;
-        size_t rec_bytes = 0;
-        if ((st = scr.get_tagged((size_t)cells * 32, kTagPairRecords, &p.pair_rec, &clean, &rec_bytes)) != NK_OK)
+        size_t blk_bytes = 0;
+        void *blk = nullptr;
+        if ((st = scr.get_tagged((size_t)cells * 32 + (size_t)head, pair_block_tag(plan), &blk, &clean,
+                                 &blk_bytes)) != NK_OK)
             return st;
+        p.pair_blk = blk;
+        p.pair_rec = static_cast<char *>(blk) + head;
         if ((st = scr.get(cells, &p.lv2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.la2)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ld2)) != NK_OK) return st;
-        if (plan.mode == kModePairHash) {
+        if (hashed) {
             if ((st = scr.get(cells, &p.ls)) != NK_OK) return st;
             if ((st = scr.get(cells, &p.ls2)) != NK_OK) return st;
+            if (!clean) NK_HIP(launch_pair_table_init(blk, (long long)(blk_bytes / 32), s));
+        } else if (clean) {
+            NK_HIP(launch_pair_block_refresh(blk, blk_bytes, plan.stride, p.rowptr, p.n, s));
+        } else {
+            NK_HIP(launch_pair_block_init(blk, blk_bytes, plan.stride, p.rowptr, p.n, s));
         }
-        if (!clean) NK_HIP(launch_pair_rec_init(p.pair_rec, (long long)(rec_bytes / 32), s));
     } else {
         if ((st = scr.get(cells, &p.sigma)) != NK_OK) return st;
         if ((st = scr.get(cells, &p.ldeg)) != NK_OK) return st;
@@ -1527,7 +1540,7 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
         p.defer_count = dcount;
     }
     if ((st = launch_persistent(plan, p, scr, s, ev0, hashed ? nullptr : ev1)) != NK_OK) return st;
-    plan.pair_rec = p.pair_rec;
+    plan.pair_rec = p.pair_blk;
     if (hashed) {
         unsigned long long nd = 0;
         NK_HIP(hipMemcpyAsync(&nd, dcount, sizeof(nd), hipMemcpyDeviceToHost, s));
@@ -1578,7 +1591,7 @@ nk_status nk_pair_counts(const int32_t *rowptr, const int32_t *colidx, int32_t n
                            ev0, ev1)) != NK_OK)
             return st;
         st = finish(dst, h, s);
-        if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
+        if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, pair_block_tag(plan));
         NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     } else {
         st = finish(dst, h, s);
@@ -1629,7 +1642,7 @@ nk_status nk_bc_pair_sample(const int32_t *rowptr, const int32_t *colidx, int32_
     const double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
     NK_HIP(launch_counts_to_bc(cnt, bc, scale, n, s));
     st = finish(dst, h, s);
-    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
+    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, pair_block_tag(plan));
     if (r > 0) NK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     stats_record(*h, plan.grid, plan.block, plan.lds, ms);
     return st;
@@ -1659,7 +1672,7 @@ nk_status nk_sample_paths(const int32_t *rowptr, const int32_t *colidx, int32_t 
                        dst, scr, s, &plan, nullptr, nullptr)) != NK_OK)
         return st;
     st = finish(dst, h, s);
-    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, kTagPairRecords);
+    if (st == NK_OK && plan.pair_rec) scr.mark(plan.pair_rec, pair_block_tag(plan));
     stats_record(*h, plan.grid, plan.block, plan.lds, 0.0f);
     return st;
 }

@@ -112,9 +112,12 @@ struct Params {
     uint32_t *dagm;            // per-slot bitmap over the arcs: shortest-path DAG arcs of
     long long dag_words;       // the current source (all clear between sources); words per slot
     // pair mode: 32-byte per-vertex records of both search sides (path
-    // counts and distances from u and from v; `stride` records per slot)
-    // and the level lists of the side grown from the target
+    // counts and distances from u and from v, and, one record per vertex,
+    // the vertex's degree; `stride` records per slot) and the level lists
+    // of the side grown from the target; pair_blk is the pooled block that
+    // holds the records (host side only)
     void *pair_rec;
+    void *pair_blk;
     int32_t *lv2;
     int32_t *la2;
     int32_t *ld2;
@@ -210,9 +213,27 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, long lon
 hipError_t launch_scale_f64(double *p, double scale, long long count, hipStream_t s);
 hipError_t launch_counts_to_bc(const uint32_t *counts, double *bc, double scale, long long count, hipStream_t s);
 hipError_t launch_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long long *key, hipStream_t s);
+// Pair-mode record block, one record per vertex per slot: a 256-byte head
+// (int32 [0] = n of the row pointers kept, [1] = stale flag), the row
+// pointers the degree fields were filled from (stride + 1 entries, padded
+// to 256 bytes), then the records of every whole slot that fits.
+__host__ __device__ inline long long pair_block_head_bytes(long long stride) {
+    return 256 + ((stride + 1) * 4 + 255) / 256 * 256;
+}
+// Prepares a record block of `bytes` bytes for the graph rowptr (n
+// vertices): every record of every whole slot unreached (path counts 0,
+// distances -1) with its vertex's degree (0 past n), rowptr[0..n] kept.
+hipError_t launch_pair_block_init(void *blk, size_t bytes, long long stride, const int32_t *rowptr, int32_t n,
+                                  hipStream_t s);
+// A block last prepared (or refreshed) for some graph with this stride:
+// if the kept row pointers differ from rowptr[0..n], rewrites every
+// record's degree field and the kept row pointers (the records stay
+// unreached).  Three launches; no host synchronisation.
+hipError_t launch_pair_block_refresh(void *blk, size_t bytes, long long stride, const int32_t *rowptr, int32_t n,
+                                     hipStream_t s);
+// Hashed pair mode: every table entry free and unreached.
+hipError_t launch_pair_table_init(void *rec, long long count, hipStream_t s);
 // Sampled closeness: out[o] = (n-1) / (n/k * acc[perm[o]]) (0 where acc = 0).
-// Pair mode: every record unreached (path counts 0, distances -1).
-hipError_t launch_pair_rec_init(void *rec, long long count, hipStream_t s);
 hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,
                                hipStream_t s);
 // Degree-descending relabelling of a single graph (nk_relabel.hip).

@@ -1365,8 +1365,13 @@ struct HashRecs {
 // Top-down growth of side X by one level (list[f0, f1) at distance dep)
 // into list[f1, ...): every arc y -> z with z not reached by X before this
 // level adds sigma_X(y) to sigma_X(z).  The first adder appends z with its
-// first arc and degree, adds the degree to *newcost, and, when the other
-// side has reached z, appends z to the meeting list (meet, *nm).
+// degree, adds the degree to *newcost, and, when the other side has reached
+// z, appends z to the meeting list (meet, *nm).  One record per vertex
+// holds the degree, so a reached vertex costs its record's line only; its
+// arc range is read when (if ever) its level is expanded.  Hash-table
+// entries hold no degree: the row pointers give it, and the arc range is
+// listed with the vertex.  Side 1 - X does not change during the level, so its
+// distance is read with side X's.
 template <int BLOCK, class Recs>
 __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int X, const Scr &s, const GView &g,
                            int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
@@ -1376,7 +1381,8 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
         if (tid < cnt) sm.val.u[tid] = R.listed(s, tb + tid)->sig[X];
-        const int32_t total = stage_list<BLOCK>(sm, s, tb, cnt);
+        const int32_t total =
+            Recs::kHashed ? stage_list<BLOCK>(sm, s, tb, cnt) : stage_ids<BLOCK>(sm, s.lv, g, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
@@ -1385,12 +1391,17 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
             bool act[kChunk];
             unsigned long long add[kChunk], old[kChunk];
             PairRec *e[kChunk];
+            int32_t dother[kChunk], deg[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
                 e[j] = kk[j] >= 0 ? R.claim(w[j]) : nullptr;
                 if (Recs::kHashed && kk[j] >= 0 && !e[j]) *full = 1;
+                // d[0], d[1] and the degree (one record per vertex) in one load
+                const int4 q = e[j] ? *reinterpret_cast<const int4 *>(e[j]->d) : make_int4(0, 0, 0, 0);
+                const int32_t dz = X == 0 ? q.x : q.y;
+                dother[j] = X == 0 ? q.y : q.x;
+                deg[j] = q.z;
                 // unreached, or reached on this very level by another adder
-                const int32_t dz = e[j] ? e[j]->d[X] : 0;
                 act[j] = e[j] != nullptr && (dz < 0 || dz == dep + 1);
                 add[j] = act[j] ? sm.val.u[kk[j]] : 0ULL;
             }
@@ -1407,16 +1418,20 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
                 }
                 if (fresh) {
                     e[j]->d[X] = dep + 1;
-                    a0 = g.rp[w[j]];
-                    dg = g.rp[w[j] + 1] - a0;
-                    met = e[j]->d[1 - X] >= 0;
+                    if (Recs::kHashed) {
+                        a0 = g.rp[w[j]];
+                        dg = g.rp[w[j] + 1] - a0;
+                    } else {
+                        dg = deg[j];
+                    }
+                    met = dother[j] >= 0;
                     dsum += (unsigned long long)dg;
                 }
                 const int32_t pos = wave_append_pos(fresh, w[j], s.lv + f1, &sm.count, lcap - f1, &p.st->err);
-                if (pos >= 0) {
+                if (Recs::kHashed && pos >= 0) {
                     s.la[f1 + pos] = a0;
                     s.ld[f1 + pos] = dg;
-                    if (Recs::kHashed) s.ls[f1 + pos] = R.slot(e[j]);
+                    s.ls[f1 + pos] = R.slot(e[j]);
                 }
                 // meeting vertices: new on side X and already reached by the other side
                 wave_append(met, w[j], meet, nm, lcap, &p.st->err);
@@ -2149,7 +2164,7 @@ __global__ void k_argmax_degree(const int32_t *rowptr, int32_t n, unsigned long 
     }
 }
 
-__global__ void k_pair_rec_init(PairRec *rec, long long count) {
+__global__ void k_pair_table_init(PairRec *rec, long long count) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         rec[i].sig[0] = 0ULL;
@@ -2159,6 +2174,54 @@ __global__ void k_pair_rec_init(PairRec *rec, long long count) {
         rec[i].key = 0;
         rec[i].pad = 0;
     }
+}
+
+// Record block fill (layout at pair_block_head_bytes): the degree field of
+// every record of `slots` slots, and with `full` the unreached state too;
+// the row pointers rp[0..n] kept at the head.  Without `full` the launch
+// does nothing unless the head was found stale.  Threads walk vertices in
+// x and slots in y, so neighbouring threads write neighbouring records.
+__global__ void k_pair_block_fill(char *blk, long long slots, long long stride, const int32_t *rp, int32_t n,
+                                  int32_t full) {
+    int32_t *head = reinterpret_cast<int32_t *>(blk);
+    if (!full && head[1] == 0) return;
+    int32_t *kept = head + 64;
+    PairRec *rec = reinterpret_cast<PairRec *>(blk + pair_block_head_bytes(stride));
+    const long long step = (long long)gridDim.x * blockDim.x;
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long v = v0; v < stride; v += step) {
+        const int32_t dg = v < n ? rp[v + 1] - rp[v] : 0;
+        for (long long sl = blockIdx.y; sl < slots; sl += gridDim.y) {
+            PairRec *e = rec + sl * stride + v;
+            if (full) {
+                e->sig[0] = 0ULL;
+                e->sig[1] = 0ULL;
+                e->d[0] = -1;
+                e->d[1] = -1;
+                e->pad = 0;
+            }
+            e->key = dg;
+        }
+    }
+    if (blockIdx.y == 0) {
+        for (long long v = v0; v <= n; v += step) kept[v] = rp[v];
+        if (v0 == 0) {
+            head[0] = n;
+            if (full) head[1] = 0;
+        }
+    }
+}
+
+// Sets the head's stale flag (cleared before) when the kept row pointers
+// are not rp[0..n].  The kept array has stride + 1 >= n + 1 entries.
+__global__ void k_pair_block_check(char *blk, const int32_t *rp, int32_t n) {
+    int32_t *head = reinterpret_cast<int32_t *>(blk);
+    const int32_t *kept = head + 64;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    const long long v0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool diff = v0 == 0 && head[0] != n;
+    for (long long v = v0; v <= n; v += step) diff |= kept[v] != rp[v];
+    if (diff) head[1] = 1;
 }
 
 __global__ void k_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k,
@@ -2178,10 +2241,41 @@ static inline unsigned grid_for(long long count, int block) {
     return (unsigned)g;
 }
 
-hipError_t launch_pair_rec_init(void *rec, long long count, hipStream_t s) {
-    hipLaunchKernelGGL(k_pair_rec_init, dim3(grid_for(count, 256)), dim3(256), 0, s, reinterpret_cast<PairRec *>(rec),
-                       count);
+hipError_t launch_pair_table_init(void *rec, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_table_init, dim3(grid_for(count, 256)), dim3(256), 0, s,
+                       reinterpret_cast<PairRec *>(rec), count);
     return hipGetLastError();
+}
+
+// whole slots of a record block of `bytes` bytes
+static long long pair_block_slots(size_t bytes, long long stride) {
+    const long long head = pair_block_head_bytes(stride);
+    return (long long)bytes > head ? ((long long)bytes - head) / (32 * stride) : 0;
+}
+
+static hipError_t launch_pair_block_fill(void *blk, size_t bytes, long long stride, const int32_t *rowptr, int32_t n,
+                                         int32_t full, hipStream_t s) {
+    const long long slots = pair_block_slots(bytes, stride);
+    const unsigned gx = grid_for(stride, 256) < 1024 ? grid_for(stride, 256) : 1024;
+    const unsigned gy = slots < 8 ? (unsigned)(slots > 0 ? slots : 1) : 8;
+    hipLaunchKernelGGL(k_pair_block_fill, dim3(gx, gy), dim3(256), 0, s, reinterpret_cast<char *>(blk), slots, stride,
+                       rowptr, n, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_block_init(void *blk, size_t bytes, long long stride, const int32_t *rowptr, int32_t n,
+                                  hipStream_t s) {
+    return launch_pair_block_fill(blk, bytes, stride, rowptr, n, 1, s);
+}
+
+hipError_t launch_pair_block_refresh(void *blk, size_t bytes, long long stride, const int32_t *rowptr, int32_t n,
+                                     hipStream_t s) {
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t *>(blk) + 1, 0, 1, s);
+    if (e != hipSuccess) return e;
+    const unsigned g = grid_for((long long)n + 1, 256) < 2048 ? grid_for((long long)n + 1, 256) : 2048;
+    hipLaunchKernelGGL(k_pair_block_check, dim3(g), dim3(256), 0, s, reinterpret_cast<char *>(blk), rowptr, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_pair_block_fill(blk, bytes, stride, rowptr, n, 0, s);
 }
 
 hipError_t launch_close_finish(const unsigned long long *acc, const int32_t *perm, int32_t n, int32_t k, double *out,

@@ -33,7 +33,13 @@ nk_status dev_info(DevInfo *out);
 // Pooled device scratch.  Blocks return to the pool when the holder is
 // destroyed; the pool keeps them for later calls until nk_shutdown.
 // Scratch block tags (contents that stay meaningful across calls).
-constexpr int kTagPairRecords = 1;   // pair-mode records, all unreached
+// Pair-mode record blocks: every record unreached, and the degree field of
+// every record of every whole slot filled from the row pointers kept at the
+// block's head, for the record layout of the stride the tag carries.
+constexpr uint64_t kTagPairRecords = 1;
+inline uint64_t pair_records_tag(long long stride) { return kTagPairRecords | ((uint64_t)stride << 8); }
+// Pair-mode hash tables: every entry free and unreached.
+constexpr uint64_t kTagPairTables = 2;
 
 class Scratch {
 public:
@@ -54,8 +60,8 @@ public:
     // whole block's size, which may exceed `bytes`: a caller that marks the
     // block must have prepared all of it.  Any block handed out loses its
     // tag until mark() sets it again.
-    nk_status get_tagged(size_t bytes, int tag, void **out, bool *clean, size_t *block_bytes);
-    void mark(void *p, int tag);
+    nk_status get_tagged(size_t bytes, uint64_t tag, void **out, bool *clean, size_t *block_bytes);
+    void mark(void *p, uint64_t tag);
 
 private:
     std::vector<void *> held_;
@@ -107,6 +113,11 @@ struct LaunchPlan {
     void *pair_rec;   // pair mode: the record block the launch used (set by the caller after the launch)
     long long dag_words;   // weighted mode: per-slot words of the DAG-arc bitmap
 };
+// The tag a pair-mode record block of `plan` carries after a successful
+// launch (records or hash tables, by the plan's mode and stride).
+inline uint64_t pair_block_tag(const LaunchPlan &plan) {
+    return plan.mode == kModePairHash ? kTagPairTables : pair_records_tag(plan.stride);
+}
 
 // Picks block size, bitmap placement and grid for graphs of at most n_max
 // vertices and `ntasks` tasks.  max_slots > 0 caps the grid.  m_arcs: the

@@ -216,7 +216,7 @@ static void start_request(nk_server *sv, Slot &sl, Request *rq) {
             p.iso = g.iso;
             p.st = sl.dst;
             if ((st = launch_persistent(sl.plan, p, scr, s, nullptr, nullptr)) != NK_OK) return bail(st);
-            sl.plan.pair_rec = p.pair_rec;
+            sl.plan.pair_rec = p.pair_blk;
         }
         (void)launch_gather_u32(cnt, g.perm, n, cnt_orig, s);
         const double scale = r > 0 ? (double)n * (double)(n - 1) / (double)r : 0.0;
@@ -239,7 +239,7 @@ static void finish_request(nk_server *sv, Slot &sl) {
     }
     if (rq->status == NK_OK && rq->out) memcpy(rq->out, sl.staging, sizeof(double) * g.n);
     // a successful pair launch leaves its records all unreached
-    if (rq->status == NK_OK && sl.plan.pair_rec) sl.scr->mark(sl.plan.pair_rec, kTagPairRecords);
+    if (rq->status == NK_OK && sl.plan.pair_rec) sl.scr->mark(sl.plan.pair_rec, pair_block_tag(sl.plan));
     sl.plan.pair_rec = nullptr;
     rq->t_done = now_s();
     delete sl.scr;
