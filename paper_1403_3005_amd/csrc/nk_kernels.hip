@@ -1300,13 +1300,15 @@ __device__ void block_sum_u128(unsigned long long x, BiState &bs, unsigned long 
 }
 
 // Pair mode keeps both search sides' state of a vertex in one 32-byte
-// record, so the visited test, the path-count update, the meeting test and
-// the walk's predecessor test each touch one cache line.  d = -1 is
-// unreached; a sample resets the records it touched.
+// record, so the visited test, the path-count update, the meeting test, the
+// side-choice cost and the walk's predecessor test each touch one cache
+// line.  d = -1 is unreached; a sample resets the path counts and distances
+// of the records it touched.
 struct PairRec {
     unsigned long long sig[2];   // path counts from u (side 0) and from v (side 1)
     int32_t d[2];                // distances from u and from v
-    int32_t key;                 // hashed records: vertex + 1 (0 = free entry)
+    int32_t key;                 // one record per vertex: the vertex's degree;
+                                 // hashed records: vertex + 1 (0 = free entry)
     int32_t pad;
 };
 
