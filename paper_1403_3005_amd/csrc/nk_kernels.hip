@@ -1266,6 +1266,9 @@ struct BiState {
     int32_t pad;
     int32_t pickw, pickv;            // block walk: first crossing wave, chosen vertex
     int32_t full;                    // hashed records: a claim found the table full
+    int32_t small[2];                // the path counts of each side's deepest level sum below 2^64
+    int32_t tover;                   // the level being built: its path counts' sum reached 2^64
+    unsigned long long tsum;         // ... and that sum modulo 2^64
     unsigned long long part_lo[16], part_hi[16];
     unsigned long long total, r0;
 };
@@ -1328,6 +1331,7 @@ struct DirectRecs {
     __device__ PairRec *claim(int32_t v) const { return R + v; }
     __device__ int32_t slot(const PairRec *e) const { return (int32_t)(e - R); }
     __device__ PairRec *listed(const Scr &s, int32_t i) const { return R + s.lv[i]; }
+    __device__ PairRec *lookup(int32_t v, int32_t *) const { return R + v; }
 };
 
 struct HashRecs {
@@ -1362,6 +1366,19 @@ struct HashRecs {
     }
     __device__ int32_t slot(const PairRec *e) const { return (int32_t)(e - T); }
     __device__ PairRec *listed(const Scr &s, int32_t i) const { return T + s.ls[i]; }
+    // the entry of v, or NULL when no side has reached v; a probe that gives
+    // up raises *full (the sample is then deferred)
+    __device__ PairRec *lookup(int32_t v, int32_t *full) const {
+        uint32_t h = home(v);
+        for (int i = 0; i < kPairHashProbes; ++i) {
+            const int32_t k = T[h].key;
+            if (k == v + 1) return T + h;
+            if (k == 0) return nullptr;
+            h = (h + 1u) & mask;
+        }
+        *full = 1;
+        return nullptr;
+    }
 };
 
 // Top-down growth of side X by one level (list[f0, f1) at distance dep)
@@ -1375,18 +1392,21 @@ struct HashRecs {
 // listed with the vertex.  Side 1 - X does not change during the level, so its
 // distance is read with side X's.
 template <int BLOCK, class Recs>
-__device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int X, const Scr &s, const GView &g,
-                           int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
-                           unsigned long long *newcost, int32_t lcap, int32_t *full, Counters &c) {
+__device__ void pair_level(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Recs &R, int X, const Scr &s,
+                           const GView &g, int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
+                           unsigned long long *newcost, int32_t lcap, int32_t *full, bool count_arcs, Counters &c) {
     const int tid = threadIdx.x;
     unsigned long long dsum = 0;
+    // sum of the path counts the level adds (= of its vertices' counts)
+    unsigned long long tsum = 0;
+    bool tover = false;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
         if (tid < cnt) sm.val.u[tid] = R.listed(s, tb + tid)->sig[X];
         const int32_t total =
             Recs::kHashed ? stage_list<BLOCK>(sm, s, tb, cnt) : stage_ids<BLOCK>(sm, s.lv, g, tb, cnt);
         __syncthreads();
-        if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+        if (tid == 0 && count_arcs) c.arcs_fwd += (unsigned long long)total;
         for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
             int32_t kk[kChunk], w[kChunk];
             load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
@@ -1417,6 +1437,8 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
                 if (act[j]) {
                     c.dag++;
                     if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                    tsum += add[j];
+                    if (tsum < add[j]) tover = true;
                 }
                 if (fresh) {
                     e[j]->d[X] = dep + 1;
@@ -1443,6 +1465,66 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
     }
     dsum = wave_sum<unsigned long long>(dsum);
     if (lane_id() == 0 && dsum) atomicAdd(newcost, dsum);
+    if (tsum) {
+        const unsigned long long o = atomicAdd(&bs.tsum, tsum);
+        if (o + tsum < o) tover = true;
+    }
+    if (tover) bs.tover = 1;
+}
+
+// The arcs leaving side X's deepest level (list[f0, f1) at distance dep)
+// when the next level may be the last: only vertices the other side has
+// already reached (the meeting set M) are written -- path count, distance,
+// appended to meet -- exactly as the full level would write them; every
+// other vertex of that level is left untouched.  If M comes out empty
+// nothing was written and the full level runs.  Almost all of a sample's
+// reached vertices sit in its last level (Chung-Lu 4M: 95%, against about
+// 30 in M), so that level costs reads only.  The full level's overflow
+// check is kept by running this only while the deepest level's counts sum
+// below 2^64: on a simple graph no count of the next level can then reach
+// it.
+template <int BLOCK, class Recs>
+__device__ void pair_probe(const Params &p, Tile<BLOCK> &sm, const Recs &R, int X, const Scr &s, const GView &g,
+                           int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm, int32_t lcap,
+                           int32_t *full, Counters &c) {
+    const int tid = threadIdx.x;
+    for (int32_t tb = f0; tb < f1; tb += BLOCK) {
+        const int32_t cnt = min(BLOCK, f1 - tb);
+        if (tid < cnt) sm.val.u[tid] = R.listed(s, tb + tid)->sig[X];
+        const int32_t total =
+            Recs::kHashed ? stage_list<BLOCK>(sm, s, tb, cnt) : stage_ids<BLOCK>(sm, s.lv, g, tb, cnt);
+        __syncthreads();
+        if (tid == 0) c.arcs_fwd += (unsigned long long)total;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
+            int32_t kk[kChunk], w[kChunk];
+            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
+            bool hit[kChunk];
+            unsigned long long add[kChunk], old[kChunk];
+            PairRec *e[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                e[j] = kk[j] >= 0 ? R.lookup(w[j], full) : nullptr;
+                const int4 q = e[j] ? *reinterpret_cast<const int4 *>(e[j]->d) : make_int4(-1, -1, 0, 0);
+                const int32_t dz = X == 0 ? q.x : q.y, dy = X == 0 ? q.y : q.x;
+                // reached by the other side, and by X not before this level
+                hit[j] = e[j] != nullptr && dy >= 0 && (dz < 0 || dz == dep + 1);
+                add[j] = hit[j] ? sm.val.u[kk[j]] : 0ULL;
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) old[j] = hit[j] ? atomicAdd(&e[j]->sig[X], add[j]) : 1ULL;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const bool fresh = hit[j] && old[j] == 0ULL;
+                if (hit[j]) {
+                    c.dag++;
+                    if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                }
+                if (fresh) e[j]->d[X] = dep + 1;
+                wave_append(fresh, w[j], meet, nm, lcap, &p.st->err);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Walk from `from` to the root `rootv` of search side X, all threads of
@@ -1568,6 +1650,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         bs.hi[tid] = 1;
         bs.depth[tid] = 0;
         bs.cost[tid] = dg;
+        bs.small[tid] = 1;
     }
     if (tid == 0) {
         bs.result = 0;
@@ -1582,6 +1665,23 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         const int X = bs.cost[0] <= bs.cost[1] ? 0 : 1;
         const Scr &sx = X == 0 ? sa : sb;
         const int32_t lo = bs.lo[X], hi = bs.hi[X], dep = bs.depth[X];
+        const bool probed = bs.small[X] != 0;
+        if (probed) {
+            // the meeting set first; a last level ends the search here
+            pair_probe<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm, lcap, &bs.full, c);
+            __syncthreads();
+            const bool deferred = Recs::kHashed && bs.full;
+            const bool met = bs.nm > 0;
+            __syncthreads();
+            if (deferred || met) {
+                if (tid == 0) {
+                    bs.result = deferred ? -4 : 1;
+                    c.td++;
+                }
+                __syncthreads();
+                break;
+            }
+        }
         // hashed records: a level that could take the table past half full
         // (each arc leaving the frontier may add a vertex) is not run
         if (Recs::kHashed && (long long)bs.hi[0] + bs.hi[1] + bs.cost[X] > (long long)(lcap >> 1)) {
@@ -1594,11 +1694,13 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         if (tid == 0) {
             sm.count = 0;
             bs.newcost = 0;
+            bs.tsum = 0;
+            bs.tover = 0;
             c.td++;
         }
         __syncthreads();
-        pair_level<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm,
-                          reinterpret_cast<unsigned long long *>(&bs.newcost), lcap, &bs.full, c);
+        pair_level<BLOCK>(p, sm, bs, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm,
+                          reinterpret_cast<unsigned long long *>(&bs.newcost), lcap, &bs.full, !probed, c);
         __syncthreads();
         const int32_t nnew = sm.count < lcap - hi ? sm.count : lcap - hi;
         if (tid == 0) {
@@ -1606,6 +1708,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             bs.hi[X] = hi + nnew;
             bs.depth[X] = dep + 1;
             bs.cost[X] = bs.newcost;
+            bs.small[X] = bs.tover ? 0 : 1;
             // hashed records: a full table, or one past half full (long
             // probes), leaves the sample to the one-record-per-vertex launch
             if (Recs::kHashed && (bs.full || bs.hi[0] + bs.hi[1] > (lcap >> 1)))
