@@ -1381,6 +1381,26 @@ struct HashRecs {
     }
 };
 
+// Per-side filters in LDS: one bit per hashed vertex id for every vertex a
+// search side has listed (2^kPairFilterLog2 bits a side).  A clear bit
+// means the side has not reached the vertex, so its record need not be
+// read; a set bit may be a collision.  Vertices written by a probe that
+// ends the search are not added (nothing tests them afterwards: every
+// later test looks for levels below the meeting level).
+constexpr int kPairFilterLog2 = 17;
+constexpr int kPairFilterWords = 1 << (kPairFilterLog2 - 5);
+__device__ __forceinline__ uint32_t filter_bit(int32_t v) {
+    return ((uint32_t)v * 0x85EBCA6Bu) >> (32 - kPairFilterLog2);
+}
+__device__ __forceinline__ void filter_add(uint32_t *f, int32_t v) {
+    const uint32_t b = filter_bit(v);
+    atomicOr(&f[b >> 5], 1u << (b & 31));
+}
+__device__ __forceinline__ bool filter_has(const uint32_t *f, int32_t v) {
+    const uint32_t b = filter_bit(v);
+    return (f[b >> 5] >> (b & 31)) & 1u;
+}
+
 // Top-down growth of side X by one level (list[f0, f1) at distance dep)
 // into list[f1, ...): every arc y -> z with z not reached by X before this
 // level adds sigma_X(y) to sigma_X(z).  The first adder appends z with its
@@ -1394,7 +1414,8 @@ struct HashRecs {
 template <int BLOCK, class Recs>
 __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Recs &R, int X, const Scr &s,
                            const GView &g, int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm,
-                           unsigned long long *newcost, int32_t lcap, int32_t *full, bool count_arcs, Counters &c) {
+                           unsigned long long *newcost, int32_t lcap, int32_t *full, bool count_arcs,
+                           uint32_t *filt, Counters &c) {
     const int tid = threadIdx.x;
     unsigned long long dsum = 0;
     // sum of the path counts the level adds (= of its vertices' counts)
@@ -1442,6 +1463,7 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, BiState &bs, const 
                 }
                 if (fresh) {
                     e[j]->d[X] = dep + 1;
+                    filter_add(filt, w[j]);
                     if (Recs::kHashed) {
                         a0 = g.rp[w[j]];
                         dg = g.rp[w[j] + 1] - a0;
@@ -1476,17 +1498,19 @@ __device__ void pair_level(const Params &p, Tile<BLOCK> &sm, BiState &bs, const 
 // when the next level may be the last: only vertices the other side has
 // already reached (the meeting set M) are written -- path count, distance,
 // appended to meet -- exactly as the full level would write them; every
-// other vertex of that level is left untouched.  If M comes out empty
-// nothing was written and the full level runs.  Almost all of a sample's
-// reached vertices sit in its last level (Chung-Lu 4M: 95%, against about
-// 30 in M), so that level costs reads only.  The full level's overflow
+// other vertex of that level is left untouched, and only targets the other
+// side's filter lets through have their records read.  If M comes out
+// empty nothing was written and the full level runs.  Almost all of a
+// sample's reached vertices sit in its last level (Chung-Lu 4M: 95%,
+// against about 30 in M), so that level costs little beyond its column
+// indices.  The full level's overflow
 // check is kept by running this only while the deepest level's counts sum
 // below 2^64: on a simple graph no count of the next level can then reach
 // it.
 template <int BLOCK, class Recs>
 __device__ void pair_probe(const Params &p, Tile<BLOCK> &sm, const Recs &R, int X, const Scr &s, const GView &g,
                            int32_t f0, int32_t f1, int32_t dep, int32_t *meet, int32_t *nm, int32_t lcap,
-                           int32_t *full, Counters &c) {
+                           int32_t *full, const uint32_t *other, Counters &c) {
     const int tid = threadIdx.x;
     for (int32_t tb = f0; tb < f1; tb += BLOCK) {
         const int32_t cnt = min(BLOCK, f1 - tb);
@@ -1503,7 +1527,8 @@ __device__ void pair_probe(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
             PairRec *e[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; ++j) {
-                e[j] = kk[j] >= 0 ? R.lookup(w[j], full) : nullptr;
+                // only vertices the other side may have reached are looked up
+                e[j] = kk[j] >= 0 && filter_has(other, w[j]) ? R.lookup(w[j], full) : nullptr;
                 const int4 q = e[j] ? *reinterpret_cast<const int4 *>(e[j]->d) : make_int4(-1, -1, 0, 0);
                 const int32_t dz = X == 0 ? q.x : q.y, dy = X == 0 ? q.y : q.x;
                 // reached by the other side, and by X not before this level
@@ -1541,8 +1566,8 @@ __device__ void pair_probe(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
 constexpr int kWalkArcs = 4;
 
 template <int BLOCK, class Recs, typename Emit>
-__device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, const GView &g, int32_t from,
-                           int32_t rootv, unsigned long long stream, long long j, Emit emit) {
+__device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, const uint32_t *filt, const GView &g,
+                           int32_t from, int32_t rootv, unsigned long long stream, long long j, Emit emit) {
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = lane_id(), wid = wave_id();
     int32_t x = from;
@@ -1568,7 +1593,8 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
 #pragma unroll
             for (int q = 0; q < kWalkArcs; ++q) {
                 sp[q] = 0ULL;
-                if (pp[q] >= 0) {
+                // a predecessor is listed on side X: its filter bit is set
+                if (pp[q] >= 0 && filter_has(filt, pp[q])) {
                     const PairRec *ep = R.find(pp[q]);
                     if (ep && ep->d[X] == dx - 1) sp[q] = ep->sig[X];
                 }
@@ -1629,11 +1655,13 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
 // from v's side towards u.  The records of every listed vertex are reset at
 // the end, so the next sample starts from unreached records.
 template <int BLOCK, class Recs>
-__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Recs &R, const Scr &sa,
-                             const Scr &sb, const GView &g, int32_t u, int32_t v, long long j, long long task,
-                             int32_t lcap, Counters &c) {
+__device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, const Recs &R, uint32_t *filt,
+                             const Scr &sa, const Scr &sb, const GView &g, int32_t u, int32_t v, long long j,
+                             long long task, int32_t lcap, Counters &c) {
     const int tid = threadIdx.x;
     if (tid == 0) bs.full = 0;
+    for (int i = tid; i < 2 * kPairFilterWords; i += BLOCK) filt[i] = 0u;
+    __syncthreads();
     if (tid < 2) {
         // (one thread claims each root: u != v, and an empty table has room)
         const Scr &x = tid == 0 ? sa : sb;
@@ -1651,6 +1679,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         bs.depth[tid] = 0;
         bs.cost[tid] = dg;
         bs.small[tid] = 1;
+        filter_add(filt + tid * kPairFilterWords, r);
     }
     if (tid == 0) {
         bs.result = 0;
@@ -1668,7 +1697,8 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         const bool probed = bs.small[X] != 0;
         if (probed) {
             // the meeting set first; a last level ends the search here
-            pair_probe<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm, lcap, &bs.full, c);
+            pair_probe<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm, lcap, &bs.full,
+                              filt + (1 - X) * kPairFilterWords, c);
             __syncthreads();
             const bool deferred = Recs::kHashed && bs.full;
             const bool met = bs.nm > 0;
@@ -1700,7 +1730,8 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         }
         __syncthreads();
         pair_level<BLOCK>(p, sm, bs, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm,
-                          reinterpret_cast<unsigned long long *>(&bs.newcost), lcap, &bs.full, !probed, c);
+                          reinterpret_cast<unsigned long long *>(&bs.newcost), lcap, &bs.full, !probed,
+                          filt + X * kPairFilterWords, c);
         __syncthreads();
         const int32_t nnew = sm.count < lcap - hi ? sm.count : lcap - hi;
         if (tid == 0) {
@@ -1816,12 +1847,13 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             if (p.p_path && pos < p.maxlen) p.p_path[task * p.maxlen + pos] = p.inv ? p.inv[vtx] : vtx;
         };
         // side B: steps 1 .. kb-1 are interior, listed from v's side
-        bool ok = walk_block<BLOCK>(p, bs, R, 1, g, z, v, 5, j, [&](int32_t i, int32_t vtx) {
-            if (i < kb) put(kb - 1 - i, vtx);
-        });
+        bool ok = walk_block<BLOCK>(p, bs, R, 1, filt + kPairFilterWords, g, z, v, 5, j,
+                                    [&](int32_t i, int32_t vtx) {
+                                        if (i < kb) put(kb - 1 - i, vtx);
+                                    });
         if (tid == 0 && zc) put(nb, z);
         if (ok)
-            ok = walk_block<BLOCK>(p, bs, R, 0, g, z, u, 3, j, [&](int32_t i, int32_t vtx) {
+            ok = walk_block<BLOCK>(p, bs, R, 0, filt, g, z, u, 3, j, [&](int32_t i, int32_t vtx) {
                 if (i < ha) put(nb + zc + i - 1, vtx);
             });
         if (!ok && tid == 0) atomicOr(&p.st->err, kErrInternal);
@@ -1913,8 +1945,11 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
     const long long t_kernel = clock64();
     int32_t ep = 0;                                   // weighted mode: round counter
     __shared__ unsigned long long wsd[MODE == kModeWeighted ? BLOCK : 1];   // distances of staged vertices
+    // pair modes: the two search sides' filters
+    __shared__ uint32_t pfilt[MODE == kModePair || MODE == kModePairHash ? 2 * kPairFilterWords : 1];
     (void)ep;
     (void)wsd;
+    (void)pfilt;
     for (;;) {
         if (tid == 0) sm.task = (long long)atomicAdd(&p.st->head, 1ULL);
         __syncthreads();
@@ -1987,10 +2022,10 @@ __global__ __launch_bounds__(BLOCK) void k_brandes(Params p) {
             const Counters c0 = c;
             if constexpr (MODE == kModePairHash) {
                 const HashRecs hr{rec, (1u << p.ph_log2) - 1u, 32 - p.ph_log2};
-                bidir_sample<BLOCK>(p, sm, bs, hr, s, s2, g, src, target, j, tt,
+                bidir_sample<BLOCK>(p, sm, bs, hr, pfilt, s, s2, g, src, target, j, tt,
                                     (int32_t)min<long long>(p.stride, g.n), c);
             } else {
-                bidir_sample<BLOCK>(p, sm, bs, DirectRecs{rec}, s, s2, g, src, target, j, tt, g.n, c);
+                bidir_sample<BLOCK>(p, sm, bs, DirectRecs{rec}, pfilt, s, s2, g, src, target, j, tt, g.n, c);
             }
             if (bs.result == -4) c = c0;
             if (tid == 0) {
