@@ -1388,6 +1388,7 @@ struct HashRecs {
 // ends the search are not added (nothing tests them afterwards: every
 // later test looks for levels below the meeting level).
 constexpr int kPairFilterLog2 = 17;
+constexpr int kProbeChunks = 4;
 constexpr int kPairFilterWords = 1 << (kPairFilterLog2 - 5);
 __device__ __forceinline__ uint32_t filter_bit(int32_t v) {
     return ((uint32_t)v * 0x85EBCA6Bu) >> (32 - kPairFilterLog2);
@@ -1519,33 +1520,44 @@ __device__ void pair_probe(const Params &p, Tile<BLOCK> &sm, const Recs &R, int 
             Recs::kHashed ? stage_list<BLOCK>(sm, s, tb, cnt) : stage_ids<BLOCK>(sm, s.lv, g, tb, cnt);
         __syncthreads();
         if (tid == 0) c.arcs_fwd += (unsigned long long)total;
-        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk) {
-            int32_t kk[kChunk], w[kChunk];
-            load_chunk<BLOCK>(sm, g, cnt, total, rb + tid * kChunk, kk, w);
-            bool hit[kChunk];
-            unsigned long long add[kChunk], old[kChunk];
-            PairRec *e[kChunk];
+        // most arcs end at a clear filter bit: U chunks of column indices
+        // are loaded at once, then each chunk is settled (hash tables: one,
+        // their probe loops need the registers)
+        constexpr int U = Recs::kHashed ? 1 : kProbeChunks;
+        for (int32_t rb = 0; rb < total; rb += BLOCK * kChunk * U) {
+            int32_t kkq[U][kChunk], wq[U][kChunk];
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                // only vertices the other side may have reached are looked up
-                e[j] = kk[j] >= 0 && filter_has(other, w[j]) ? R.lookup(w[j], full) : nullptr;
-                const int4 q = e[j] ? *reinterpret_cast<const int4 *>(e[j]->d) : make_int4(-1, -1, 0, 0);
-                const int32_t dz = X == 0 ? q.x : q.y, dy = X == 0 ? q.y : q.x;
-                // reached by the other side, and by X not before this level
-                hit[j] = e[j] != nullptr && dy >= 0 && (dz < 0 || dz == dep + 1);
-                add[j] = hit[j] ? sm.val.u[kk[j]] : 0ULL;
-            }
+            for (int u = 0; u < U; ++u)
+                load_chunk<BLOCK>(sm, g, cnt, total, rb + (u * BLOCK + tid) * kChunk, kkq[u], wq[u]);
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) old[j] = hit[j] ? atomicAdd(&e[j]->sig[X], add[j]) : 1ULL;
+            for (int u = 0; u < U; ++u) {
+                const int32_t(&kk)[kChunk] = kkq[u];
+                const int32_t(&w)[kChunk] = wq[u];
+                bool hit[kChunk];
+                unsigned long long add[kChunk], old[kChunk];
+                PairRec *e[kChunk];
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const bool fresh = hit[j] && old[j] == 0ULL;
-                if (hit[j]) {
-                    c.dag++;
-                    if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                for (int j = 0; j < kChunk; ++j) {
+                    // only vertices the other side may have reached are looked up
+                    e[j] = kk[j] >= 0 && filter_has(other, w[j]) ? R.lookup(w[j], full) : nullptr;
+                    const int4 q = e[j] ? *reinterpret_cast<const int4 *>(e[j]->d) : make_int4(-1, -1, 0, 0);
+                    const int32_t dz = X == 0 ? q.x : q.y, dy = X == 0 ? q.y : q.x;
+                    // reached by the other side, and by X not before this level
+                    hit[j] = e[j] != nullptr && dy >= 0 && (dz < 0 || dz == dep + 1);
+                    add[j] = hit[j] ? sm.val.u[kk[j]] : 0ULL;
                 }
-                if (fresh) e[j]->d[X] = dep + 1;
-                wave_append(fresh, w[j], meet, nm, lcap, &p.st->err);
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) old[j] = hit[j] ? atomicAdd(&e[j]->sig[X], add[j]) : 1ULL;
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    const bool fresh = hit[j] && old[j] == 0ULL;
+                    if (hit[j]) {
+                        c.dag++;
+                        if (old[j] + add[j] < old[j]) atomicOr(&p.st->err, kErrOverflow);
+                    }
+                    if (fresh) e[j]->d[X] = dep + 1;
+                    wave_append(fresh, w[j], meet, nm, lcap, &p.st->err);
+                }
             }
         }
         __syncthreads();
@@ -1572,6 +1584,8 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
     const int tid = threadIdx.x, lane = lane_id(), wid = wave_id();
     int32_t x = from;
     for (unsigned long long tt = 0;; ++tt) {
+        // x's arc range is read together with its record
+        const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         const PairRec *ex = R.find(x);
         if (!ex) return false;
         const int32_t dx = ex->d[X];
@@ -1581,7 +1595,6 @@ __device__ bool walk_block(const Params &p, BiState &bs, const Recs &R, int X, c
             return true;
         }
         const unsigned long long r = bounded(draw(p.seed, stream, (unsigned long long)j, tt), ex->sig[X]);
-        const int32_t a0 = g.rp[x], a1 = g.rp[x + 1];
         unsigned long long carry = 0ULL;
         int32_t pick = -1;
         for (int32_t base = a0; base < a1; base += BLOCK * kWalkArcs) {
@@ -1774,6 +1787,12 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             const int32_t oid = p.inv ? p.inv[z] : z;
             idlo = min(idlo, oid);
             idhi = max(idhi, oid);
+            // one entry per thread when M fits the block: ids and weights in
+            // the tile (its arrays are free once the search has ended)
+            if (nm <= BLOCK) {
+                sm.v[tid] = oid;
+                sm.val.u[tid] = w;
+            }
         }
         if (wrap) {
             atomicOr(&p.st->err, kErrOverflow);
@@ -1804,6 +1823,24 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             }
         } else {
             const unsigned long long r0 = bounded(draw(p.seed, 4, (unsigned long long)j, 0), tlo);
+            if (nm <= BLOCK) {
+                // the z whose weights of smaller ids sum to at most r0 and,
+                // with its own weight, above it (ids are distinct and the
+                // total is below 2^64): one thread finds itself.  Weights of
+                // zero (counts that wrapped, already reported as overflow)
+                // can leave no such z; then z is the largest id, as the
+                // threshold search would end, so that z is always a vertex.
+                if (tid < nm && sm.v[tid] == thi_id) bs.z = sa.cand[tid];
+                __syncthreads();
+                if (tid < nm) {
+                    const int32_t me = sm.v[tid];
+                    unsigned long long below = 0ULL;
+                    for (int32_t k = 0; k < nm; ++k)
+                        if (sm.v[k] < me) below += sm.val.u[k];
+                    if (below <= r0 && r0 - below < mine) bs.z = sa.cand[tid];
+                }
+                tlo_id = thi_id;   // the threshold search below has nothing to do
+            }
             // smallest original-id threshold T with sum of weights of ids <= T above r0
             while (tlo_id < thi_id) {
                 const int32_t mid = tlo_id + ((thi_id - tlo_id) >> 1);
@@ -1820,7 +1857,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
                 else
                     tlo_id = mid + 1;
             }
-            for (int32_t i = tid; i < nm; i += BLOCK) {
+            for (int32_t i = tid; i < nm && nm > BLOCK; i += BLOCK) {
                 const int32_t z = sa.cand[i];
                 if ((p.inv ? p.inv[z] : z) == tlo_id) bs.z = z;
             }
