@@ -239,7 +239,9 @@ def pair_record(args) -> dict:
     n = 4e6: samples/s over `steps` calls, and the pair kernel's roofline.
     Algorithmic bytes of a sample's bidirectional search: 16 per scanned arc
     (its column index and the head's distance and path count) and 36 per
-    reached vertex (its list entry, its record written and reset)."""
+    listed vertex (its list entry, its record written and reset).  A search's
+    last level is probed: its vertices are read, not listed, except the
+    meeting vertices, which the other side has listed already."""
     import numpy as np
     import torch
 
