@@ -79,7 +79,8 @@ def counter_traffic(workload: str, kernel: str = KERNEL):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", text)
-    m_bytes = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", text)
+    # (a summary of a one-launch-per-call kernel says "per call")
+    m_bytes = re.search(r"HBM bytes per (?:launch|call) \(calibrated\):\s*([0-9.eE+]+)", text)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(kernel):
         return None
     return float(m_bytes.group(1))
@@ -271,7 +272,7 @@ def pair_record(args) -> dict:
            "warmup": 1, "ms_per_step": round(sec * 1e3, 2), "n": g.n, "arcs": g.m, "r": r, "vd_bound": vd,
            "r_times_edges_gteps": round(r * g.m_undirected / sec / 1e9, 3), "kernel_ms": round(kern_s * 1e3, 2),
            "arcs_scanned": st["arcs_fwd"], "reached": st["reached"],
-           "roofline": roofline(byts, kern_s, "k_brandes (pair mode)")}
+           "roofline": roofline(byts, kern_s, "k_brandes (pair mode)", counter_traffic("pair_chunglu4m"))}
     if not args.no_cpu_baseline:
         threads = cpu_threads()
         ns = 400 * threads
