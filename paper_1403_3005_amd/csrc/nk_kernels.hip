@@ -1267,6 +1267,7 @@ struct BiState {
     int32_t pickw, pickv;            // block walk: first crossing wave, chosen vertex
     int32_t full;                    // hashed records: a claim found the table full
     int32_t small[2];                // the path counts of each side's deepest level sum below 2^64
+    long long dsum[2];               // arcs of all the vertices each side has listed
     int32_t tover;                   // the level being built: its path counts' sum reached 2^64
     unsigned long long tsum;         // ... and that sum modulo 2^64
     unsigned long long part_lo[16], part_hi[16];
@@ -1389,6 +1390,11 @@ struct HashRecs {
 // later test looks for levels below the meeting level).
 constexpr int kPairFilterLog2 = 17;
 constexpr int kProbeChunks = 4;
+// A level is probed first when at least this many of its arcs are expected
+// to meet the other side (Chung-Lu 4M, 300 samples on the CPU: 87% of the
+// levels that do not end the search go unprobed, 3 of 300 last levels run
+// in full).
+constexpr double kProbeMeets = 0.05;
 constexpr int kPairFilterWords = 1 << (kPairFilterLog2 - 5);
 __device__ __forceinline__ uint32_t filter_bit(int32_t v) {
     return ((uint32_t)v * 0x85EBCA6Bu) >> (32 - kPairFilterLog2);
@@ -1691,6 +1697,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         bs.hi[tid] = 1;
         bs.depth[tid] = 0;
         bs.cost[tid] = dg;
+        bs.dsum[tid] = dg;
         bs.small[tid] = 1;
         filter_add(filt + tid * kPairFilterWords, r);
     }
@@ -1707,7 +1714,11 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
         const int X = bs.cost[0] <= bs.cost[1] ? 0 : 1;
         const Scr &sx = X == 0 ? sa : sb;
         const int32_t lo = bs.lo[X], hi = bs.hi[X], dep = bs.depth[X];
-        const bool probed = bs.small[X] != 0;
+        // probe when the level may well be the last: the arcs leaving X's
+        // frontier times the share of all arcs that belong to vertices the
+        // other side has listed is the expected number of arcs that meet
+        const bool probed = bs.small[X] != 0 &&
+                            (double)bs.cost[X] * (double)bs.dsum[1 - X] >= kProbeMeets * (double)g.m;
         if (probed) {
             // the meeting set first; a last level ends the search here
             pair_probe<BLOCK>(p, sm, R, X, sx, g, lo, hi, dep, sa.cand, &bs.nm, lcap, &bs.full,
@@ -1752,6 +1763,7 @@ __device__ void bidir_sample(const Params &p, Tile<BLOCK> &sm, BiState &bs, cons
             bs.hi[X] = hi + nnew;
             bs.depth[X] = dep + 1;
             bs.cost[X] = bs.newcost;
+            bs.dsum[X] += bs.newcost;
             bs.small[X] = bs.tover ? 0 : 1;
             // hashed records: a full table, or one past half full (long
             // probes), leaves the sample to the one-record-per-vertex launch
