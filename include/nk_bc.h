@@ -417,6 +417,9 @@ nk_status nk_batch_plan_finish(nk_batch_plan *plan, void *stream);
  *   out[14] pair samples that could outgrow their slot's hashed records
  *           and ran again with one record per vertex (flags bit 6)
  *   out[15] reserved
+ *   (pair sampling: out[1] counts the vertices the searches listed; a
+ *   search's probed last level is read, and only its meeting vertices,
+ *   which the other side listed, are written)
  *   (nk_bc_weighted: out[2] arcs relaxed in the distance rounds, out[5]
  *   distance rounds, out[6] shortest-path DAG layers, out[4] DAG arcs)
  *   out[16..23] shader-clock cycles per phase, summed over workgroups:
