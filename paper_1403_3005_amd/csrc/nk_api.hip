@@ -793,7 +793,7 @@ nk_status launch_persistent(const LaunchPlan &plan, Params &p, Scratch &scr, hip
 // it, the largest component it missed, and a second sweep from the lowest
 // far vertex (info layout as nk_vd_bound).
 nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
-                        hipStream_t s) {
+                        hipStream_t s, bool lower) {
     for (int i = 0; i < 8; ++i) info[i] = 0;
     if (n == 0) return NK_OK;
     Scratch scr;
@@ -827,9 +827,12 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     int32_t c2 = 0;
     if (c0 < n)
         if ((st = largest_unreached_component(rowptr, colidx, n, w.d, label, size, flag, s, &c2)) != NK_OK) return st;
-    // second sweep from a
-    if ((st = grid_bfs(rowptr, colidx, n, m, a, w, s, r2)) != NK_OK) return st;
-    const int32_t e2 = r2[0];
+    // second sweep from a (the lower bound only)
+    int32_t e2 = -1;
+    if (lower) {
+        if ((st = grid_bfs(rowptr, colidx, n, m, a, w, s, r2)) != NK_OK) return st;
+        e2 = r2[0];
+    }
     int32_t ub = 2 * e1 + 1;
     if (ub > c0) ub = c0;
     if (c2 > ub) ub = c2;
@@ -1617,7 +1620,8 @@ nk_status nk_bc_pair_sample(const int32_t *rowptr, const int32_t *colidx, int32_
     if (!bc) return fail(NK_E_INVALID_ARG, "bc is NULL");
     hipStream_t s = (hipStream_t)stream;
     int32_t info[8];
-    if ((st = vd_bound_impl(rowptr, colidx, n, m, info, s)) != NK_OK) return st;
+    // the sample size needs the upper bound only
+    if ((st = vd_bound_impl(rowptr, colidx, n, m, info, s, false)) != NK_OK) return st;
     const long long r = n >= 2 ? nk_rk_sample_size(eps, delta, info[4]) : 0;
     if (r_out) *r_out = r;
     if (vd_out) *vd_out = info[4];

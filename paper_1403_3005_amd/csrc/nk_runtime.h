@@ -251,7 +251,9 @@ hipError_t launch_gather_scale(const double *in, const int32_t *perm, int32_t n,
 hipError_t launch_gather_u32(const uint32_t *in, const int32_t *perm, int32_t n, uint32_t *out, hipStream_t s);
 
 // Vertex-diameter bound (see nk_vd_bound); runs synchronously on `s`.
+// lower = false skips the second sweep, which gives only the lower bound
+// (info[3] is then -1 and info[5] 0): the upper bound info[4] is the same.
 nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t *info,
-                        hipStream_t s);
+                        hipStream_t s, bool lower = true);
 
 }  // namespace nk
