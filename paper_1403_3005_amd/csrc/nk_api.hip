@@ -814,14 +814,15 @@ nk_status vd_bound_impl(const int32_t *rowptr, const int32_t *colidx, int32_t n,
     NK_HIP(launch_validate(rowptr, colidx, n, m, 0, dst, s));
     NK_HIP(launch_fill_u64(key, 0ULL, 1, s));
     NK_HIP(launch_argmax_degree(rowptr, n, key, s));
-    if ((st = finish(dst, h, s)) != NK_OK) return st;
+    // (the status read synchronises the stream, so the key has arrived too)
     unsigned long long k = 0;
     NK_HIP(hipMemcpyAsync(&k, key, 8, hipMemcpyDeviceToHost, s));
-    NK_HIP(hipStreamSynchronize(s));
+    if ((st = finish(dst, h, s)) != NK_OK) return st;
     const int32_t x0 = (int32_t)(0xffffffffULL - (k & 0xffffffffULL));
-    // first sweep from x0: e1, the lowest far vertex a, and |C(x0)|
+    // first sweep from x0 (its degree is the key's high word): e1, the
+    // lowest far vertex a (for the second sweep only), and |C(x0)|
     int32_t r1[3], r2[3];
-    if ((st = grid_bfs(rowptr, colidx, n, m, x0, w, s, r1)) != NK_OK) return st;
+    if ((st = grid_bfs(rowptr, colidx, n, m, x0, w, s, r1, (int32_t)(k >> 32), lower)) != NK_OK) return st;
     const int32_t e1 = r1[0], a = r1[1], c0 = r1[2];
     // largest component among the vertices the first sweep did not reach
     int32_t c2 = 0;

@@ -347,15 +347,14 @@ nk_status bfs_work_get(Scratch &scr, int32_t n, hipStream_t s, BfsWork *w) {
 }
 
 nk_status grid_bfs(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t src,
-                   const BfsWork &w, hipStream_t s, int32_t out[3]) {
+                   const BfsWork &w, hipStream_t s, int32_t out[3], int32_t src_deg, bool want_lowest) {
     int32_t *d = w.d;
     int32_t *low = reinterpret_cast<int32_t *>(w.cnt + 8);
     hipLaunchKernelGGL(k_gbfs_init, dim3(grid_of(n, 256)), dim3(256), 0, s, d, n, src, w.f0, w.cnt);
     NK_HIP(hipGetLastError());
     int32_t nf = 1, level = 0, reached = 1;
     int32_t *front = w.f0, *next = w.f1;
-    int32_t src_deg = 0;
-    {
+    if (src_deg < 0) {
         int32_t rp2[2];
         NK_HIP(hipMemcpyAsync(rp2, rowptr + src, 8, hipMemcpyDeviceToHost, s));
         NK_HIP(hipStreamSynchronize(s));
@@ -410,6 +409,10 @@ nk_status grid_bfs(const int32_t *rowptr, const int32_t *colidx, int32_t n, int6
         ++level;
     }
     if (h.newc > n) return fail(NK_E_INTERNAL, "breadth-first search overran its frontier");
+    out[0] = level;
+    out[1] = -1;
+    out[2] = reached;
+    if (!want_lowest) return NK_OK;
     // lowest id on the deepest level (front[0, nf))
     NK_HIP(launch_fill_i32(low, 0x7fffffff, 1, s));
     hipLaunchKernelGGL(k_min_i32, dim3(grid_of(nf, 256)), dim3(256), 0, s, front, nf, low);

@@ -183,9 +183,11 @@ struct BfsWork {
 };
 nk_status bfs_work_get(Scratch &scr, int32_t n, hipStream_t s, BfsWork *w);
 // Distances from src into w.d; out = {eccentricity of src, lowest id at
-// that distance, vertices reached}.  Synchronises s.
+// that distance (-1 unless want_lowest), vertices reached}.  src_deg: the
+// source's degree if the caller knows it (else -1: read from rowptr).
+// Synchronises s.
 nk_status grid_bfs(const int32_t *rowptr, const int32_t *colidx, int32_t n, int64_t m, int32_t src,
-                   const BfsWork &w, hipStream_t s, int32_t out[3]);
+                   const BfsWork &w, hipStream_t s, int32_t out[3], int32_t src_deg = -1, bool want_lowest = true);
 // Size of the largest connected component among the vertices with
 // skip[v] < 0 (label, size: n ints of scratch; flag: one int).
 nk_status largest_unreached_component(const int32_t *rowptr, const int32_t *colidx, int32_t n, const int32_t *skip,
