@@ -1480,15 +1480,12 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
                           int32_t *path, int32_t maxlen, DevStatus *dst, Scratch &scr, hipStream_t s,
                           LaunchPlan *plan_out, hipEvent_t ev0, hipEvent_t ev1) {
     nk_status st;
-    uint32_t *iso;
-    const long long words = ((long long)n + 31) / 32;
-    if ((st = scr.get(words, &iso)) != NK_OK) return st;
     // The graph runs under the caller's ids: a pair sample touches a few
     // thousand vertices, and degree relabelling (a pass over every arc per
     // call) left the pair kernel's time unchanged on Chung-Lu, R-MAT and
-    // Erdos-Renyi graphs.
+    // Erdos-Renyi graphs.  (A sample checks its endpoints' degrees itself,
+    // so no isolated-vertex bitmap is built.)
     const Relabeled g = {rowptr, colidx, nullptr, nullptr};
-    NK_HIP(launch_iso_bitmap(g.rowptr, n, iso, s));
     uint32_t *cnt = counts;
     if (counts && g.perm) {
         if ((st = scr.get(n, &cnt)) != NK_OK) return st;
@@ -1533,7 +1530,6 @@ static nk_status pair_run(const int32_t *rowptr, const int32_t *colidx, int32_t 
     p.maxlen = maxlen;
     p.perm = g.perm;
     p.inv = g.inv;
-    p.iso = iso;
     p.st = dst;
     unsigned long long *dcount = nullptr;
     if (hashed) {
